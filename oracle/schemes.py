@@ -1,0 +1,114 @@
+"""Splitting steps and monitors built on the mu-mode integrator (oracle).
+
+Pins (tests/test_oracle_schemes.py):
+  gpe_strang     -- beta = 0 reduces to the plain integrator with E(tau);
+                    the nonlinear subflow against its closed form (|psi|
+                    constant, phase -s beta |psi|^2); mass conservation
+                    (Section 2, advantages list); second order in tau (error
+                    ratio ~4 when tau halves, self-convergence).
+  ho_strang      -- eps = 0: a product of Hermite functions sampled at the
+                    nodes acquires exactly exp(-i tau lambda_i) per step,
+                    lambda_i = sum (1/2 + i_mu) (Section 3); unitarity;
+                    second order in tau for eps != 0.
+  merged loops   -- gpe_strang_merged equals gpe_strang (phase flows of the
+                    nonlinear part compose: N(a) N(b) = N(a + b) because N
+                    keeps |psi|).
+  monitors       -- mass of a normalised state is 1; energy of a 1-D HO
+                    eigenvector of the FD Hamiltonian equals its eigenvalue.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from .mumode import mode_product, tucker
+
+
+# ------------------------------------------------- Gross-Pitaevskii --------
+
+def gpe_nonlinear(psi: np.ndarray, s: float, beta: float) -> np.ndarray:
+    """Exact flow over time s of i psi_t = beta |psi|^2 psi:
+    psi <- exp(-i s beta |psi|^2) psi (|psi| is constant along it)."""
+    return np.exp(-1j * s * beta * np.abs(psi) ** 2) * psi
+
+
+def gpe_strang(psi: np.ndarray, E, tau: float, beta: float, nsteps: int = 1) -> np.ndarray:
+    """Strang splitting N(tau/2) L(tau) N(tau/2) per step, where L(tau) is the
+    mu-mode integrator with E_mu = exp(-i tau H_mu) and N the exact nonlinear
+    flow (Section 4.5: linear part by the integrator, nonlinear part exact)."""
+    for _ in range(nsteps):
+        psi = gpe_nonlinear(psi, 0.5 * tau, beta)
+        psi = tucker(psi, E)
+        psi = gpe_nonlinear(psi, 0.5 * tau, beta)
+    return psi
+
+
+def gpe_strang_merged(psi: np.ndarray, E, tau: float, beta: float, nsteps: int = 1) -> np.ndarray:
+    """Same scheme with adjacent half-steps of N merged:
+    N(tau/2) [L N(tau)]^(nsteps-1) L N(tau/2)."""
+    psi = gpe_nonlinear(psi, 0.5 * tau, beta)
+    for k in range(nsteps):
+        psi = tucker(psi, E)
+        psi = gpe_nonlinear(psi, tau if k < nsteps - 1 else 0.5 * tau, beta)
+    return psi
+
+
+# --------------------------------------- harmonic oscillator (Hermite) -----
+
+def ho_potential_flow(psi: np.ndarray, nodes, a: float, b: float, eps: float) -> np.ndarray:
+    """Exact flow from time a to b of i psi_t = (eps/2) sin(t) |x|^2 psi:
+    psi <- exp(-i (eps/2) |x|^2 (cos a - cos b)) psi (pointwise)."""
+    d = psi.ndim
+    r2 = np.zeros((1,) * d)
+    for mu in range(d):
+        shape = [1] * d
+        shape[mu] = len(nodes[mu])
+        r2 = r2 + (np.asarray(nodes[mu]) ** 2).reshape(shape)
+    return np.exp(-1j * 0.5 * eps * r2 * (np.cos(a) - np.cos(b))) * psi
+
+
+def ho_linear(psi: np.ndarray, Phi, Psi, tau: float) -> np.ndarray:
+    """Exact flow of i psi_t = -1/2 sum (d^2 - x^2) psi in Hermite space:
+    forward transform (equation real2spec), multiply coefficient i by
+    exp(-i tau lambda_i) with lambda_i = sum_mu (1/2 + i_mu) (Section 3),
+    backward transform (equation spec2real)."""
+    d = psi.ndim
+    c = tucker(psi, Phi)
+    lam = np.zeros((1,) * d)
+    for mu in range(d):
+        shape = [1] * d
+        shape[mu] = c.shape[mu]
+        lam = lam + (0.5 + np.arange(c.shape[mu], dtype=np.float64)).reshape(shape)
+    c = np.exp(-1j * tau * lam) * c
+    return tucker(c, Psi)
+
+
+def ho_strang(psi: np.ndarray, Phi, Psi, nodes, t0: float, tau: float, eps: float,
+              nsteps: int = 1) -> np.ndarray:
+    """Strang step for V(x,t) = |x|^2/2 (1 + eps sin t): the harmonic part is
+    exact in Hermite space, the time-dependent remainder is integrated
+    exactly over each half step:
+    P(t+tau/2, t+tau) L_H(tau) P(t, t+tau/2)."""
+    t = t0
+    for _ in range(nsteps):
+        psi = ho_potential_flow(psi, nodes, t, t + 0.5 * tau, eps)
+        psi = ho_linear(psi, Phi, Psi, tau)
+        psi = ho_potential_flow(psi, nodes, t + 0.5 * tau, t + tau, eps)
+        t = t + tau
+    return psi
+
+
+# ----------------------------------------------------------- monitors ------
+
+def norm2(psi: np.ndarray, cell: float) -> float:
+    """Discrete mass h^d sum |psi|^2 (conserved by unitary steps)."""
+    return float(cell * np.sum(np.abs(psi) ** 2))
+
+
+def energy_gpe(psi: np.ndarray, H, beta: float, cell: float) -> float:
+    """Discrete GPE energy h^d [Re sum conj(psi) (sum_mu psi x_mu H_mu)
+    + (beta/2) sum |psi|^4]."""
+    Hpsi = np.zeros_like(psi)
+    for mu, Hm in enumerate(H, start=1):
+        Hpsi = Hpsi + mode_product(psi, Hm, mu)
+    kin = np.real(np.vdot(psi.reshape(-1), Hpsi.reshape(-1)))
+    return float(cell * (kin + 0.5 * beta * np.sum(np.abs(psi) ** 4)))

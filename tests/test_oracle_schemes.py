@@ -1,0 +1,150 @@
+"""Pins of the oracle's splitting steps and monitors (CPU only)."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import mumode as om
+from oracle import operators as op
+from oracle import schemes as sc
+
+
+def _rel(a, b):
+    return np.linalg.norm((a - b).ravel()) / np.linalg.norm(b.ravel())
+
+
+def _gpe_setup(n=16, a=-8.0, b=8.0, tau=0.05, beta=100.0):
+    E = op.ho_exponential(n, a, b, tau)
+    psi = synth.thomas_fermi_initial(n, a, b, 3, beta, cfg_id=4)
+    return psi, [E, E, E]
+
+
+def test_gpe_beta_zero_reduces_to_integrator():
+    psi, E = _gpe_setup()
+    out = sc.gpe_strang(psi, E, 0.05, 0.0, 3)
+    assert _rel(out, om.expstep(psi, E, 3)) < 1e-14
+
+
+def test_gpe_nonlinear_flow_solves_its_ode():
+    g = synth.rng(201, 0)
+    psi = synth.random_tensor((5, 6, 7), True, g)
+    beta, s, ds = 100.0, 0.013, 1e-6
+    out = sc.gpe_nonlinear(psi, s, beta)
+    assert np.max(np.abs(np.abs(out) - np.abs(psi))) < 1e-14
+    # d/ds N(s) psi = -i beta |N(s) psi|^2 N(s) psi   (central difference in s)
+    dNds = (sc.gpe_nonlinear(psi, s + ds, beta) - sc.gpe_nonlinear(psi, s - ds, beta)) / (2 * ds)
+    rhs = -1j * beta * np.abs(out) ** 2 * out
+    assert _rel(dNds, rhs) < 1e-6
+    # flows compose: N(a) N(b) = N(a + b)
+    assert _rel(sc.gpe_nonlinear(sc.gpe_nonlinear(psi, 0.01, beta), 0.003, beta),
+                sc.gpe_nonlinear(psi, 0.013, beta)) < 1e-13
+
+
+def test_gpe_merged_equals_unmerged():
+    psi, E = _gpe_setup()
+    a = sc.gpe_strang(psi, E, 0.05, 100.0, 4)
+    b = sc.gpe_strang_merged(psi, E, 0.05, 100.0, 4)
+    assert _rel(b, a) < 1e-13
+
+
+def test_gpe_mass_conserved():
+    n, a, b = 16, -8.0, 8.0
+    psi, E = _gpe_setup(n, a, b)
+    h = (b - a) / (n + 1)
+    m0 = sc.norm2(psi, h ** 3)
+    m1 = sc.norm2(sc.gpe_strang(psi, E, 0.05, 100.0, 5), h ** 3)
+    assert abs(m0 - 1.0) < 1e-13 and abs(m1 - m0) < 1e-13
+
+
+def test_gpe_strang_second_order():
+    n, a, b, beta, T = 12, -6.0, 6.0, 100.0, 0.2
+    psi0 = synth.thomas_fermi_initial(n, a, b, 3, beta, cfg_id=4)
+
+    def run(k):
+        tau = T / k
+        E = op.ho_exponential(n, a, b, tau)
+        return sc.gpe_strang(psi0, [E, E, E], tau, beta, k)
+
+    ref = run(256)
+    e1 = np.linalg.norm((run(8) - ref).ravel())
+    e2 = np.linalg.norm((run(16) - ref).ravel())
+    e3 = np.linalg.norm((run(32) - ref).ravel())
+    assert 3.5 < e1 / e2 < 4.5 and 3.5 < e2 / e3 < 4.5
+
+
+# ------------------------------------------------ harmonic oscillator ------
+
+def _ho_mats(m):
+    return op.hermite_forward(m), op.hermite_backward(m), op.hermite_nodes(m)
+
+
+def test_ho_eigenstate_gets_exact_phase():
+    m, tau = 16, 0.37
+    Phi, Psi, X = _ho_mats(m)
+    f = op.hermite_functions(m, X)
+    k = (2, 0, 5)
+    psi = f[k[0]][:, None, None] * f[k[1]][None, :, None] * f[k[2]][None, None, :]
+    out = sc.ho_strang(psi, [Phi] * 3, [Psi] * 3, [X] * 3, 0.0, tau, 0.0, nsteps=3)
+    lam = sum(k) + 1.5
+    assert _rel(out, np.exp(-1j * 3 * tau * lam) * psi) < 1e-12
+
+
+def test_ho_unitary_in_discrete_inner_product():
+    m = 16
+    Phi, Psi, X = _ho_mats(m)
+    w = op.hermite_weights(m, X)
+    W = w[:, None, None] * w[None, :, None] * w[None, None, :]
+    c = synth.hermite_coefficients(m, 6, 3, cfg_id=3)
+    psi = om.tucker(c, [Psi] * 3)
+    out = sc.ho_strang(psi, [Phi] * 3, [Psi] * 3, [X] * 3, 0.3, 0.02, 0.1, nsteps=4)
+    n0 = np.sum(np.abs(psi) ** 2 * W)
+    n1 = np.sum(np.abs(out) ** 2 * W)
+    assert abs(n1 / n0 - 1.0) < 1e-12
+    # the weighted nodal norm equals the coefficient norm (discrete Parseval)
+    assert abs(n0 / np.sum(np.abs(c) ** 2) - 1.0) < 1e-12
+
+
+def test_ho_strang_second_order():
+    m, T, eps = 12, 1.0, 0.1
+    Phi, Psi, X = _ho_mats(m)
+    c = synth.hermite_coefficients(m, 5, 3, cfg_id=3)
+    psi0 = om.tucker(c, [Psi] * 3)
+
+    def run(k):
+        return sc.ho_strang(psi0, [Phi] * 3, [Psi] * 3, [X] * 3, 0.0, T / k, eps, nsteps=k)
+
+    ref = run(512)
+    e1 = np.linalg.norm((run(8) - ref).ravel())
+    e2 = np.linalg.norm((run(16) - ref).ravel())
+    assert 3.5 < e1 / e2 < 4.5
+
+
+def test_ho_potential_flow_composes():
+    g = synth.rng(202, 0)
+    X = [np.linspace(-3, 3, 4), np.linspace(-2, 2, 5), np.linspace(-1, 1, 3)]
+    psi = synth.random_tensor((4, 5, 3), True, g)
+    one = sc.ho_potential_flow(psi, X, 0.1, 0.9, 0.1)
+    two = sc.ho_potential_flow(sc.ho_potential_flow(psi, X, 0.1, 0.4, 0.1), X, 0.4, 0.9, 0.1)
+    assert _rel(two, one) < 1e-14
+    # solves i psi_t = (eps/2) sin(t) |x|^2 psi at t = b (difference in b)
+    db = 1e-6
+    d = (sc.ho_potential_flow(psi, X, 0.1, 0.9 + db, 0.1) - sc.ho_potential_flow(psi, X, 0.1, 0.9 - db, 0.1)) / (2 * db)
+    r2 = X[0][:, None, None] ** 2 + X[1][None, :, None] ** 2 + X[2][None, None, :] ** 2
+    assert _rel(1j * d, 0.05 * np.sin(0.9) * r2 * one) < 1e-6
+
+
+# ----------------------------------------------------------- monitors ------
+
+def test_energy_of_fd_eigenvectors():
+    n, a, b = 20, -5.0, 5.0
+    h = (b - a) / (n + 1)
+    H = op.ho_hamiltonian(n, a, b)
+    lam, V = np.linalg.eigh(H)
+    vs = [V[:, k] / np.sqrt(h) for k in (0, 1, 3)]        # h sum v^2 = 1
+    psi = vs[0][:, None, None] * vs[1][None, :, None] * vs[2][None, None, :]
+    assert abs(sc.norm2(psi, h ** 3) - 1.0) < 1e-13
+    e0 = sc.energy_gpe(psi, [H, H, H], 0.0, h ** 3)
+    assert abs(e0 - (lam[0] + lam[1] + lam[3])) < 1e-11
+    beta = 7.0
+    e1 = sc.energy_gpe(psi, [H, H, H], beta, h ** 3)
+    quartic = np.prod([np.sum(v ** 4) for v in vs]) * h ** 3
+    assert abs(e1 - e0 - 0.5 * beta * quartic) < 1e-11
