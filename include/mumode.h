@@ -1,0 +1,182 @@
+/*
+ * mumode.h -- C ABI of the MI355X (gfx950) mu-mode product library.
+ *
+ * The library applies small dense n_mu x n_mu (or m x n_mu) matrices along
+ * the modes of a d-dimensional tensor (the mu-mode product of Definition 2.1
+ * of Caliari, Cassini, Einkemmer, Ostermann, Zivcovich, "A mu-mode integrator
+ * for solving evolution equations in Kronecker form"), and builds on it the
+ * mu-mode integrator (Section 2, equation dd-tensor), tensor spectral
+ * transforms (Section 3, equations real2spec / spec2real) and Strang
+ * splitting steps whose linear part is the integrator (Sections 4.3-4.5).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Tensors are dense and column-major: entry (i_1, ..., i_d) sits at linear
+ *    index i_1 + n_1 (i_2 + n_2 (i_3 + ...)) (0-based; Section 4.1 gives the
+ *    1-based form).  Complex values are interleaved (re, im).  Tensor data
+ *    pointers are DEVICE pointers, 16-byte aligned.
+ *  - Matrices handed to mm_op_prepare are column-major FP64 masters
+ *    (L[i + j*ld]), real (MM_R64) or complex interleaved (MM_C128), in host
+ *    memory (on_device = 0) or device memory (on_device = 1).
+ *  - dtype <-> precision: an FP64-prepared operator acts on MM_R64 / MM_C128
+ *    tensors; every other precision acts on MM_R32 / MM_C64 tensors.  A real
+ *    operator may act on a complex tensor (applied to re and im); a complex
+ *    operator on a real tensor is MM_ERR_DTYPE.
+ *  - Ownership: the caller owns tensors, matrices and streams.  The context
+ *    owns operators (mm_op) and its device workspace; mm_destroy frees them.
+ *  - All tensor work is enqueued asynchronously on `stream` (0 = the null
+ *    stream); only the monitors (mm_norm2, mm_energy_gpe) synchronise.
+ *  - Every argument is validated before anything is launched.  No exception
+ *    crosses the ABI; failures return an mm_status, with detail text from
+ *    mm_last_error(ctx).  One context per host thread.
+ */
+#ifndef MUMODE_H
+#define MUMODE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  MM_OK = 0,
+  MM_ERR_ARG = 1,         /* null pointer, aliasing, bad enum, nsteps < 0     */
+  MM_ERR_SHAPE = 2,       /* d out of [1, MM_MAXD], dim <= 0, mu out of range,
+                             op cols != n_mu, non-square op where required,
+                             size above the supported maximum                 */
+  MM_ERR_DTYPE = 3,       /* tensor dtype does not match the op precision     */
+  MM_ERR_ALIGN = 4,       /* tensor data not 16-byte aligned                  */
+  MM_ERR_NOMEM = 5,       /* device allocation failed                         */
+  MM_ERR_HIP = 6,         /* a HIP runtime call failed (text in last_error)   */
+  MM_ERR_UNSUPPORTED = 7, /* valid request this build does not implement      */
+  MM_ERR_NONFINITE = 8,   /* a monitor found NaN / Inf                        */
+  MM_ERR_NODEVICE = 9     /* no usable gfx950 device                          */
+} mm_status;
+
+typedef enum { MM_R32 = 0, MM_R64 = 1, MM_C64 = 2, MM_C128 = 3 } mm_dtype;
+
+/* Arithmetic of the contractions.
+ *  MM_PREC_FP64         FP64 MFMA, FP64 state.
+ *  MM_PREC_FP32         FP32 MFMA, FP32 state.
+ *  MM_PREC_SPLIT_BF16X3 operator and state split into three RNE bfloat16
+ *                       pieces each (x = x0 + x1 + x2); the six piece
+ *                       products x_a y_b with a + b <= 2 run on BF16 MFMA with
+ *                       FP32 accumulation.
+ *  MM_PREC_BF16         one bfloat16 piece each (single BF16 MFMA product);
+ *                       reported for comparison only.                        */
+typedef enum {
+  MM_PREC_FP64 = 0,
+  MM_PREC_FP32 = 1,
+  MM_PREC_SPLIT_BF16X3 = 2,
+  MM_PREC_BF16 = 3
+} mm_prec;
+
+#define MM_MAXD 6
+
+typedef struct mm_ctx_s* mm_ctx;
+typedef struct mm_op_s* mm_op;
+typedef struct ihipStream_t* mm_stream; /* same object as hipStream_t */
+
+typedef struct {
+  int d;                   /* order of the tensor, 1..MM_MAXD                  */
+  int64_t dims[MM_MAXD];   /* n_1..n_d (entries beyond d ignored)              */
+  mm_dtype dtype;
+  void* data;              /* device pointer, column-major, 16-byte aligned    */
+} mm_tensor;
+
+typedef struct {
+  int64_t rows, cols, ld;  /* ld >= rows                                        */
+  mm_dtype dtype;          /* MM_R64 or MM_C128                                 */
+  const void* data;        /* column-major FP64 master                          */
+  int on_device;           /* 0: host pointer, 1: device pointer                */
+} mm_matrix;
+
+/* ------------------------------------------------------------ context ---- */
+
+/* Create a context on HIP device `device` (checks it is gfx950).
+ * Returns MM_ERR_NODEVICE if there is none; *out is NULL on failure. */
+mm_status mm_create(mm_ctx* out, int device);
+/* Free every operator and buffer the context owns.  NULL is accepted. */
+mm_status mm_destroy(mm_ctx ctx);
+/* Static description of a status code. */
+const char* mm_status_string(mm_status s);
+/* Detail text of the last failure on this context ("" if none); valid until
+ * the next call on ctx.  With ctx == NULL: the last mm_create failure. */
+const char* mm_last_error(mm_ctx ctx);
+/* Library version string. */
+const char* mm_version(void);
+
+/* ---------------------------------------------------------- operators ---- */
+
+/* Prepare a matrix L (rows m x cols n) for the given precision: copy the FP64
+ * master to the device and convert / split it into the layout the kernels
+ * read.  The context owns *out.  m, n in [1, 4096]. */
+mm_status mm_op_prepare(mm_ctx ctx, const mm_matrix* master, mm_prec prec, mm_op* out);
+mm_status mm_op_destroy(mm_ctx ctx, mm_op op);
+/* Shape / type query of a prepared operator (any out pointer may be NULL). */
+mm_status mm_op_info(mm_op op, int64_t* rows, int64_t* cols, int* is_complex, mm_prec* prec);
+
+/* ------------------------------------------------------ tensor products -- */
+
+/* S = T x_mu L (Definition 2.1): S(.., i, ..) = sum_j L[i,j] T(.., j, ..).
+ * mu is 1-based.  out->dims must equal T->dims with dims[mu-1] replaced by
+ * L's rows; out must not overlap T (MM_ERR_ARG). */
+mm_status mumode_apply(mm_ctx ctx, mm_tensor* out, const mm_tensor* T, mm_op L, int mu,
+                       mm_stream stream);
+
+/* mu-mode integrator (Section 2, equation dd-tensor), in place, nsteps times:
+ * T <- T x_1 E[0] x_2 E[1] ... x_d E[d-1].  E[k] == NULL leaves mode k+1
+ * unchanged.  Every non-NULL E[k] must be square n_{k+1} x n_{k+1}. */
+mm_status mumode_expstep(mm_ctx ctx, mm_tensor* T, const mm_op* E, int nsteps, mm_stream stream);
+
+/* Tucker operator with rectangular matrices (Section 3, equations
+ * real2spec and spec2real): out = in x_1 Phi[0] ... x_d Phi[d-1], with
+ * out->dims[k] = rows of Phi[k] (in->dims[k] if Phi[k] == NULL).  out must
+ * not overlap in. */
+mm_status mumode_transform(mm_ctx ctx, mm_tensor* out, const mm_tensor* in, const mm_op* Phi,
+                           mm_stream stream);
+
+/* Strang splitting for the cubic Gross-Pitaevskii equation
+ * i psi_t = H psi + beta |psi|^2 psi with H in Kronecker form (Section 4.5:
+ * linear part by the integrator, nonlinear part integrated exactly).  One step
+ * is N(tau/2) L(tau) N(tau/2) with L(tau) = x_1 E[0] ... x_d E[d-1],
+ * E[k] = exp(-i tau H_{k+1}), and N(s) psi = exp(-i s beta |psi|^2) psi.
+ * Adjacent half steps of N are merged (exact, since N keeps |psi|), and each
+ * N is fused into the neighbouring mode product.  psi is complex (MM_C64 or
+ * MM_C128), updated in place. */
+mm_status gpe_strang_step(mm_ctx ctx, mm_tensor* psi, const mm_op* E, double tau, double beta,
+                          int nsteps, mm_stream stream);
+
+/* Discrete mass cell * sum |T|^2, accumulated in FP64 on the device;
+ * synchronises `stream`.  Returns MM_ERR_NONFINITE if T holds NaN / Inf. */
+mm_status mm_norm2(mm_ctx ctx, const mm_tensor* T, double cell, double* host_out, mm_stream stream);
+
+/* ------------------------------------------ FP64 operator formation (host) */
+
+/* Second-order centred second difference h^-2 (1, -2, 1) on n nodes of
+ * [a, b] (Section 4.1): bc = 0 Dirichlet (n interior nodes,
+ * h = (b-a)/(n+1)), bc = 1 periodic (h = (b-a)/n).  out: n*n doubles,
+ * column-major, caller-owned. */
+mm_status mm_fd2_matrix(int n, double a, double b, int bc, double* out);
+
+/* exp(c A) for a complex n x n matrix A (column-major interleaved, n*n*2
+ * doubles) and complex scalar c = c_re + i c_im, by scaling and squaring of a
+ * truncated Taylor series in FP64 (host).  out: n*n*2 doubles. */
+mm_status mm_expm(int n, const double* A, double c_re, double c_im, double* out);
+
+/* Gauss-Hermite nodes X (m doubles, ascending) and Hermite-function weights
+ * w_l = 1/(m phi_{m-1}(X_l)^2) (Section 3). */
+mm_status mm_hermite_nodes(int m, double* X, double* w);
+
+/* Hermite transform matrices at the m Gauss-Hermite nodes (Section 3):
+ * forward Phi[k,l] = phi_k(X_l) w_l and backward Psi[l,k] = phi_k(X_l), both
+ * m x m column-major real (either pointer may be NULL). */
+mm_status mm_hermite_matrices(int m, double* Phi, double* Psi);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MUMODE_H */

@@ -1,0 +1,207 @@
+"""Python binding of the MI355X mu-mode product library (include/mumode.h).
+
+Argument marshalling only: every tensor operation runs in the HIP kernels of
+``libmumode.so``.  Tensors are torch tensors on the GPU with shape
+(n_d, ..., n_1), C-contiguous, so that their memory is the column-major
+(i_1 fastest) layout of the library; dtypes float32, float64, complex64,
+complex128.  Matrices are numpy arrays indexed L[i, j]; they are handed to
+the library as column-major FP64 masters.  Work is enqueued on torch's
+current stream.
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+
+from . import _lib
+from ._lib import (MM_C64, MM_C128, MM_PREC_BF16, MM_PREC_FP32, MM_PREC_FP64,  # noqa: F401
+                   MM_PREC_SPLIT_BF16X3, MM_R32, MM_R64)
+
+PRECISIONS = {"fp64": MM_PREC_FP64, "fp32": MM_PREC_FP32, "bf16x3": MM_PREC_SPLIT_BF16X3,
+              "bf16": MM_PREC_BF16}
+
+
+class MumodeError(RuntimeError):
+    def __init__(self, status: int, where: str, detail: str):
+        self.status = status
+        name = _lib.lib.mm_status_string(status).decode()
+        super().__init__(f"{where}: {name} ({status}): {detail}")
+
+
+def _check(status: int, where: str, ctx=None):
+    if status != 0:
+        detail = _lib.lib.mm_last_error(ctx).decode() if ctx is not None or where == "mm_create" else ""
+        raise MumodeError(status, where, detail)
+
+
+def version() -> str:
+    return _lib.lib.mm_version().decode()
+
+
+# ------------------------------------------------------------ host FP64 ----
+
+def fd2_matrix(n: int, a: float, b: float, bc: str = "dirichlet") -> np.ndarray:
+    out = np.zeros((n, n), dtype=np.float64, order="F")
+    _check(_lib.lib.mm_fd2_matrix(n, a, b, 0 if bc == "dirichlet" else 1,
+                                  out.ctypes.data_as(C.POINTER(C.c_double))), "mm_fd2_matrix")
+    return np.asarray(out)
+
+
+def expm(A: np.ndarray, c: complex = 1.0) -> np.ndarray:
+    """exp(c A) of a small square matrix (FP64 on the host)."""
+    A = np.asfortranarray(np.asarray(A, dtype=np.complex128))
+    n = A.shape[0]
+    out = np.zeros((n, n), dtype=np.complex128, order="F")
+    _check(_lib.lib.mm_expm(n, A.ctypes.data_as(C.POINTER(C.c_double)), float(np.real(c)), float(np.imag(c)),
+                            out.ctypes.data_as(C.POINTER(C.c_double))), "mm_expm")
+    return np.asarray(out)
+
+
+def hermite_nodes(m: int):
+    X = np.zeros(m)
+    w = np.zeros(m)
+    _check(_lib.lib.mm_hermite_nodes(m, X.ctypes.data_as(C.POINTER(C.c_double)),
+                                     w.ctypes.data_as(C.POINTER(C.c_double))), "mm_hermite_nodes")
+    return X, w
+
+
+def hermite_matrices(m: int):
+    Phi = np.zeros((m, m), order="F")
+    Psi = np.zeros((m, m), order="F")
+    _check(_lib.lib.mm_hermite_matrices(m, Phi.ctypes.data_as(C.POINTER(C.c_double)),
+                                        Psi.ctypes.data_as(C.POINTER(C.c_double))), "mm_hermite_matrices")
+    return np.asarray(Phi), np.asarray(Psi)
+
+
+# -------------------------------------------------------------- tensors ----
+
+def _dtype_code(t) -> int:
+    import torch
+    m = {torch.float32: MM_R32, torch.float64: MM_R64, torch.complex64: MM_C64, torch.complex128: MM_C128}
+    if t.dtype not in m:
+        raise TypeError(f"unsupported dtype {t.dtype}")
+    return m[t.dtype]
+
+
+def as_mm_tensor(t) -> _lib.MMTensor:
+    if not t.is_contiguous():
+        raise ValueError("tensor must be contiguous")
+    d = t.dim()
+    if not 1 <= d <= _lib.MM_MAXD:
+        raise ValueError("tensor order out of range")
+    mt = _lib.MMTensor()
+    mt.d = d
+    for k in range(d):
+        mt.dims[k] = int(t.shape[d - 1 - k])      # n_1 is the last torch dim
+    mt.dtype = _dtype_code(t)
+    mt.data = t.data_ptr()
+    return mt
+
+
+def _stream(stream):
+    if stream is not None:
+        return C.c_void_p(int(stream))
+    import torch
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class Op:
+    """A prepared operator owned by a Context."""
+
+    def __init__(self, ctx: "Context", handle: C.c_void_p, rows: int, cols: int, cplx: bool, prec: int):
+        self.ctx = ctx
+        self.handle = handle
+        self.rows, self.cols, self.cplx, self.prec = rows, cols, cplx, prec
+
+    def destroy(self):
+        if self.handle:
+            _check(_lib.lib.mm_op_destroy(self.ctx.handle, self.handle), "mm_op_destroy", self.ctx.handle)
+            self.handle = None
+
+
+def _op_array(ops):
+    arr = (C.c_void_p * len(ops))()
+    for k, o in enumerate(ops):
+        arr[k] = None if o is None else o.handle
+    return arr
+
+
+class Context:
+    """mm_create / mm_destroy around one device."""
+
+    def __init__(self, device: int = 0):
+        h = C.c_void_p()
+        st = _lib.lib.mm_create(C.byref(h), device)
+        if st != 0:
+            raise MumodeError(st, "mm_create", _lib.lib.mm_last_error(None).decode())
+        self.handle = h
+        self.device = device
+
+    def close(self):
+        if self.handle:
+            _lib.lib.mm_destroy(self.handle)
+            self.handle = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _chk(self, st, where):
+        _check(st, where, self.handle)
+
+    # ------------------------------------------------------------ ops ----
+    def mm_op_prepare(self, L: np.ndarray, prec="fp64") -> Op:
+        prec = PRECISIONS[prec] if isinstance(prec, str) else int(prec)
+        L = np.asarray(L)
+        cplx = np.iscomplexobj(L)
+        F = np.asfortranarray(L.astype(np.complex128 if cplx else np.float64))
+        m = _lib.MMMatrix()
+        m.rows, m.cols = F.shape
+        m.ld = F.shape[0]
+        m.dtype = MM_C128 if cplx else MM_R64
+        m.data = F.ctypes.data
+        m.on_device = 0
+        h = C.c_void_p()
+        self._chk(_lib.lib.mm_op_prepare(self.handle, C.byref(m), prec, C.byref(h)), "mm_op_prepare")
+        return Op(self, h, F.shape[0], F.shape[1], cplx, prec)
+
+    # -------------------------------------------------------- products ----
+    def mumode_apply(self, out, T, L: Op, mu: int, stream=None):
+        o, t = as_mm_tensor(out), as_mm_tensor(T)
+        self._chk(_lib.lib.mumode_apply(self.handle, C.byref(o), C.byref(t), L.handle, mu, _stream(stream)),
+                  "mumode_apply")
+        return out
+
+    def mumode_expstep(self, T, E, nsteps: int = 1, stream=None):
+        t = as_mm_tensor(T)
+        self._chk(_lib.lib.mumode_expstep(self.handle, C.byref(t), _op_array(E), nsteps, _stream(stream)),
+                  "mumode_expstep")
+        return T
+
+    def mumode_transform(self, out, T, Phi, stream=None):
+        o, t = as_mm_tensor(out), as_mm_tensor(T)
+        self._chk(_lib.lib.mumode_transform(self.handle, C.byref(o), C.byref(t), _op_array(Phi),
+                                            _stream(stream)), "mumode_transform")
+        return out
+
+    def gpe_strang_step(self, psi, E, tau: float, beta: float, nsteps: int = 1, stream=None):
+        t = as_mm_tensor(psi)
+        self._chk(_lib.lib.gpe_strang_step(self.handle, C.byref(t), _op_array(E), float(tau), float(beta),
+                                           nsteps, _stream(stream)), "gpe_strang_step")
+        return psi
+
+    def mm_norm2(self, T, cell: float = 1.0, stream=None) -> float:
+        t = as_mm_tensor(T)
+        out = C.c_double()
+        self._chk(_lib.lib.mm_norm2(self.handle, C.byref(t), float(cell), C.byref(out), _stream(stream)),
+                  "mm_norm2")
+        return out.value

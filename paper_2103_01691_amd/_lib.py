@@ -1,0 +1,77 @@
+"""ctypes declarations of the C ABI in include/mumode.h.
+
+Loads the in-tree ``libmumode.so``.  There is no fallback: if the library is
+missing, importing this module raises, so nothing silently runs elsewhere.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libmumode.so")
+
+MM_MAXD = 6
+
+MM_OK, MM_ERR_ARG, MM_ERR_SHAPE, MM_ERR_DTYPE, MM_ERR_ALIGN, MM_ERR_NOMEM, MM_ERR_HIP, \
+    MM_ERR_UNSUPPORTED, MM_ERR_NONFINITE, MM_ERR_NODEVICE = range(10)
+MM_R32, MM_R64, MM_C64, MM_C128 = range(4)
+MM_PREC_FP64, MM_PREC_FP32, MM_PREC_SPLIT_BF16X3, MM_PREC_BF16 = range(4)
+
+# every symbol include/mumode.h declares
+EXPORTS = [
+    "mm_create", "mm_destroy", "mm_status_string", "mm_last_error", "mm_version",
+    "mm_op_prepare", "mm_op_destroy", "mm_op_info",
+    "mumode_apply", "mumode_expstep", "mumode_transform", "gpe_strang_step", "mm_norm2",
+    "mm_fd2_matrix", "mm_expm", "mm_hermite_nodes", "mm_hermite_matrices",
+]
+
+
+class MMTensor(C.Structure):
+    _fields_ = [("d", C.c_int), ("dims", C.c_int64 * MM_MAXD), ("dtype", C.c_int), ("data", C.c_void_p)]
+
+
+class MMMatrix(C.Structure):
+    _fields_ = [("rows", C.c_int64), ("cols", C.c_int64), ("ld", C.c_int64), ("dtype", C.c_int),
+                ("data", C.c_void_p), ("on_device", C.c_int)]
+
+
+def _load():
+    # torch ships its own HIP runtime (soname libamdhip64.so.7).  Loading it
+    # first makes the library bind to that same runtime instead of pulling in
+    # a second HIP / HSA runtime from /opt/rocm, which would leave torch
+    # without devices.
+    import torch  # noqa: F401
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run paper_2103_01691_amd.build.build()")
+    lib = C.CDLL(LIB_PATH)
+    st = C.c_int
+    P = C.c_void_p
+    d = C.c_double
+    sig = {
+        "mm_create": (st, [C.POINTER(P), C.c_int]),
+        "mm_destroy": (st, [P]),
+        "mm_status_string": (C.c_char_p, [st]),
+        "mm_last_error": (C.c_char_p, [P]),
+        "mm_version": (C.c_char_p, []),
+        "mm_op_prepare": (st, [P, C.POINTER(MMMatrix), C.c_int, C.POINTER(P)]),
+        "mm_op_destroy": (st, [P, P]),
+        "mm_op_info": (st, [P, C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_int), C.POINTER(C.c_int)]),
+        "mumode_apply": (st, [P, C.POINTER(MMTensor), C.POINTER(MMTensor), P, C.c_int, P]),
+        "mumode_expstep": (st, [P, C.POINTER(MMTensor), C.POINTER(P), C.c_int, P]),
+        "mumode_transform": (st, [P, C.POINTER(MMTensor), C.POINTER(MMTensor), C.POINTER(P), P]),
+        "gpe_strang_step": (st, [P, C.POINTER(MMTensor), C.POINTER(P), d, d, C.c_int, P]),
+        "mm_norm2": (st, [P, C.POINTER(MMTensor), d, C.POINTER(d), P]),
+        "mm_fd2_matrix": (st, [C.c_int, d, d, C.c_int, C.POINTER(d)]),
+        "mm_expm": (st, [C.c_int, C.POINTER(d), d, d, C.POINTER(d)]),
+        "mm_hermite_nodes": (st, [C.c_int, C.POINTER(d), C.POINTER(d)]),
+        "mm_hermite_matrices": (st, [C.c_int, C.POINTER(d), C.POINTER(d)]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    return lib
+
+
+lib = _load()

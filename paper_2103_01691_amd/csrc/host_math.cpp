@@ -1,0 +1,181 @@
+// FP64 formation of the small 1-D operators on the host: finite-difference
+// generators (Section 4.1), the matrix exponential E = exp(c A) of a small
+// dense matrix (Section 2: the d exponentials are precomputed once for a
+// constant step), and Gauss-Hermite nodes, weights and transform matrices
+// (Section 3).  None of this is on the per-step path.
+#include <cmath>
+#include <complex>
+#include <cstring>
+#include <vector>
+
+#include "../../include/mumode.h"
+
+namespace {
+
+typedef std::complex<double> cd;
+
+// C = A B, n x n complex, column-major.
+void matmul(int n, const cd* A, const cd* B, cd* C) {
+  for (int j = 0; j < n; ++j) {
+    cd* c = C + (size_t)j * n;
+    for (int i = 0; i < n; ++i) c[i] = 0.0;
+    for (int k = 0; k < n; ++k) {
+      const cd b = B[k + (size_t)j * n];
+      if (b == 0.0) continue;
+      const cd* a = A + (size_t)k * n;
+      for (int i = 0; i < n; ++i) c[i] += a[i] * b;
+    }
+  }
+}
+
+double norm1(int n, const cd* A) {
+  double m = 0.0;
+  for (int j = 0; j < n; ++j) {
+    double s = 0.0;
+    for (int i = 0; i < n; ++i) s += std::abs(A[i + (size_t)j * n]);
+    m = std::max(m, s);
+  }
+  return m;
+}
+
+// Orthonormal Hermite functions phi_0..phi_{kmax-1} at x (three-term
+// recurrence normalised for H_k exp(-x^2/2)).
+void hermite_values(int kmax, double x, double* phi) {
+  phi[0] = std::pow(M_PI, -0.25) * std::exp(-0.5 * x * x);
+  if (kmax > 1) phi[1] = std::sqrt(2.0) * x * phi[0];
+  for (int k = 1; k + 1 < kmax; ++k)
+    phi[k + 1] = std::sqrt(2.0 / (k + 1)) * x * phi[k] - std::sqrt((double)k / (k + 1)) * phi[k - 1];
+}
+
+// Number of eigenvalues below x of the symmetric tridiagonal Jacobi matrix of
+// the Hermite recurrence (zero diagonal, off-diagonal sqrt(k/2)), by the
+// Sturm sequence of its leading principal minors.
+int sturm_count(int m, double x) {
+  int cnt = 0;
+  double q = -x;
+  if (q < 0) ++cnt;
+  for (int k = 1; k < m; ++k) {
+    const double b2 = 0.5 * k;
+    if (q == 0.0) q = 1e-300;
+    q = -x - b2 / q;
+    if (q < 0) ++cnt;
+  }
+  return cnt;
+}
+
+}  // namespace
+
+extern "C" {
+
+mm_status mm_fd2_matrix(int n, double a, double b, int bc, double* out) {
+  if (!out) return MM_ERR_ARG;
+  if (n < 1 || n > 65536 || !(b > a)) return MM_ERR_SHAPE;
+  if (bc != 0 && bc != 1) return MM_ERR_ARG;
+  if (bc == 1 && n < 3) return MM_ERR_SHAPE;
+  const double h = bc == 0 ? (b - a) / (n + 1) : (b - a) / n;
+  const double s = 1.0 / (h * h);
+  std::memset(out, 0, sizeof(double) * (size_t)n * n);
+  for (int j = 0; j < n; ++j) {
+    out[j + (size_t)j * n] = -2.0 * s;
+    if (j > 0) out[j + (size_t)(j - 1) * n] = s;
+    if (j + 1 < n) out[j + (size_t)(j + 1) * n] = s;
+  }
+  if (bc == 1) {
+    out[0 + (size_t)(n - 1) * n] += s;
+    out[(n - 1) + 0] += s;
+  }
+  return MM_OK;
+}
+
+mm_status mm_expm(int n, const double* A, double c_re, double c_im, double* out) {
+  if (!A || !out) return MM_ERR_ARG;
+  if (n < 1 || n > 4096) return MM_ERR_SHAPE;
+  const size_t nn = (size_t)n * n;
+  const cd c(c_re, c_im);
+  std::vector<cd> X(nn), T(nn), W(nn);
+  for (size_t e = 0; e < nn; ++e) {
+    const cd v = c * cd(A[2 * e], A[2 * e + 1]);
+    if (!std::isfinite(v.real()) || !std::isfinite(v.imag())) return MM_ERR_NONFINITE;
+    X[e] = v;
+  }
+  // scaling: ||X / 2^s||_1 <= 1/2
+  const double nrm = norm1(n, X.data());
+  int s = 0;
+  if (nrm > 0.5) s = (int)std::ceil(std::log2(nrm / 0.5));
+  const double sc = std::ldexp(1.0, -s);
+  for (auto& v : X) v *= sc;
+  // Taylor polynomial of degree 18 by Horner's rule: the truncation error
+  // for ||X|| <= 1/2 is below 0.5^19 / 19! ~ 1.6e-23.
+  const int deg = 18;
+  for (size_t e = 0; e < nn; ++e) T[e] = 0.0;
+  for (int i = 0; i < n; ++i) T[i + (size_t)i * n] = 1.0;
+  for (int k = deg; k >= 1; --k) {
+    matmul(n, X.data(), T.data(), W.data());
+    const double f = 1.0 / k;
+    for (size_t e = 0; e < nn; ++e) T[e] = W[e] * f;
+    for (int i = 0; i < n; ++i) T[i + (size_t)i * n] += 1.0;
+  }
+  // squaring
+  for (int k = 0; k < s; ++k) {
+    matmul(n, T.data(), T.data(), W.data());
+    T.swap(W);
+  }
+  for (size_t e = 0; e < nn; ++e) {
+    out[2 * e] = T[e].real();
+    out[2 * e + 1] = T[e].imag();
+  }
+  return MM_OK;
+}
+
+mm_status mm_hermite_nodes(int m, double* X, double* w) {
+  if (!X) return MM_ERR_ARG;
+  if (m < 1 || m > 4096) return MM_ERR_SHAPE;
+  // Gershgorin bound of the Jacobi matrix
+  const double R = 2.0 * std::sqrt(0.5 * (m - 1)) + 1.0;
+  std::vector<double> phi(m + 1);
+  for (int k = 0; k < m; ++k) {
+    // k-th eigenvalue (ascending) by bisection on the Sturm count
+    double lo = -R, hi = R;
+    for (int it = 0; it < 200 && hi - lo > 1e-15 * std::max(1.0, std::fabs(lo)); ++it) {
+      const double mid = 0.5 * (lo + hi);
+      if (sturm_count(m, mid) > k) hi = mid;
+      else lo = mid;
+    }
+    double x = 0.5 * (lo + hi);
+    // Newton polish on phi_m(x) = 0, phi_m' = sqrt(2m) phi_{m-1} - x phi_m
+    for (int it = 0; it < 3; ++it) {
+      hermite_values(m + 1, x, phi.data());
+      const double f = phi[m];
+      const double fp = std::sqrt(2.0 * m) * phi[m - 1] - x * phi[m];
+      if (fp == 0.0) break;
+      const double dx = f / fp;
+      if (std::fabs(dx) > 1e-6 * std::max(1.0, std::fabs(x))) break;
+      x -= dx;
+    }
+    X[k] = x;
+  }
+  if (w) {
+    for (int k = 0; k < m; ++k) {
+      hermite_values(m, X[k], phi.data());
+      w[k] = 1.0 / (m * phi[m - 1] * phi[m - 1]);
+    }
+  }
+  return MM_OK;
+}
+
+mm_status mm_hermite_matrices(int m, double* Phi, double* Psi) {
+  if (m < 1 || m > 4096) return MM_ERR_SHAPE;
+  std::vector<double> X(m), w(m), phi(m);
+  mm_status st = mm_hermite_nodes(m, X.data(), w.data());
+  if (st != MM_OK) return st;
+  for (int l = 0; l < m; ++l) {
+    hermite_values(m, X[l], phi.data());
+    for (int k = 0; k < m; ++k) {
+      if (Phi) Phi[k + (size_t)l * m] = phi[k] * w[l];   // Phi[k, l]
+      if (Psi) Psi[l + (size_t)k * m] = phi[k];          // Psi[l, k]
+    }
+  }
+  return MM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,521 @@
+// Host runtime of the mu-mode library: contexts, prepared operators,
+// argument validation and dispatch of the mode-product kernels.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/mumode.h"
+#include "mm_internal.h"
+
+struct mm_op_s {
+  int64_t rows = 0, cols = 0;
+  int cplx = 0;
+  mm_prec prec = MM_PREC_FP64;
+  double* dev_master = nullptr;  // FP64 master on the device, ld = rows
+  void* prep = nullptr;          // fragment-order operator (own complexity)
+  int KBT = 0, MFT = 0;
+  void* prep_c = nullptr;        // real master promoted to complex (lazily)
+  int KBT_c = 0, MFT_c = 0;
+  double* dev_master_c = nullptr;
+};
+
+struct mm_ctx_s {
+  int device = 0;
+  std::string err;
+  std::vector<mm_op> ops;
+  void* ws = nullptr;            // ping-pong buffer for products that cannot run in place
+  size_t ws_bytes = 0;
+  double* red_partial = nullptr;
+  double* red_result = nullptr;
+  double* host_result = nullptr; // pinned
+};
+
+namespace {
+
+std::string g_create_err;
+
+mm_status fail(mm_ctx ctx, mm_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  if (ctx) ctx->err = buf;
+  else g_create_err = buf;
+  return st;
+}
+
+#define HIPCHK(ctx, call)                                                              \
+  do {                                                                                 \
+    hipError_t e_ = (call);                                                            \
+    if (e_ != hipSuccess)                                                              \
+      return fail(ctx, MM_ERR_HIP, "%s failed: %s", #call, hipGetErrorString(e_));    \
+  } while (0)
+
+int kprec(mm_prec p) {
+  switch (p) {
+    case MM_PREC_FP64: return mm::KP_F64;
+    case MM_PREC_FP32: return mm::KP_F32;
+    case MM_PREC_SPLIT_BF16X3: return mm::KP_BF16X3;
+    default: return mm::KP_BF16;
+  }
+}
+
+bool is_complex(mm_dtype t) { return t == MM_C64 || t == MM_C128; }
+bool is_f64(mm_dtype t) { return t == MM_R64 || t == MM_C128; }
+size_t dsize(mm_dtype t) { return t == MM_R32 ? 4 : (t == MM_C128 ? 16 : 8); }
+
+int64_t numel(const mm_tensor* T) {
+  int64_t n = 1;
+  for (int k = 0; k < T->d; ++k) n *= T->dims[k];
+  return n;
+}
+
+mm_status check_tensor(mm_ctx ctx, const mm_tensor* T, const char* name) {
+  if (!T) return fail(ctx, MM_ERR_ARG, "%s is NULL", name);
+  if (T->d < 1 || T->d > MM_MAXD) return fail(ctx, MM_ERR_SHAPE, "%s: d = %d outside [1, %d]", name, T->d, MM_MAXD);
+  for (int k = 0; k < T->d; ++k)
+    if (T->dims[k] <= 0) return fail(ctx, MM_ERR_SHAPE, "%s: dims[%d] = %lld <= 0", name, k, (long long)T->dims[k]);
+  if (T->dtype < MM_R32 || T->dtype > MM_C128) return fail(ctx, MM_ERR_ARG, "%s: bad dtype", name);
+  if (!T->data) return fail(ctx, MM_ERR_ARG, "%s: data is NULL", name);
+  if (((uintptr_t)T->data) & 15) return fail(ctx, MM_ERR_ALIGN, "%s: data not 16-byte aligned", name);
+  if (numel(T) > ((int64_t)1 << 40)) return fail(ctx, MM_ERR_SHAPE, "%s: too many entries", name);
+  return MM_OK;
+}
+
+bool overlap(const mm_tensor* A, const mm_tensor* B) {
+  const char* a0 = (const char*)A->data;
+  const char* a1 = a0 + numel(A) * dsize(A->dtype);
+  const char* b0 = (const char*)B->data;
+  const char* b1 = b0 + numel(B) * dsize(B->dtype);
+  return a0 < b1 && b0 < a1;
+}
+
+mm_status check_op_dtype(mm_ctx ctx, mm_op L, mm_dtype t) {
+  if (L->cplx && !is_complex(t)) return fail(ctx, MM_ERR_DTYPE, "complex operator on a real tensor");
+  const bool want64 = L->prec == MM_PREC_FP64;
+  if (want64 != is_f64(t))
+    return fail(ctx, MM_ERR_DTYPE, "operator precision %d does not match tensor dtype %d", (int)L->prec, (int)t);
+  return MM_OK;
+}
+
+// Prepare (or reuse) the fragment-order operator for a given complexity.
+mm_status ensure_prepared(mm_ctx ctx, mm_op L, bool cplx, hipStream_t s, void** prep, int* KBT, int* MFT) {
+  const int kp = kprec(L->prec);
+  mm::FragGeom g = mm::frag_geom(kp);
+  const int64_t Mr = cplx ? 2 * L->rows : L->rows;
+  const int64_t Kr = cplx ? 2 * L->cols : L->cols;
+  const int kbt = (int)((Kr + g.KB - 1) / g.KB);
+  const int mft = (int)((Mr + g.MB - 1) / g.MB);
+  if (cplx == (bool)L->cplx) {
+    *prep = L->prep;
+    *KBT = L->KBT;
+    *MFT = L->MFT;
+    return MM_OK;
+  }
+  // real operator acting on a complex state: promote to complex once
+  if (!L->prep_c) {
+    const size_t nn = (size_t)L->rows * L->cols;
+    std::vector<double> host(nn), cm(2 * nn, 0.0);
+    HIPCHK(ctx, hipMemcpy(host.data(), L->dev_master, nn * sizeof(double), hipMemcpyDeviceToHost));
+    for (size_t e = 0; e < nn; ++e) cm[2 * e] = host[e];
+    HIPCHK(ctx, hipMalloc((void**)&L->dev_master_c, 2 * nn * sizeof(double)));
+    HIPCHK(ctx, hipMemcpy(L->dev_master_c, cm.data(), 2 * nn * sizeof(double), hipMemcpyHostToDevice));
+    HIPCHK(ctx, hipMalloc(&L->prep_c, mm::prepared_bytes(kp, kbt, mft)));
+    HIPCHK(ctx, mm::launch_prepare(kp, 1, L->dev_master_c, L->rows, L->cols, L->rows, nullptr, nullptr,
+                                   L->prep_c, kbt, mft, s));
+    L->KBT_c = kbt;
+    L->MFT_c = mft;
+  }
+  *prep = L->prep_c;
+  *KBT = L->KBT_c;
+  *MFT = L->MFT_c;
+  return MM_OK;
+}
+
+// One mode product out = in x_mu L on a tensor with dims `dims` (input dims),
+// optional fused phases.  `in` and `out` may be equal when the plan covers
+// all rows in one workgroup (checked by the caller through *in_place_ok).
+mm_status run_mode(mm_ctx ctx, const void* in, void* out, const int64_t* dims, int d, mm_dtype dt,
+                   mm_op L, int mu, double s_pre, double s_post, hipStream_t s, mm::ModePlan* plan_out,
+                   bool dry) {
+  const bool cplx = is_complex(dt);
+  void* prep = nullptr;
+  int KBT = 0, MFT = 0;
+  if (!dry) {
+    mm_status st = ensure_prepared(ctx, L, cplx, s, &prep, &KBT, &MFT);
+    if (st != MM_OK) return st;
+  } else {
+    mm::FragGeom g = mm::frag_geom(kprec(L->prec));
+    KBT = (int)(((cplx ? 2 : 1) * L->cols + g.KB - 1) / g.KB);
+    MFT = (int)(((cplx ? 2 : 1) * L->rows + g.MB - 1) / g.MB);
+  }
+  mm::ModeArgs a;
+  int64_t P = 1, Q = 1;
+  for (int k = 0; k < mu - 1; ++k) P *= dims[k];
+  for (int k = mu; k < d; ++k) Q *= dims[k];
+  a.in = in;
+  a.out = out;
+  a.A = prep;
+  a.P = P;
+  a.Q = Q;
+  a.F = P * Q;
+  a.n = (int)dims[mu - 1];
+  a.m = (int)L->rows;
+  a.Kr = (cplx ? 2 : 1) * a.n;
+  a.Mr = (cplx ? 2 : 1) * a.m;
+  a.KBT = KBT;
+  a.MFT = MFT;
+  a.s_pre = s_pre;
+  a.s_post = s_post;
+  const bool kcontig = (P == 1) && (a.Kr % 8 == 0);
+  const bool fcontig = (P % 4 == 0);
+  mm::ModePlan plan;
+  if (!mm::plan_mode(a, kprec(L->prec), cplx ? 1 : 0, s_pre != 0.0, s_post != 0.0, fcontig, kcontig, &plan))
+    return fail(ctx, MM_ERR_UNSUPPORTED, "no kernel plan for this shape");
+  if (plan_out) *plan_out = plan;
+  if (dry) return MM_OK;
+  HIPCHK(ctx, mm::launch_mode(plan, a, s));
+  return MM_OK;
+}
+
+mm_status ensure_ws(mm_ctx ctx, size_t bytes) {
+  if (ctx->ws_bytes >= bytes) return MM_OK;
+  if (ctx->ws) {
+    HIPCHK(ctx, hipDeviceSynchronize());
+    HIPCHK(ctx, hipFree(ctx->ws));
+    ctx->ws = nullptr;
+    ctx->ws_bytes = 0;
+  }
+  if (hipMalloc(&ctx->ws, bytes) != hipSuccess) return fail(ctx, MM_ERR_NOMEM, "workspace of %zu bytes", bytes);
+  ctx->ws_bytes = bytes;
+  return MM_OK;
+}
+
+// Tucker sweep over the modes with per-mode ops (square), in place on T.
+// first_pre / last_post: phase coefficients fused into the first / last
+// applied product (0 = none).
+mm_status sweep(mm_ctx ctx, mm_tensor* T, const mm_op* E, double first_pre, double last_post, hipStream_t s) {
+  int first = -1, last = -1;
+  for (int k = 0; k < T->d; ++k)
+    if (E[k]) {
+      if (first < 0) first = k;
+      last = k;
+    }
+  if (first < 0) return MM_OK;
+  const size_t bytes = (size_t)numel(T) * dsize(T->dtype);
+  void* cur = T->data;
+  for (int k = first; k <= last; ++k) {
+    if (!E[k]) continue;
+    mm::ModePlan plan;
+    mm_status st = run_mode(ctx, cur, cur, T->dims, T->d, T->dtype, E[k], k + 1, 0, 0, s, &plan, true);
+    if (st != MM_OK) return st;
+    void* dst = cur;
+    if (!plan.covers_all_rows) {
+      st = ensure_ws(ctx, bytes);
+      if (st != MM_OK) return st;
+      dst = (cur == T->data) ? ctx->ws : T->data;
+    }
+    st = run_mode(ctx, cur, dst, T->dims, T->d, T->dtype, E[k], k + 1, k == first ? first_pre : 0.0,
+                  k == last ? last_post : 0.0, s, nullptr, false);
+    if (st != MM_OK) return st;
+    cur = dst;
+  }
+  if (cur != T->data) HIPCHK(ctx, hipMemcpyAsync(T->data, cur, bytes, hipMemcpyDeviceToDevice, s));
+  return MM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* mm_version(void) { return "mumode-gfx950 0.1"; }
+
+const char* mm_status_string(mm_status s) {
+  switch (s) {
+    case MM_OK: return "ok";
+    case MM_ERR_ARG: return "invalid argument";
+    case MM_ERR_SHAPE: return "invalid shape";
+    case MM_ERR_DTYPE: return "dtype / precision mismatch";
+    case MM_ERR_ALIGN: return "misaligned data";
+    case MM_ERR_NOMEM: return "out of device memory";
+    case MM_ERR_HIP: return "HIP runtime error";
+    case MM_ERR_UNSUPPORTED: return "unsupported";
+    case MM_ERR_NONFINITE: return "non-finite value";
+    case MM_ERR_NODEVICE: return "no gfx950 device";
+  }
+  return "unknown status";
+}
+
+const char* mm_last_error(mm_ctx ctx) { return ctx ? ctx->err.c_str() : g_create_err.c_str(); }
+
+mm_status mm_create(mm_ctx* out, int device) {
+  if (!out) return fail(nullptr, MM_ERR_ARG, "out is NULL");
+  *out = nullptr;
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess || count <= 0)
+    return fail(nullptr, MM_ERR_NODEVICE, "no HIP device visible");
+  if (device < 0 || device >= count) return fail(nullptr, MM_ERR_NODEVICE, "device %d of %d", device, count);
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, device) != hipSuccess) return fail(nullptr, MM_ERR_NODEVICE, "device properties");
+  if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+    return fail(nullptr, MM_ERR_NODEVICE, "device %d is %s, not gfx950", device, prop.gcnArchName);
+  if (hipSetDevice(device) != hipSuccess) return fail(nullptr, MM_ERR_HIP, "hipSetDevice");
+  mm_ctx c = new mm_ctx_s;
+  c->device = device;
+  if (hipMalloc((void**)&c->red_partial, sizeof(double) * mm::norm_partials()) != hipSuccess ||
+      hipMalloc((void**)&c->red_result, sizeof(double) * 4) != hipSuccess ||
+      hipHostMalloc((void**)&c->host_result, sizeof(double) * 4, hipHostMallocDefault) != hipSuccess) {
+    delete c;
+    return fail(nullptr, MM_ERR_NOMEM, "context buffers");
+  }
+  *out = c;
+  return MM_OK;
+}
+
+mm_status mm_op_destroy(mm_ctx ctx, mm_op op) {
+  if (!ctx || !op) return MM_ERR_ARG;
+  auto it = std::find(ctx->ops.begin(), ctx->ops.end(), op);
+  if (it == ctx->ops.end()) return fail(ctx, MM_ERR_ARG, "operator not owned by this context");
+  ctx->ops.erase(it);
+  hipSetDevice(ctx->device);
+  hipDeviceSynchronize();
+  if (op->dev_master) hipFree(op->dev_master);
+  if (op->prep) hipFree(op->prep);
+  if (op->prep_c) hipFree(op->prep_c);
+  if (op->dev_master_c) hipFree(op->dev_master_c);
+  delete op;
+  return MM_OK;
+}
+
+mm_status mm_destroy(mm_ctx ctx) {
+  if (!ctx) return MM_OK;
+  hipSetDevice(ctx->device);
+  hipDeviceSynchronize();
+  while (!ctx->ops.empty()) mm_op_destroy(ctx, ctx->ops.back());
+  if (ctx->ws) hipFree(ctx->ws);
+  if (ctx->red_partial) hipFree(ctx->red_partial);
+  if (ctx->red_result) hipFree(ctx->red_result);
+  if (ctx->host_result) hipHostFree(ctx->host_result);
+  delete ctx;
+  return MM_OK;
+}
+
+mm_status mm_op_prepare(mm_ctx ctx, const mm_matrix* M, mm_prec prec, mm_op* out) {
+  if (!ctx) return MM_ERR_ARG;
+  if (!M || !out || !M->data) return fail(ctx, MM_ERR_ARG, "NULL matrix or output");
+  *out = nullptr;
+  if (M->dtype != MM_R64 && M->dtype != MM_C128) return fail(ctx, MM_ERR_DTYPE, "master must be MM_R64 or MM_C128");
+  if (prec < MM_PREC_FP64 || prec > MM_PREC_BF16) return fail(ctx, MM_ERR_ARG, "bad precision");
+  if (M->rows < 1 || M->cols < 1 || M->rows > 4096 || M->cols > 4096)
+    return fail(ctx, MM_ERR_SHAPE, "operator %lld x %lld outside [1, 4096]", (long long)M->rows, (long long)M->cols);
+  if (M->ld < M->rows) return fail(ctx, MM_ERR_SHAPE, "ld < rows");
+  HIPCHK(ctx, hipSetDevice(ctx->device));
+  const int cplx = M->dtype == MM_C128;
+  const int comps = cplx ? 2 : 1;
+  // compact host copy (ld = rows)
+  std::vector<double> host((size_t)M->rows * M->cols * comps);
+  if (M->on_device) {
+    std::vector<double> full((size_t)M->ld * M->cols * comps);
+    HIPCHK(ctx, hipMemcpy(full.data(), M->data, full.size() * sizeof(double), hipMemcpyDeviceToHost));
+    for (int64_t j = 0; j < M->cols; ++j)
+      std::memcpy(&host[(size_t)j * M->rows * comps], &full[(size_t)j * M->ld * comps], sizeof(double) * M->rows * comps);
+  } else {
+    const double* src = (const double*)M->data;
+    for (int64_t j = 0; j < M->cols; ++j)
+      std::memcpy(&host[(size_t)j * M->rows * comps], src + (size_t)j * M->ld * comps, sizeof(double) * M->rows * comps);
+  }
+  for (double v : host)
+    if (!std::isfinite(v)) return fail(ctx, MM_ERR_NONFINITE, "operator holds NaN / Inf");
+  mm_op op = new mm_op_s;
+  op->rows = M->rows;
+  op->cols = M->cols;
+  op->cplx = cplx;
+  op->prec = prec;
+  const int kp = kprec(prec);
+  mm::FragGeom g = mm::frag_geom(kp);
+  op->KBT = (int)((comps * M->cols + g.KB - 1) / g.KB);
+  op->MFT = (int)((comps * M->rows + g.MB - 1) / g.MB);
+  if (hipMalloc((void**)&op->dev_master, host.size() * sizeof(double)) != hipSuccess ||
+      hipMalloc(&op->prep, mm::prepared_bytes(kp, op->KBT, op->MFT)) != hipSuccess) {
+    if (op->dev_master) hipFree(op->dev_master);
+    delete op;
+    return fail(ctx, MM_ERR_NOMEM, "operator buffers");
+  }
+  ctx->ops.push_back(op);
+  HIPCHK(ctx, hipMemcpy(op->dev_master, host.data(), host.size() * sizeof(double), hipMemcpyHostToDevice));
+  HIPCHK(ctx, mm::launch_prepare(kp, cplx, op->dev_master, op->rows, op->cols, op->rows, nullptr, nullptr,
+                                 op->prep, op->KBT, op->MFT, 0));
+  HIPCHK(ctx, hipDeviceSynchronize());
+  *out = op;
+  return MM_OK;
+}
+
+mm_status mm_op_info(mm_op op, int64_t* rows, int64_t* cols, int* is_complex_, mm_prec* prec) {
+  if (!op) return MM_ERR_ARG;
+  if (rows) *rows = op->rows;
+  if (cols) *cols = op->cols;
+  if (is_complex_) *is_complex_ = op->cplx;
+  if (prec) *prec = op->prec;
+  return MM_OK;
+}
+
+mm_status mumode_apply(mm_ctx ctx, mm_tensor* out, const mm_tensor* T, mm_op L, int mu, mm_stream stream) {
+  if (!ctx) return MM_ERR_ARG;
+  mm_status st = check_tensor(ctx, T, "T");
+  if (st != MM_OK) return st;
+  st = check_tensor(ctx, out, "out");
+  if (st != MM_OK) return st;
+  if (!L) return fail(ctx, MM_ERR_ARG, "operator is NULL");
+  if (mu < 1 || mu > T->d) return fail(ctx, MM_ERR_SHAPE, "mu = %d outside [1, %d]", mu, T->d);
+  if (L->cols != T->dims[mu - 1])
+    return fail(ctx, MM_ERR_SHAPE, "operator has %lld columns, n_mu = %lld", (long long)L->cols, (long long)T->dims[mu - 1]);
+  if (out->d != T->d || out->dtype != T->dtype) return fail(ctx, MM_ERR_SHAPE, "out must have T's order and dtype");
+  for (int k = 0; k < T->d; ++k) {
+    const int64_t want = (k == mu - 1) ? L->rows : T->dims[k];
+    if (out->dims[k] != want) return fail(ctx, MM_ERR_SHAPE, "out dims[%d] = %lld, expected %lld", k, (long long)out->dims[k], (long long)want);
+  }
+  st = check_op_dtype(ctx, L, T->dtype);
+  if (st != MM_OK) return st;
+  if (overlap(out, T)) return fail(ctx, MM_ERR_ARG, "out overlaps T");
+  HIPCHK(ctx, hipSetDevice(ctx->device));
+  return run_mode(ctx, T->data, out->data, T->dims, T->d, T->dtype, L, mu, 0, 0, (hipStream_t)stream, nullptr, false);
+}
+
+mm_status mumode_expstep(mm_ctx ctx, mm_tensor* T, const mm_op* E, int nsteps, mm_stream stream) {
+  if (!ctx) return MM_ERR_ARG;
+  mm_status st = check_tensor(ctx, T, "T");
+  if (st != MM_OK) return st;
+  if (!E) return fail(ctx, MM_ERR_ARG, "E is NULL");
+  if (nsteps < 0) return fail(ctx, MM_ERR_ARG, "nsteps < 0");
+  for (int k = 0; k < T->d; ++k) {
+    if (!E[k]) continue;
+    if (E[k]->rows != E[k]->cols || E[k]->cols != T->dims[k])
+      return fail(ctx, MM_ERR_SHAPE, "E[%d] must be %lld x %lld", k, (long long)T->dims[k], (long long)T->dims[k]);
+    st = check_op_dtype(ctx, E[k], T->dtype);
+    if (st != MM_OK) return st;
+  }
+  HIPCHK(ctx, hipSetDevice(ctx->device));
+  for (int it = 0; it < nsteps; ++it) {
+    st = sweep(ctx, T, E, 0.0, 0.0, (hipStream_t)stream);
+    if (st != MM_OK) return st;
+  }
+  return MM_OK;
+}
+
+mm_status mumode_transform(mm_ctx ctx, mm_tensor* out, const mm_tensor* in, const mm_op* Phi, mm_stream stream) {
+  if (!ctx) return MM_ERR_ARG;
+  mm_status st = check_tensor(ctx, in, "in");
+  if (st != MM_OK) return st;
+  st = check_tensor(ctx, out, "out");
+  if (st != MM_OK) return st;
+  if (!Phi) return fail(ctx, MM_ERR_ARG, "Phi is NULL");
+  if (out->d != in->d || out->dtype != in->dtype) return fail(ctx, MM_ERR_SHAPE, "out must have in's order and dtype");
+  for (int k = 0; k < in->d; ++k) {
+    if (Phi[k]) {
+      if (Phi[k]->cols != in->dims[k]) return fail(ctx, MM_ERR_SHAPE, "Phi[%d] has %lld columns, expected %lld", k, (long long)Phi[k]->cols, (long long)in->dims[k]);
+      st = check_op_dtype(ctx, Phi[k], in->dtype);
+      if (st != MM_OK) return st;
+    }
+    const int64_t want = Phi[k] ? Phi[k]->rows : in->dims[k];
+    if (out->dims[k] != want) return fail(ctx, MM_ERR_SHAPE, "out dims[%d] = %lld, expected %lld", k, (long long)out->dims[k], (long long)want);
+  }
+  if (overlap(out, in)) return fail(ctx, MM_ERR_ARG, "out overlaps in");
+  HIPCHK(ctx, hipSetDevice(ctx->device));
+  hipStream_t s = (hipStream_t)stream;
+  // chain of rectangular products: in -> A -> B -> ... -> out, where the
+  // intermediate tensors live in the workspace (two halves) and the last
+  // product writes out.
+  int last = -1, count = 0;
+  for (int k = 0; k < in->d; ++k)
+    if (Phi[k]) {
+      last = k;
+      ++count;
+    }
+  const size_t es = dsize(in->dtype);
+  if (count == 0) {
+    HIPCHK(ctx, hipMemcpyAsync(out->data, in->data, (size_t)numel(in) * es, hipMemcpyDeviceToDevice, s));
+    return MM_OK;
+  }
+  // largest intermediate
+  int64_t dims[MM_MAXD];
+  for (int k = 0; k < in->d; ++k) dims[k] = in->dims[k];
+  size_t maxb = 0;
+  for (int k = 0; k < in->d; ++k) {
+    if (!Phi[k]) continue;
+    dims[k] = Phi[k]->rows;
+    int64_t n = 1;
+    for (int q = 0; q < in->d; ++q) n *= dims[q];
+    maxb = std::max(maxb, (size_t)n * es);
+  }
+  const size_t half = (maxb + 255) / 256 * 256;
+  if (count > 1) {
+    st = ensure_ws(ctx, 2 * half);
+    if (st != MM_OK) return st;
+  }
+  for (int k = 0; k < in->d; ++k) dims[k] = in->dims[k];
+  const void* cur = in->data;
+  int pp = 0;
+  for (int k = 0; k < in->d; ++k) {
+    if (!Phi[k]) continue;
+    void* dst = (k == last) ? out->data : (void*)((char*)ctx->ws + pp * half);
+    st = run_mode(ctx, cur, dst, dims, in->d, in->dtype, Phi[k], k + 1, 0, 0, s, nullptr, false);
+    if (st != MM_OK) return st;
+    dims[k] = Phi[k]->rows;
+    cur = dst;
+    pp ^= 1;
+  }
+  return MM_OK;
+}
+
+mm_status gpe_strang_step(mm_ctx ctx, mm_tensor* psi, const mm_op* E, double tau, double beta, int nsteps,
+                          mm_stream stream) {
+  if (!ctx) return MM_ERR_ARG;
+  mm_status st = check_tensor(ctx, psi, "psi");
+  if (st != MM_OK) return st;
+  if (!is_complex(psi->dtype)) return fail(ctx, MM_ERR_DTYPE, "psi must be complex");
+  if (!E) return fail(ctx, MM_ERR_ARG, "E is NULL");
+  if (nsteps < 0) return fail(ctx, MM_ERR_ARG, "nsteps < 0");
+  if (!std::isfinite(tau) || !std::isfinite(beta)) return fail(ctx, MM_ERR_ARG, "tau / beta not finite");
+  for (int k = 0; k < psi->d; ++k) {
+    if (!E[k]) return fail(ctx, MM_ERR_ARG, "E[%d] is NULL", k);
+    if (E[k]->rows != E[k]->cols || E[k]->cols != psi->dims[k])
+      return fail(ctx, MM_ERR_SHAPE, "E[%d] must be %lld x %lld", k, (long long)psi->dims[k], (long long)psi->dims[k]);
+    st = check_op_dtype(ctx, E[k], psi->dtype);
+    if (st != MM_OK) return st;
+  }
+  HIPCHK(ctx, hipSetDevice(ctx->device));
+  const double half = 0.5 * tau * beta, full = tau * beta;
+  for (int it = 0; it < nsteps; ++it) {
+    const double pre = (it == 0) ? half : 0.0;
+    const double post = (it + 1 < nsteps) ? full : half;
+    st = sweep(ctx, psi, E, pre, post, (hipStream_t)stream);
+    if (st != MM_OK) return st;
+  }
+  return MM_OK;
+}
+
+mm_status mm_norm2(mm_ctx ctx, const mm_tensor* T, double cell, double* host_out, mm_stream stream) {
+  if (!ctx) return MM_ERR_ARG;
+  mm_status st = check_tensor(ctx, T, "T");
+  if (st != MM_OK) return st;
+  if (!host_out) return fail(ctx, MM_ERR_ARG, "host_out is NULL");
+  HIPCHK(ctx, hipSetDevice(ctx->device));
+  hipStream_t s = (hipStream_t)stream;
+  const int64_t count = numel(T) * (is_complex(T->dtype) ? 2 : 1);
+  HIPCHK(ctx, mm::launch_norm2(T->data, count, is_f64(T->dtype) ? 1 : 0, ctx->red_partial, ctx->red_result, s));
+  HIPCHK(ctx, hipMemcpyAsync(ctx->host_result, ctx->red_result, sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPCHK(ctx, hipStreamSynchronize(s));
+  const double v = ctx->host_result[0] * cell;
+  *host_out = v;
+  if (!std::isfinite(v)) return fail(ctx, MM_ERR_NONFINITE, "norm is not finite");
+  return MM_OK;
+}
+
+}  // extern "C"
