@@ -1,0 +1,179 @@
+"""Benchmark of the mu-mode hot path on one MI355X.
+
+Workload: one Strang step of the 3-D cubic Gross-Pitaevskii equation
+i psi_t = -1/2 Laplace psi + 1/2 |x|^2 psi + beta |psi|^2 psi, beta = 100,
+n = 256 per direction on [-8, 8]^3 (homogeneous Dirichlet, second-order
+finite differences), tau = 1e-3, complex64 state, the three mu-mode products
+in split BF16x3 MFMA with FP32 accumulation, the nonlinear phase fused into
+the last product.  Synthetic seeded Thomas-Fermi-like initial state.
+
+Prints one JSON line.  The same step in plain FP64 (complex128 state, FP64
+MFMA) and in FP32 is timed beside it, the per-launch durations of the
+mode-product kernels come from HIP events recorded around each launch inside
+the timed region, and the FP64 CPU oracle is timed on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK = {  # MI355X published dense peaks
+    "bf16": 2516.6e12, "fp32": 157.3e12, "fp64": 78.6e12, "hbm": 8.0e12,
+}
+N, A, B, BETA, TAU, D = 256, -8.0, 8.0, 100.0, 1e-3, 3
+FLOPS_PER_PRODUCT = 8.0 * N * N ** D            # complex MAC = 8 flops, n per output entry
+FLOPS_PER_STEP = D * FLOPS_PER_PRODUCT
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def build_operator(mm):
+    x = np.linspace(A, B, N + 2)[1:-1]
+    H = -0.5 * mm.fd2_matrix(N, A, B) + np.diag(0.5 * x ** 2)
+    return mm.expm(H, -1j * TAU)
+
+
+def time_path(ctx, mm, torch, E, psi0_np, prec, steps, warmup, profile):
+    cdt = torch.complex128 if prec == "fp64" else torch.complex64
+    npdt = np.complex128 if prec == "fp64" else np.complex64
+    import synth
+    psi = torch.from_numpy(synth.to_device_layout(psi0_np.astype(npdt))).cuda()
+    op = ctx.mm_op_prepare(E, prec)
+    ops = [op] * D
+    if warmup > 0:
+        ctx.gpe_strang_step(psi, ops, TAU, BETA, warmup)
+    torch.cuda.synchronize()
+    if profile:
+        ctx.mm_profile_begin()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev0.record()
+    ctx.gpe_strang_step(psi, ops, TAU, BETA, steps)
+    ev1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = ev0.elapsed_time(ev1)
+    recs = ctx.mm_profile_end() if profile else []
+    op.destroy()
+    del psi
+    torch.cuda.empty_cache()
+    return ms / steps, wall, recs
+
+
+def cpu_baseline(psi0, nsteps):
+    from oracle import operators as op
+    from oracle import schemes as sc
+    E = op.ho_exponential(N, A, B, TAU)
+    p = psi0.astype(np.complex64).astype(np.complex128)
+    t0 = time.perf_counter()
+    out = sc.gpe_strang(p, [E] * D, TAU, BETA, nsteps)
+    dt = time.perf_counter() - t0
+    return nsteps / dt, dt, out, p
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--cpu-steps", type=int, default=4, help="oracle steps timed on the host (0: skip)")
+    ap.add_argument("--no-side-paths", action="store_true", help="skip the FP64 / FP32 comparison paths")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); this build has no multi-GPU path",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_2103_01691_amd as mm
+    import synth
+
+    log("building operator (host FP64 expm)")
+    E = build_operator(mm)
+    log("building initial state")
+    psi0 = synth.thomas_fermi_initial(N, A, B, D, BETA, cfg_id=4)
+    ctx = mm.Context(0)
+
+    log(f"timing split bf16x3: {args.warmup} warmup + {args.steps} steps")
+    ms, wall, recs = time_path(ctx, mm, torch, E, psi0, "bf16x3", args.steps, args.warmup, True)
+    prod_ms = [t for _, t in recs]
+    kinds = sorted(set(k for k, _ in recs))
+    per_kind = {str(k): float(np.mean([t for kk, t in recs if kk == k])) for k in kinds}
+    avg_launch_ms = float(np.mean(prod_ms)) if prod_ms else None
+    achieved = FLOPS_PER_PRODUCT / (avg_launch_ms * 1e-3) if avg_launch_ms else None
+
+    side = {}
+    if not args.no_side_paths:
+        for prec in ("fp64", "fp32"):
+            k = max(10, args.steps // 4)
+            log(f"timing {prec}: {k} steps")
+            pms, _, _ = time_path(ctx, mm, torch, E, psi0, prec, k, 5, False)
+            side[prec] = {"ms_per_step": pms, "steps_per_s": 1e3 / pms,
+                          "tflops_effective": FLOPS_PER_STEP / (pms * 1e-3) / 1e12}
+
+    # one GPU step vs the oracle on the identical cast input, plus the CPU baseline
+    cpu = None
+    parity = None
+    if args.cpu_steps > 0:
+        threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+        log(f"oracle: {args.cpu_steps} FP64 steps on the host ({threads} threads)")
+        sps, dt, ref, p0 = cpu_baseline(psi0, args.cpu_steps)
+        cpu = {"value": sps, "unit": "steps/s", "cores": threads, "kind": "oracle",
+               "sample": f"{args.cpu_steps} unmerged FP64 Strang steps of the full 256^3 GPE workload ({dt:.1f} s)"}
+        psi = torch.from_numpy(synth.to_device_layout(psi0.astype(np.complex64))).cuda()
+        op = ctx.mm_op_prepare(E, "bf16x3")
+        ctx.gpe_strang_step(psi, [op] * D, TAU, BETA, args.cpu_steps)
+        torch.cuda.synchronize()
+        got = synth.from_device_layout(psi.cpu().numpy()).astype(np.complex128)
+        parity = float(np.linalg.norm((got - ref).ravel()) / np.linalg.norm(ref.ravel()))
+        op.destroy()
+
+    out = {
+        "metric": "3D n=256 steps/s & achieved TFLOP/s: split-precision MFMA vs plain FP64",
+        "value": 1e3 / ms,
+        "unit": "steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "bf16x3",
+        "data": "synthetic",
+        "config": {"workload": "gpe3d_strang_n256_split_bf16x3", "d": D, "n": N, "beta": BETA, "tau": TAU,
+                   "domain": [A, B], "state": "complex64", "precision": "split_bf16x3_fp32acc",
+                   "parallelism": "single_gpu"},
+        "tflops_effective": FLOPS_PER_STEP / (ms * 1e-3) / 1e12,
+        "roofline": {
+            "bound": "mfma", "achieved": achieved / 1e12 if achieved else None, "peak": PEAK["bf16"] / 1e12,
+            "unit": "TFLOP/s", "frac": (achieved / PEAK["bf16"]) if achieved else None, "traffic": None,
+            "kernel": "mode_kernel (split BF16x3, complex 256x256 operator, one mu-mode product per launch)",
+            "avg_launch_ms": avg_launch_ms, "launches": len(prod_ms), "per_kind_ms": per_kind,
+            "executed_mfma_frac": (6 * achieved / PEAK["bf16"]) if achieved else None,
+        },
+        "paths": side,
+        "speedup_vs_fp64": (side["fp64"]["ms_per_step"] / ms) if "fp64" in side else None,
+        "parity_rel_l2_vs_oracle": parity,
+        "cpu_baseline": cpu,
+        "wall_s_timed": wall,
+    }
+    print(json.dumps(out), flush=True)
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()

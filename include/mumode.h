@@ -153,6 +153,19 @@ mm_status gpe_strang_step(mm_ctx ctx, mm_tensor* psi, const mm_op* E, double tau
  * synchronises `stream`.  Returns MM_ERR_NONFINITE if T holds NaN / Inf. */
 mm_status mm_norm2(mm_ctx ctx, const mm_tensor* T, double cell, double* host_out, mm_stream stream);
 
+/* ------------------------------------------------------------ timing ---- */
+
+/* Start recording a pair of HIP events around every mode-product kernel
+ * launch of this context (on the launch stream).  Clears earlier records. */
+mm_status mm_profile_begin(mm_ctx ctx);
+/* Stop recording, wait for the recorded events and return, per launch in
+ * issue order, a kernel kind code (prec*1000 + complex*100 + load*10 +
+ * prologue*2 + epilogue; load 0 = contiguous fibres, 1 = strided fibres,
+ * 2 = generic gather) and its duration in ms.  At most max_records entries
+ * are written to kinds / ms (either may be NULL); *count receives the total
+ * number of launches recorded. */
+mm_status mm_profile_end(mm_ctx ctx, int max_records, int* count, int* kinds, double* ms);
+
 /* ------------------------------------------ FP64 operator formation (host) */
 
 /* Second-order centred second difference h^-2 (1, -2, 1) on n nodes of

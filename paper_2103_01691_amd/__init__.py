@@ -205,3 +205,16 @@ class Context:
         self._chk(_lib.lib.mm_norm2(self.handle, C.byref(t), float(cell), C.byref(out), _stream(stream)),
                   "mm_norm2")
         return out.value
+
+    # --------------------------------------------------------- timing ----
+    def mm_profile_begin(self):
+        self._chk(_lib.lib.mm_profile_begin(self.handle), "mm_profile_begin")
+
+    def mm_profile_end(self, max_records: int = 1 << 16):
+        """Returns a list of (kind_code, ms) per recorded launch."""
+        n = C.c_int()
+        kinds = (C.c_int * max_records)()
+        ms = (C.c_double * max_records)()
+        self._chk(_lib.lib.mm_profile_end(self.handle, max_records, C.byref(n), kinds, ms), "mm_profile_end")
+        k = min(n.value, max_records)
+        return [(kinds[i], ms[i]) for i in range(k)]

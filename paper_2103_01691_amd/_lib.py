@@ -23,6 +23,7 @@ EXPORTS = [
     "mm_create", "mm_destroy", "mm_status_string", "mm_last_error", "mm_version",
     "mm_op_prepare", "mm_op_destroy", "mm_op_info",
     "mumode_apply", "mumode_expstep", "mumode_transform", "gpe_strang_step", "mm_norm2",
+    "mm_profile_begin", "mm_profile_end",
     "mm_fd2_matrix", "mm_expm", "mm_hermite_nodes", "mm_hermite_matrices",
 ]
 
@@ -62,6 +63,8 @@ def _load():
         "mumode_transform": (st, [P, C.POINTER(MMTensor), C.POINTER(MMTensor), C.POINTER(P), P]),
         "gpe_strang_step": (st, [P, C.POINTER(MMTensor), C.POINTER(P), d, d, C.c_int, P]),
         "mm_norm2": (st, [P, C.POINTER(MMTensor), d, C.POINTER(d), P]),
+        "mm_profile_begin": (st, [P]),
+        "mm_profile_end": (st, [P, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(d)]),
         "mm_fd2_matrix": (st, [C.c_int, d, d, C.c_int, C.POINTER(d)]),
         "mm_expm": (st, [C.c_int, C.POINTER(d), d, d, C.POINTER(d)]),
         "mm_hermite_nodes": (st, [C.c_int, C.POINTER(d), C.POINTER(d)]),

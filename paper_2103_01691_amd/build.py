@@ -1,6 +1,6 @@
 """Build libmumode.so (HIP kernels + C ABI runtime) in-tree for gfx950.
 
-Usage: python -m paper_2103_01691_amd.build   (or build() from Python).
+Usage: python paper_2103_01691_amd/build.py   (or __graft_entry__.build()).
 Every call recompiles every source.
 """
 from __future__ import annotations

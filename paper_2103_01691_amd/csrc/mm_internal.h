@@ -15,6 +15,7 @@ struct FragGeom {
   int MB, NB, KB, KPL, NPC;
 };
 FragGeom frag_geom(int prec);
+int split_variant();
 
 // Arguments of one mu-mode product launch (real-GEMM view, see
 // mode_kernels.hip).  Complex tensors: P, Q, n, m count complex entries.
@@ -33,6 +34,7 @@ struct ModeArgs {
 // Per-launch plan chosen by the runtime.
 struct ModePlan {
   int prec, cplx, load, pro, epi;
+  int variant;         // tile shape variant (split complex kernels)
   int grid_x, grid_y, threads;
   int mt_rows;         // real rows covered by one workgroup (multiple of MB)
   bool covers_all_rows;

@@ -37,6 +37,7 @@
 
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+#include <cstdlib>
 
 #include "mm_internal.h"
 
@@ -462,57 +463,75 @@ __global__ __launch_bounds__(64 * WAVES) void mode_kernel(ModeArgs a) {
 
 // Tile shapes per precision: WMF x WNF fragments per wave, WAVES waves
 // stacked along M, KCH K-blocks per LDS chunk.
-template <int PR> struct Cfg;
-template <> struct Cfg<KP_F64> { static constexpr int WMF = 8, WNF = 2, WAVES = 4, KCH = 8; };
-template <> struct Cfg<KP_F32> { static constexpr int WMF = 4, WNF = 2, WAVES = 4, KCH = 32; };
-template <> struct Cfg<KP_BF16X3> { static constexpr int WMF = 4, WNF = 2, WAVES = 4, KCH = 4; };
-template <> struct Cfg<KP_BF16> { static constexpr int WMF = 4, WNF = 2, WAVES = 4, KCH = 4; };
+template <int PR, int V = 0> struct Cfg;
+template <> struct Cfg<KP_F64, 0> { static constexpr int WMF = 8, WNF = 2, WAVES = 4, KCH = 8; };
+template <> struct Cfg<KP_F32, 0> { static constexpr int WMF = 4, WNF = 2, WAVES = 4, KCH = 32; };
+template <> struct Cfg<KP_BF16X3, 0> { static constexpr int WMF = 4, WNF = 2, WAVES = 4, KCH = 4; };
+template <> struct Cfg<KP_BF16, 0> { static constexpr int WMF = 4, WNF = 2, WAVES = 4, KCH = 4; };
+// alternative tile shapes of the split complex kernels (selected at run time)
+template <> struct Cfg<KP_BF16X3, 1> { static constexpr int WMF = 4, WNF = 4, WAVES = 4, KCH = 4; };
+template <> struct Cfg<KP_BF16X3, 2> { static constexpr int WMF = 4, WNF = 4, WAVES = 4, KCH = 2; };
+template <> struct Cfg<KP_BF16X3, 3> { static constexpr int WMF = 2, WNF = 2, WAVES = 8, KCH = 4; };
+constexpr int SPLIT_VARIANTS = 4;
 
 typedef void (*KernFn)(ModeArgs);
 
-template <int PR, bool CPLX, int LD, bool PRO, bool EPI>
-KernFn pick4() {
-  typedef Cfg<PR> C;
+template <int PR, bool CPLX, int LD, bool PRO, bool EPI, int V>
+KernFn pick5() {
+  typedef Cfg<PR, V> C;
   return &mode_kernel<PR, CPLX, LD, C::WMF, C::WNF, C::WAVES, C::KCH, PRO, EPI>;
 }
 
-template <int PR, bool CPLX, int LD>
-KernFn pick3(int pro, int epi) {
-  if constexpr (CPLX) {
-    if (pro && epi) return pick4<PR, CPLX, LD, true, true>();
-    if (pro) return pick4<PR, CPLX, LD, true, false>();
-    if (epi) return pick4<PR, CPLX, LD, false, true>();
+template <int PR, bool CPLX, int LD, bool PRO, bool EPI>
+KernFn pick4(int v) {
+  if constexpr (PR == KP_BF16X3 && CPLX && LD != KL_GENERIC) {
+    switch (v) {
+      case 1: return pick5<PR, CPLX, LD, PRO, EPI, 1>();
+      case 2: return pick5<PR, CPLX, LD, PRO, EPI, 2>();
+      case 3: return pick5<PR, CPLX, LD, PRO, EPI, 3>();
+      default: break;
+    }
   }
-  return pick4<PR, CPLX, LD, false, false>();
+  return pick5<PR, CPLX, LD, PRO, EPI, 0>();
+}
+
+template <int PR, bool CPLX, int LD>
+KernFn pick3(int pro, int epi, int v) {
+  if constexpr (CPLX) {
+    if (pro && epi) return pick4<PR, CPLX, LD, true, true>(v);
+    if (pro) return pick4<PR, CPLX, LD, true, false>(v);
+    if (epi) return pick4<PR, CPLX, LD, false, true>(v);
+  }
+  return pick4<PR, CPLX, LD, false, false>(v);
 }
 
 template <int PR, bool CPLX>
-KernFn pick2(int ld, int pro, int epi) {
+KernFn pick2(int ld, int pro, int epi, int v) {
   switch (ld) {
-    case KL_KCONTIG: return pick3<PR, CPLX, KL_KCONTIG>(pro, epi);
-    case KL_FCONTIG: return pick3<PR, CPLX, KL_FCONTIG>(pro, epi);
-    default: return pick3<PR, CPLX, KL_GENERIC>(pro, epi);
+    case KL_KCONTIG: return pick3<PR, CPLX, KL_KCONTIG>(pro, epi, v);
+    case KL_FCONTIG: return pick3<PR, CPLX, KL_FCONTIG>(pro, epi, v);
+    default: return pick3<PR, CPLX, KL_GENERIC>(pro, epi, v);
   }
 }
 
 template <int PR>
-KernFn pick1(int cplx, int ld, int pro, int epi) {
-  return cplx ? pick2<PR, true>(ld, pro, epi) : pick2<PR, false>(ld, pro, epi);
+KernFn pick1(int cplx, int ld, int pro, int epi, int v) {
+  return cplx ? pick2<PR, true>(ld, pro, epi, v) : pick2<PR, false>(ld, pro, epi, v);
 }
 
-KernFn pick(int prec, int cplx, int ld, int pro, int epi) {
+KernFn pick(int prec, int cplx, int ld, int pro, int epi, int v) {
   switch (prec) {
-    case KP_F64: return pick1<KP_F64>(cplx, ld, pro, epi);
-    case KP_F32: return pick1<KP_F32>(cplx, ld, pro, epi);
-    case KP_BF16X3: return pick1<KP_BF16X3>(cplx, ld, pro, epi);
-    default: return pick1<KP_BF16>(cplx, ld, pro, epi);
+    case KP_F64: return pick1<KP_F64>(cplx, ld, pro, epi, 0);
+    case KP_F32: return pick1<KP_F32>(cplx, ld, pro, epi, 0);
+    case KP_BF16X3: return pick1<KP_BF16X3>(cplx, ld, pro, epi, v);
+    default: return pick1<KP_BF16>(cplx, ld, pro, epi, 0);
   }
 }
 
-template <int PR> void cfg_of(int& wmf, int& wnf, int& waves) {
-  wmf = Cfg<PR>::WMF;
-  wnf = Cfg<PR>::WNF;
-  waves = Cfg<PR>::WAVES;
+template <int PR, int V> void cfg_of(int& wmf, int& wnf, int& waves) {
+  wmf = Cfg<PR, V>::WMF;
+  wnf = Cfg<PR, V>::WNF;
+  waves = Cfg<PR, V>::WAVES;
 }
 
 // -------------------------------------------------------- preparation -----
@@ -622,6 +641,17 @@ __global__ __launch_bounds__(NORM_THREADS) void norm_final_kernel(const double* 
 
 // ---------------------------------------------------------- host side -----
 
+// Tile variant of the split complex kernels: MUMODE_SPLIT_TILE=0..3
+// (read once; default 0).
+int split_variant() {
+  static int v = [] {
+    const char* e = std::getenv("MUMODE_SPLIT_TILE");
+    int x = e ? std::atoi(e) : 0;
+    return (x >= 0 && x < SPLIT_VARIANTS) ? x : 0;
+  }();
+  return v;
+}
+
 FragGeom frag_geom(int prec) {
   switch (prec) {
     case KP_F64: return {16, 16, 4, 1, 1};
@@ -641,19 +671,30 @@ size_t prepared_bytes(int prec, int KBT, int MFT) {
 bool plan_mode(const ModeArgs& a, int prec, int cplx, bool want_pro, bool want_epi, bool fcontig_ok,
                bool kcontig_ok, ModePlan* plan) {
   int wmf = 0, wnf = 0, waves = 0;
+  const int load = kcontig_ok ? KL_KCONTIG : (fcontig_ok ? KL_FCONTIG : KL_GENERIC);
+  int v = 0;
+  if (prec == KP_BF16X3 && cplx && load != KL_GENERIC) v = split_variant();
   switch (prec) {
-    case KP_F64: cfg_of<KP_F64>(wmf, wnf, waves); break;
-    case KP_F32: cfg_of<KP_F32>(wmf, wnf, waves); break;
-    case KP_BF16X3: cfg_of<KP_BF16X3>(wmf, wnf, waves); break;
-    default: cfg_of<KP_BF16>(wmf, wnf, waves); break;
+    case KP_F64: cfg_of<KP_F64, 0>(wmf, wnf, waves); break;
+    case KP_F32: cfg_of<KP_F32, 0>(wmf, wnf, waves); break;
+    case KP_BF16X3:
+      switch (v) {
+        case 1: cfg_of<KP_BF16X3, 1>(wmf, wnf, waves); break;
+        case 2: cfg_of<KP_BF16X3, 2>(wmf, wnf, waves); break;
+        case 3: cfg_of<KP_BF16X3, 3>(wmf, wnf, waves); break;
+        default: cfg_of<KP_BF16X3, 0>(wmf, wnf, waves); break;
+      }
+      break;
+    default: cfg_of<KP_BF16, 0>(wmf, wnf, waves); break;
   }
+  plan->variant = v;
   FragGeom g = frag_geom(prec);
   const int nt = wnf * g.NB;
   plan->prec = prec;
   plan->cplx = cplx;
   plan->pro = (want_pro && cplx) ? 1 : 0;
   plan->epi = (want_epi && cplx) ? 1 : 0;
-  plan->load = kcontig_ok ? KL_KCONTIG : (fcontig_ok ? KL_FCONTIG : KL_GENERIC);
+  plan->load = load;
   plan->threads = 64 * waves;
   plan->mt_rows = waves * wmf * g.MB;
   plan->grid_x = (int)((a.F + nt - 1) / nt);
@@ -663,7 +704,7 @@ bool plan_mode(const ModeArgs& a, int prec, int cplx, bool want_pro, bool want_e
 }
 
 hipError_t launch_mode(const ModePlan& p, const ModeArgs& a, hipStream_t s) {
-  KernFn fn = pick(p.prec, p.cplx, p.load, p.pro, p.epi);
+  KernFn fn = pick(p.prec, p.cplx, p.load, p.pro, p.epi, p.variant);
   dim3 grid(p.grid_x, p.grid_y, 1);
   hipLaunchKernelGGL(fn, grid, dim3(p.threads), 0, s, a);
   return hipGetLastError();

@@ -34,6 +34,10 @@ struct mm_ctx_s {
   double* red_partial = nullptr;
   double* red_result = nullptr;
   double* host_result = nullptr; // pinned
+  // optional per-launch timing (mm_profile_begin / mm_profile_end)
+  bool profiling = false;
+  struct Rec { int kind; hipEvent_t a, b; };
+  std::vector<Rec> recs;
 };
 
 namespace {
@@ -181,6 +185,17 @@ mm_status run_mode(mm_ctx ctx, const void* in, void* out, const int64_t* dims, i
     return fail(ctx, MM_ERR_UNSUPPORTED, "no kernel plan for this shape");
   if (plan_out) *plan_out = plan;
   if (dry) return MM_OK;
+  if (ctx->profiling) {
+    hipEvent_t e0, e1;
+    HIPCHK(ctx, hipEventCreate(&e0));
+    HIPCHK(ctx, hipEventCreate(&e1));
+    HIPCHK(ctx, hipEventRecord(e0, s));
+    HIPCHK(ctx, mm::launch_mode(plan, a, s));
+    HIPCHK(ctx, hipEventRecord(e1, s));
+    const int kind = plan.prec * 1000 + plan.cplx * 100 + plan.load * 10 + plan.pro * 2 + plan.epi;
+    ctx->recs.push_back({kind, e0, e1});
+    return MM_OK;
+  }
   HIPCHK(ctx, mm::launch_mode(plan, a, s));
   return MM_OK;
 }
@@ -299,6 +314,10 @@ mm_status mm_destroy(mm_ctx ctx) {
   hipSetDevice(ctx->device);
   hipDeviceSynchronize();
   while (!ctx->ops.empty()) mm_op_destroy(ctx, ctx->ops.back());
+  for (auto& r : ctx->recs) {
+    hipEventDestroy(r.a);
+    hipEventDestroy(r.b);
+  }
   if (ctx->ws) hipFree(ctx->ws);
   if (ctx->red_partial) hipFree(ctx->red_partial);
   if (ctx->red_result) hipFree(ctx->red_result);
@@ -498,6 +517,41 @@ mm_status gpe_strang_step(mm_ctx ctx, mm_tensor* psi, const mm_op* E, double tau
     st = sweep(ctx, psi, E, pre, post, (hipStream_t)stream);
     if (st != MM_OK) return st;
   }
+  return MM_OK;
+}
+
+mm_status mm_profile_begin(mm_ctx ctx) {
+  if (!ctx) return MM_ERR_ARG;
+  for (auto& r : ctx->recs) {
+    hipEventDestroy(r.a);
+    hipEventDestroy(r.b);
+  }
+  ctx->recs.clear();
+  ctx->profiling = true;
+  return MM_OK;
+}
+
+mm_status mm_profile_end(mm_ctx ctx, int max_records, int* count, int* kinds, double* ms) {
+  if (!ctx || !count) return MM_ERR_ARG;
+  ctx->profiling = false;
+  HIPCHK(ctx, hipSetDevice(ctx->device));
+  int n = 0;
+  for (auto& r : ctx->recs) {
+    HIPCHK(ctx, hipEventSynchronize(r.b));
+    if (n < max_records && kinds && ms) {
+      float t = 0.f;
+      HIPCHK(ctx, hipEventElapsedTime(&t, r.a, r.b));
+      kinds[n] = r.kind;
+      ms[n] = t;
+    }
+    ++n;
+  }
+  for (auto& r : ctx->recs) {
+    hipEventDestroy(r.a);
+    hipEventDestroy(r.b);
+  }
+  ctx->recs.clear();
+  *count = n;
   return MM_OK;
 }
 
