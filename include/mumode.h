@@ -149,6 +149,38 @@ mm_status mumode_transform(mm_ctx ctx, mm_tensor* out, const mm_tensor* in, cons
 mm_status gpe_strang_step(mm_ctx ctx, mm_tensor* psi, const mm_op* E, double tau, double beta,
                           int nsteps, mm_stream stream);
 
+/* Strang step for the harmonic oscillator with a time-dependent potential,
+ * i psi_t = -1/2 Laplace psi + 1/2 |x|^2 (1 + eps sin t) psi, in nodal
+ * Hermite space (Section 3; the Hermite part is exact, Section 4.3).  One
+ * step from t: P(t+tau/2, t+tau) L(tau) P(t, t+tau/2), where L(tau) =
+ * x_1 Lh[0] ... x_d Lh[d-1] with Lh[k] = Psi diag(exp(-i tau (j+1/2))) Phi
+ * (from mm_hermite_ho_exponential) and P(a,b) is the exact flow of the
+ * remainder, exp(-i (eps/2) |x|^2 (cos a - cos b)).  P is separable over
+ * the modes, so each step folds it into the operators as diagonal factors
+ * (re-prepared on the device every step) and needs no pointwise pass.
+ * nodes[k]: host array of the n_{k+1} Gauss-Hermite nodes of mode k+1.  psi
+ * is complex, updated in place; the caller advances t0 by nsteps*tau. */
+mm_status ho_strang_step(mm_ctx ctx, mm_tensor* psi, const mm_op* Lh, const double* const* nodes,
+                         double t0, double tau, double eps, int nsteps, mm_stream stream);
+
+/* Batched integrator: count independent instances, each
+ * T[i] <- T[i] x_1 E[i][0] ... x_{d_i} E[i][d_i - 1], nsteps times, in place.
+ * Instances may differ in d, dims, dtype (real / complex) and precision.  One
+ * step of the whole batch is a single HIP graph (captured on the first call
+ * with a given set of tensors and operators, replayed afterwards): for each
+ * mode, one grouped launch per kernel kind covers every instance's fibre
+ * tiles.  Requires every n_mu <= 256 (complex) / 512 (real) and P % 4 == 0
+ * for the strided modes (MM_ERR_UNSUPPORTED otherwise).  E[i] is an array of
+ * d_i operators (NULL entries leave the mode unchanged). */
+mm_status mumode_expstep_batched(mm_ctx ctx, int count, mm_tensor* const* T, const mm_op* const* E, int nsteps,
+                                 mm_stream stream);
+
+/* Discrete GPE energy cell * [Re sum conj(psi) (sum_mu psi x_mu H[mu-1])
+ * + (beta/2) sum |psi|^4], FP64 accumulation on the device; H[k] are the 1-D
+ * Hamiltonians prepared in psi's precision.  Synchronises `stream`. */
+mm_status mm_energy_gpe(mm_ctx ctx, const mm_tensor* psi, const mm_op* H, double beta, double cell,
+                        double* host_out, mm_stream stream);
+
 /* Discrete mass cell * sum |T|^2, accumulated in FP64 on the device;
  * synchronises `stream`.  Returns MM_ERR_NONFINITE if T holds NaN / Inf. */
 mm_status mm_norm2(mm_ctx ctx, const mm_tensor* T, double cell, double* host_out, mm_stream stream);
@@ -187,6 +219,11 @@ mm_status mm_hermite_nodes(int m, double* X, double* w);
  * forward Phi[k,l] = phi_k(X_l) w_l and backward Psi[l,k] = phi_k(X_l), both
  * m x m column-major real (either pointer may be NULL). */
 mm_status mm_hermite_matrices(int m, double* Phi, double* Psi);
+
+/* Collapsed exact harmonic-oscillator propagator in nodal Hermite space:
+ * out = Psi diag(exp(-i tau (k + 1/2))) Phi (m x m complex, column-major
+ * interleaved), Phi / Psi as in mm_hermite_matrices. */
+mm_status mm_hermite_ho_exponential(int m, double tau, double* out);
 
 #ifdef __cplusplus
 }

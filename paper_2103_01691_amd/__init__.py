@@ -74,6 +74,14 @@ def hermite_matrices(m: int):
     return np.asarray(Phi), np.asarray(Psi)
 
 
+def hermite_ho_exponential(m: int, tau: float) -> np.ndarray:
+    """Psi diag(exp(-i tau (k + 1/2))) Phi (exact HO propagator, nodal space)."""
+    out = np.zeros((m, m), dtype=np.complex128, order="F")
+    _check(_lib.lib.mm_hermite_ho_exponential(m, float(tau), out.ctypes.data_as(C.POINTER(C.c_double))),
+           "mm_hermite_ho_exponential")
+    return np.asarray(out)
+
+
 # -------------------------------------------------------------- tensors ----
 
 def _dtype_code(t) -> int:
@@ -198,6 +206,32 @@ class Context:
         self._chk(_lib.lib.gpe_strang_step(self.handle, C.byref(t), _op_array(E), float(tau), float(beta),
                                            nsteps, _stream(stream)), "gpe_strang_step")
         return psi
+
+    def mumode_expstep_batched(self, tensors, ops, nsteps: int = 1, stream=None):
+        """tensors: list of torch tensors; ops: list of per-instance op lists."""
+        n = len(tensors)
+        mts = [as_mm_tensor(t) for t in tensors]
+        tarr = (C.POINTER(_lib.MMTensor) * n)(*[C.pointer(m) for m in mts])
+        oarrs = [_op_array(o) for o in ops]
+        earr = (C.POINTER(C.c_void_p) * n)(*[C.cast(o, C.POINTER(C.c_void_p)) for o in oarrs])
+        self._chk(_lib.lib.mumode_expstep_batched(self.handle, n, tarr, earr, nsteps, _stream(stream)),
+                  "mumode_expstep_batched")
+        return tensors
+
+    def ho_strang_step(self, psi, Lh, nodes, t0: float, tau: float, eps: float, nsteps: int = 1, stream=None):
+        t = as_mm_tensor(psi)
+        keep = [np.ascontiguousarray(np.asarray(x, dtype=np.float64)) for x in nodes]
+        arr = (C.POINTER(C.c_double) * len(keep))(*[k.ctypes.data_as(C.POINTER(C.c_double)) for k in keep])
+        self._chk(_lib.lib.ho_strang_step(self.handle, C.byref(t), _op_array(Lh), arr, float(t0), float(tau),
+                                          float(eps), nsteps, _stream(stream)), "ho_strang_step")
+        return psi
+
+    def mm_energy_gpe(self, psi, H, beta: float, cell: float, stream=None) -> float:
+        t = as_mm_tensor(psi)
+        out = C.c_double()
+        self._chk(_lib.lib.mm_energy_gpe(self.handle, C.byref(t), _op_array(H), float(beta), float(cell),
+                                         C.byref(out), _stream(stream)), "mm_energy_gpe")
+        return out.value
 
     def mm_norm2(self, T, cell: float = 1.0, stream=None) -> float:
         t = as_mm_tensor(T)

@@ -23,7 +23,8 @@ EXPORTS = [
     "mm_create", "mm_destroy", "mm_status_string", "mm_last_error", "mm_version",
     "mm_op_prepare", "mm_op_destroy", "mm_op_info",
     "mumode_apply", "mumode_expstep", "mumode_transform", "gpe_strang_step", "mm_norm2",
-    "mm_profile_begin", "mm_profile_end",
+    "mm_profile_begin", "mm_profile_end", "ho_strang_step", "mm_energy_gpe", "mm_hermite_ho_exponential",
+    "mumode_expstep_batched",
     "mm_fd2_matrix", "mm_expm", "mm_hermite_nodes", "mm_hermite_matrices",
 ]
 
@@ -64,6 +65,10 @@ def _load():
         "gpe_strang_step": (st, [P, C.POINTER(MMTensor), C.POINTER(P), d, d, C.c_int, P]),
         "mm_norm2": (st, [P, C.POINTER(MMTensor), d, C.POINTER(d), P]),
         "mm_profile_begin": (st, [P]),
+        "ho_strang_step": (st, [P, C.POINTER(MMTensor), C.POINTER(P), C.POINTER(C.POINTER(d)), d, d, d, C.c_int, P]),
+        "mumode_expstep_batched": (st, [P, C.c_int, C.POINTER(C.POINTER(MMTensor)), C.POINTER(C.POINTER(P)), C.c_int, P]),
+        "mm_energy_gpe": (st, [P, C.POINTER(MMTensor), C.POINTER(P), d, d, C.POINTER(d), P]),
+        "mm_hermite_ho_exponential": (st, [C.c_int, d, C.POINTER(d)]),
         "mm_profile_end": (st, [P, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(d)]),
         "mm_fd2_matrix": (st, [C.c_int, d, d, C.c_int, C.POINTER(d)]),
         "mm_expm": (st, [C.c_int, C.POINTER(d), d, d, C.POINTER(d)]),

@@ -178,4 +178,25 @@ mm_status mm_hermite_matrices(int m, double* Phi, double* Psi) {
   return MM_OK;
 }
 
+mm_status mm_hermite_ho_exponential(int m, double tau, double* out) {
+  if (!out) return MM_ERR_ARG;
+  if (m < 1 || m > 4096) return MM_ERR_SHAPE;
+  if (!std::isfinite(tau)) return MM_ERR_ARG;
+  std::vector<double> Phi((size_t)m * m), Psi((size_t)m * m);
+  mm_status st = mm_hermite_matrices(m, Phi.data(), Psi.data());
+  if (st != MM_OK) return st;
+  // E = Psi diag(exp(-i tau (k + 1/2))) Phi: Hermite function k is an
+  // eigenfunction of -1/2 (d^2 - x^2) with eigenvalue k + 1/2 (Section 3)
+  std::vector<cd> ph(m);
+  for (int k = 0; k < m; ++k) ph[k] = std::exp(cd(0.0, -tau * (k + 0.5)));
+  for (int j = 0; j < m; ++j)
+    for (int i = 0; i < m; ++i) {
+      cd acc = 0.0;
+      for (int k = 0; k < m; ++k) acc += Psi[i + (size_t)k * m] * ph[k] * Phi[k + (size_t)j * m];
+      out[2 * (i + (size_t)j * m)] = acc.real();
+      out[2 * (i + (size_t)j * m) + 1] = acc.imag();
+    }
+  return MM_OK;
+}
+
 }  // extern "C"

@@ -1,0 +1,306 @@
+// Operator preparation, FP64 reductions and the host-side planning and
+// dispatch of the mu-mode product kernels (tables in kern_<prec>.hip).
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <atomic>
+#include <cstdlib>
+
+#include "mode_tile.h"
+
+namespace mm {
+namespace {
+
+// -------------------------------------------------------- preparation -----
+
+template <int PR>
+__global__ void prepare_kernel(const double* __restrict__ master, int64_t rows, int64_t cols,
+                               int64_t ld, int cplx, PhaseScale ph, void* __restrict__ outv, int KBT,
+                               int MFT) {
+  typedef Tr<PR> T;
+  typedef typename T::pc pc;
+  constexpr int MB = T::MB, KB = T::KB, KPL = T::KPL, NPC = T::NPC;
+  const int64_t slots = (int64_t)KBT * MFT * 64;   // (kb, mf, lane)
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= slots) return;
+  const int lane = (int)(s % 64);
+  const int64_t t = s / 64;
+  const int mf = (int)(t % MFT);
+  const int kb = (int)(t / MFT);
+  const int64_t Mr = cplx ? 2 * rows : rows;
+  const int64_t Kr = cplx ? 2 * cols : cols;
+  pc* out = (pc*)outv;
+  // physical fragment row -> logical row of the real block operator; the
+  // FP64 16x16 accumulator layout puts row lane/16 + 4r in register r, so
+  // its complex rows are permuted to keep (re, im) pairs in one lane
+  const int rho = lane % MB;
+  const int row = (PR == KP_F64 && cplx) ? 2 * (mf * 8 + (rho % 4) + 4 * (rho / 8)) + ((rho / 4) % 2)
+                                         : mf * MB + rho;
+  for (int e = 0; e < KPL; ++e) {
+    const int kap = kb * KB + KPL * (lane / MB) + e;
+    double x = 0.0;
+    if (row < Mr && kap < Kr) {
+      if (cplx) {
+        const int64_t i = row / 2, j = kap / 2;
+        const int cr = row & 1, ck = kap & 1;
+        double re = master[2 * (i + j * ld)], im = master[2 * (i + j * ld) + 1];
+        // L'[i,j] = exp(-i rc rx2[i]) L[i,j] exp(-i cc cx2[j])
+        double th = 0.0;
+        if (ph.rx2) th += ph.rc * ph.rx2[i];
+        if (ph.cx2) th += ph.cc * ph.cx2[j];
+        if (th != 0.0) {
+          double sn, cs;
+          sincos(th, &sn, &cs);
+          const double r2 = re * cs + im * sn;
+          im = im * cs - re * sn;
+          re = r2;
+        }
+        x = (cr == ck) ? re : (cr == 0 ? -im : im);
+      } else {
+        x = master[row + kap * ld];
+      }
+    }
+    const int64_t base = (((int64_t)kb * MFT + mf) * NPC) * 64 * KPL + lane * KPL + e;
+    if constexpr (PR == KP_F64) {
+      out[base] = x;
+    } else if constexpr (PR == KP_F32) {
+      out[base] = (float)x;
+    } else {
+      double r = x;
+#pragma unroll
+      for (int p = 0; p < NPC; ++p) {
+        __bf16 h = (__bf16)(float)r;
+        out[base + (int64_t)p * 64 * KPL] = h;
+        r = r - (double)(float)h;
+      }
+    }
+  }
+}
+
+// ------------------------------------------------------------- norm2 ------
+
+constexpr int NORM_BLOCKS = 1024;
+constexpr int NORM_THREADS = 256;
+
+template <typename S, int KIND>
+__global__ __launch_bounds__(NORM_THREADS) void reduce_partial_kernel(const S* __restrict__ x,
+                                                                      const S* __restrict__ y,
+                                                                      int64_t count,
+                                                                      double* __restrict__ partial) {
+  __shared__ double red[NORM_THREADS];
+  double acc = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * NORM_THREADS + threadIdx.x; i < count;
+       i += (int64_t)gridDim.x * NORM_THREADS) {
+    if constexpr (KIND == RED_SQ) {
+      const double v = (double)x[i];
+      acc += v * v;
+    } else if constexpr (KIND == RED_DOT_RE) {
+      acc += (double)x[2 * i] * (double)y[2 * i] + (double)x[2 * i + 1] * (double)y[2 * i + 1];
+    } else {
+      const double a2 = (double)x[2 * i] * (double)x[2 * i] + (double)x[2 * i + 1] * (double)x[2 * i + 1];
+      acc += a2 * a2;
+    }
+  }
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = NORM_THREADS / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+}
+
+__global__ __launch_bounds__(NORM_THREADS) void norm_final_kernel(const double* __restrict__ partial,
+                                                                  int nparts,
+                                                                  double* __restrict__ result) {
+  __shared__ double red[NORM_THREADS];
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < nparts; i += NORM_THREADS) acc += partial[i];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = NORM_THREADS / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) result[0] = red[0];
+}
+
+// ---------------------------------------------------------- host side -----
+
+std::atomic<int> g_split_cls{-2};   // -2: not read yet, -1: automatic
+
+int split_class() {
+  int v = g_split_cls.load();
+  if (v == -2) {
+    const char* e = std::getenv("MUMODE_SPLIT_TILE");
+    int x = e ? std::atoi(e) : 0;
+    v = (x >= 1 && x <= 3) ? x + 2 : (x == 4 ? 0 : -1);
+    g_split_cls.store(v);
+  }
+  return v;
+}
+
+KernFn pick_kernel_any(int prec, int cplx, int ld, int pro, int epi, int cls) {
+  switch (prec) {
+    case KP_F64: return pick_kernel_f64(cplx, ld, pro, epi, cls);
+    case KP_F32: return pick_kernel_f32(cplx, ld, pro, epi, cls);
+    case KP_BF16X3: return pick_kernel_bf16x3(cplx, ld, pro, epi, cls);
+    default: return pick_kernel_bf16(cplx, ld, pro, epi, cls);
+  }
+}
+
+BatchFn pick_batch_any(int prec, int cplx, int ld, int cls) {
+  switch (prec) {
+    case KP_F64: return pick_batch_f64(cplx, ld, cls);
+    case KP_F32: return pick_batch_f32(cplx, ld, cls);
+    case KP_BF16X3: return pick_batch_bf16x3(cplx, ld, cls);
+    default: return pick_batch_bf16(cplx, ld, cls);
+  }
+}
+
+}  // namespace
+
+void set_split_class(int cls) { g_split_cls.store((cls == 0 || (cls >= 3 && cls <= 5)) ? cls : -1); }
+
+bool tile_shape(int prec, int cls, TileShape* out) {
+  switch (prec) {
+    case KP_F64: return tile_shape_f64(cls, out);
+    case KP_F32: return tile_shape_f32(cls, out);
+    case KP_BF16X3: return tile_shape_bf16x3(cls, out);
+    default: return tile_shape_bf16(cls, out);
+  }
+}
+
+FragGeom frag_geom(int prec) {
+  switch (prec) {
+    case KP_F64: return {16, 16, 4, 1, 1, 8, 32};
+    case KP_F32: return {32, 32, 2, 1, 1, 32, 16};
+    case KP_BF16X3: return {32, 32, 16, 8, 3, 4, 16};
+    default: return {32, 32, 16, 8, 1, 4, 16};
+  }
+}
+
+void op_blocks(int prec, int64_t Mr, int64_t Kr, int* KBT, int* MFT) {
+  FragGeom g = frag_geom(prec);
+  const int64_t kb = (Kr + g.KB - 1) / g.KB;
+  const int64_t mf = (Mr + g.MB - 1) / g.MB;
+  *KBT = (int)((kb + g.KPAD - 1) / g.KPAD * g.KPAD);
+  *MFT = (int)((mf + g.MPAD - 1) / g.MPAD * g.MPAD);
+}
+
+size_t prepared_bytes(int prec, int KBT, int MFT) {
+  FragGeom g = frag_geom(prec);
+  size_t elems = (size_t)KBT * MFT * g.NPC * 64 * g.KPL;
+  size_t es = prec == KP_F64 ? 8 : prec == KP_F32 ? 4 : 2;
+  return elems * es;
+}
+
+bool plan_mode(const ModeArgs& a, int prec, int cplx, bool want_pro, bool want_epi, bool fcontig_ok,
+               bool kcontig_ok, ModePlan* plan) {
+  FragGeom g = frag_geom(prec);
+  const int load = kcontig_ok ? KL_KCONTIG : (fcontig_ok ? KL_FCONTIG : KL_GENERIC);
+  const int pro = (want_pro && cplx) ? 1 : 0;
+  const int epi = (want_epi && cplx) ? 1 : 0;
+  TileShape t0;
+  if (!tile_shape(prec, 0, &t0)) return false;
+  int cls = 0;
+  const int rw = t0.WMF * g.MB;                      // rows per wave
+  if (prec == KP_BF16X3 && cplx && load != KL_GENERIC && split_class() >= 0) {
+    cls = split_class();
+  } else if (prec == KP_BF16X3 && cplx && load != KL_GENERIC && a.Mr > 2 * rw) {
+    cls = 3;   // measured fastest for 256-long complex modes (4 x 128 rows, 128 fibres)
+  } else if (!pro && !epi && load != KL_GENERIC) {
+    if (a.Mr <= rw) cls = 2;
+    else if (a.Mr <= 2 * rw) cls = 1;
+  }
+  TileShape t;
+  if (!tile_shape(prec, cls, &t)) return false;
+  plan->prec = prec;
+  plan->cplx = cplx;
+  plan->load = load;
+  plan->pro = pro;
+  plan->epi = epi;
+  plan->cls = cls;
+  plan->nt = t.WN * t.WNF * g.NB;
+  plan->threads = 64 * t.WM * t.WN;
+  plan->mt_rows = t.WM * t.WMF * g.MB;
+  plan->grid_x = (int)((a.F + plan->nt - 1) / plan->nt);
+  const int mfr = (a.Mr + g.MB - 1) / g.MB;          // fragments holding real rows
+  plan->grid_y = (mfr + t.WM * t.WMF - 1) / (t.WM * t.WMF);
+  plan->covers_all_rows = plan->grid_y == 1;
+  return plan->grid_x > 0 && pick_kernel_any(prec, cplx, load, pro, epi, cls) != nullptr;
+}
+
+hipError_t launch_mode(const ModePlan& p, const ModeArgs& a, hipStream_t s) {
+  KernFn fn = pick_kernel_any(p.prec, p.cplx, p.load, p.pro, p.epi, p.cls);
+  if (!fn) return hipErrorInvalidDeviceFunction;
+  dim3 grid(p.grid_x, p.grid_y, 1);
+  hipLaunchKernelGGL(fn, grid, dim3(p.threads), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_mode_batch(const ModePlan& p, const BatchItem* items, int count, hipStream_t s) {
+  BatchFn fn = pick_batch_any(p.prec, p.cplx, p.load, p.cls);
+  if (!fn) return hipErrorInvalidDeviceFunction;
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(fn, dim3(count), dim3(p.threads), 0, s, items);
+  return hipGetLastError();
+}
+
+hipError_t launch_prepare(int prec, int cplx, const double* master, int64_t rows, int64_t cols,
+                          int64_t ld, PhaseScale ph, void* out, int KBT, int MFT, hipStream_t s) {
+  const int64_t slots = (int64_t)KBT * MFT * 64;
+  const int threads = 256;
+  const int blocks = (int)((slots + threads - 1) / threads);
+  switch (prec) {
+    case KP_F64:
+      hipLaunchKernelGGL(prepare_kernel<KP_F64>, dim3(blocks), dim3(threads), 0, s, master, rows,
+                         cols, ld, cplx, ph, out, KBT, MFT);
+      break;
+    case KP_F32:
+      hipLaunchKernelGGL(prepare_kernel<KP_F32>, dim3(blocks), dim3(threads), 0, s, master, rows,
+                         cols, ld, cplx, ph, out, KBT, MFT);
+      break;
+    case KP_BF16X3:
+      hipLaunchKernelGGL(prepare_kernel<KP_BF16X3>, dim3(blocks), dim3(threads), 0, s, master,
+                         rows, cols, ld, cplx, ph, out, KBT, MFT);
+      break;
+    default:
+      hipLaunchKernelGGL(prepare_kernel<KP_BF16>, dim3(blocks), dim3(threads), 0, s, master, rows,
+                         cols, ld, cplx, ph, out, KBT, MFT);
+      break;
+  }
+  return hipGetLastError();
+}
+
+int norm_partials() { return NORM_BLOCKS; }
+
+template <typename S>
+void reduce_dispatch(int kind, const void* x, const void* y, int64_t count, double* partial, hipStream_t s) {
+  const S* xs = (const S*)x;
+  const S* ys = (const S*)y;
+  switch (kind) {
+    case RED_SQ:
+      hipLaunchKernelGGL((reduce_partial_kernel<S, RED_SQ>), dim3(NORM_BLOCKS), dim3(NORM_THREADS), 0, s, xs, ys,
+                         count, partial);
+      break;
+    case RED_DOT_RE:
+      hipLaunchKernelGGL((reduce_partial_kernel<S, RED_DOT_RE>), dim3(NORM_BLOCKS), dim3(NORM_THREADS), 0, s, xs,
+                         ys, count, partial);
+      break;
+    default:
+      hipLaunchKernelGGL((reduce_partial_kernel<S, RED_ABS4>), dim3(NORM_BLOCKS), dim3(NORM_THREADS), 0, s, xs,
+                         ys, count, partial);
+      break;
+  }
+}
+
+hipError_t launch_reduce(int kind, const void* x, const void* y, int64_t count, int is_f64, double* partial,
+                         double* result, hipStream_t s) {
+  if (is_f64) reduce_dispatch<double>(kind, x, y, count, partial, s);
+  else reduce_dispatch<float>(kind, x, y, count, partial, s);
+  hipLaunchKernelGGL(norm_final_kernel, dim3(1), dim3(NORM_THREADS), 0, s, partial, NORM_BLOCKS, result);
+  return hipGetLastError();
+}
+
+}  // namespace mm

@@ -11,11 +11,16 @@ enum KLoad { KL_KCONTIG = 0, KL_FCONTIG = 1, KL_GENERIC = 2 };
 
 // Geometry of the MFMA fragment a precision uses: M rows and K values per
 // fragment, K values each lane holds, operator pieces per value.
+// KPAD / MPAD: the prepared operator's K-blocks and M-fragments are padded
+// (with zeros) to multiples of these, so that every tile shape reads whole
+// chunks and whole row tiles.
 struct FragGeom {
-  int MB, NB, KB, KPL, NPC;
+  int MB, NB, KB, KPL, NPC, KPAD, MPAD;
 };
 FragGeom frag_geom(int prec);
-int split_variant();
+// Padded K-block and M-fragment counts of a prepared operator with Mr real
+// rows and Kr real columns.
+void op_blocks(int prec, int64_t Mr, int64_t Kr, int* KBT, int* MFT);
 
 // Arguments of one mu-mode product launch (real-GEMM view, see
 // mode_kernels.hip).  Complex tensors: P, Q, n, m count complex entries.
@@ -26,16 +31,52 @@ struct ModeArgs {
   int64_t P, Q, F;     // fibres: F = P*Q, entry (p, j, q) at p + P*(j + n*q)
   int n, m;            // mode length of input / output
   int Kr, Mr;          // real-GEMM K and M (2n, 2m when complex)
-  int KBT, MFT;        // K-blocks and M-fragments of the prepared operator
+  int KBT, MFT;        // padded K-blocks and M-fragments of the prepared operator
   double s_pre;        // prologue phase: psi *= exp(-i s_pre |psi|^2) (0: off)
   double s_post;       // epilogue phase, same form
 };
 
+// Per-workgroup work item of a batched launch.
+struct BatchItem {
+  ModeArgs a;
+  int64_t tile_x;
+  int tile_y;
+  int pad_;
+};
+
+typedef void (*KernFn)(ModeArgs);
+typedef void (*BatchFn)(const BatchItem*);
+
+// Workgroup tile shape: WM x WN waves, each with WMF x WNF MFMA fragments,
+// KCH K-blocks per LDS chunk.
+struct TileShape {
+  int WMF, WNF, WM, WN, KCH;
+};
+
+// Kernel tables, one per precision (kern_<prec>.hip).  cls selects the tile
+// shape (0 default; 1, 2 regrouped waves for operators with at most 256 / 128
+// real rows; 3..5 alternative split shapes).  nullptr if no instance exists.
+KernFn pick_kernel_f64(int cplx, int ld, int pro, int epi, int cls);
+KernFn pick_kernel_f32(int cplx, int ld, int pro, int epi, int cls);
+KernFn pick_kernel_bf16x3(int cplx, int ld, int pro, int epi, int cls);
+KernFn pick_kernel_bf16(int cplx, int ld, int pro, int epi, int cls);
+BatchFn pick_batch_f64(int cplx, int ld, int cls);
+BatchFn pick_batch_f32(int cplx, int ld, int cls);
+BatchFn pick_batch_bf16x3(int cplx, int ld, int cls);
+BatchFn pick_batch_bf16(int cplx, int ld, int cls);
+bool tile_shape_f64(int cls, TileShape* out);
+bool tile_shape_f32(int cls, TileShape* out);
+bool tile_shape_bf16x3(int cls, TileShape* out);
+bool tile_shape_bf16(int cls, TileShape* out);
+
+bool tile_shape(int prec, int cls, TileShape* out);
+
 // Per-launch plan chosen by the runtime.
 struct ModePlan {
   int prec, cplx, load, pro, epi;
-  int variant;         // tile shape variant (split complex kernels)
+  int cls;             // tile shape class
   int grid_x, grid_y, threads;
+  int nt;              // fibres per workgroup
   int mt_rows;         // real rows covered by one workgroup (multiple of MB)
   bool covers_all_rows;
 };
@@ -44,19 +85,36 @@ struct ModePlan {
 bool plan_mode(const ModeArgs& a, int prec, int cplx, bool want_pro, bool want_epi,
                bool fcontig_ok, bool kcontig_ok, ModePlan* plan);
 hipError_t launch_mode(const ModePlan& plan, const ModeArgs& a, hipStream_t s);
+// Batched launch: `count` work items (device array) that all use `plan`'s
+// kernel (same precision, complexity, load path and tile class).
+hipError_t launch_mode_batch(const ModePlan& plan, const BatchItem* items, int count, hipStream_t s);
+// Force the tile class of split complex kernels (-1: automatic).  Also read
+// from MUMODE_SPLIT_TILE at first use.
+void set_split_class(int cls);
+
+// Optional diagonal phase scaling of a complex master before conversion:
+// L'[i,j] = exp(-i rc rx2[i]) L[i,j] exp(-i cc cx2[j]); rx2 / cx2 are device
+// arrays (null = no factor).
+struct PhaseScale {
+  const double* rx2 = nullptr;
+  double rc = 0.0;
+  const double* cx2 = nullptr;
+  double cc = 0.0;
+};
 
 // Convert an FP64 master (device, column-major, ld) into fragment order.
-// rowph / colph (device, complex FP64, may be null) scale row i / column j of
-// a complex master by the given unit-modulus factors before conversion.
 hipError_t launch_prepare(int prec, int cplx, const double* master, int64_t rows, int64_t cols,
-                          int64_t ld, const double* rowph, const double* colph, void* out,
-                          int KBT, int MFT, hipStream_t s);
+                          int64_t ld, PhaseScale ph, void* out, int KBT, int MFT, hipStream_t s);
 size_t prepared_bytes(int prec, int KBT, int MFT);
 
-// Two-pass deterministic FP64 sum of |x|^2 over `count` scalars (fp32 or
-// fp64).  partial: device buffer of >= norm_partials() doubles.
+// Two-pass deterministic FP64 reductions (fp32 or fp64 data):
+//   RED_SQ     sum x_k^2 over `count` scalars of x
+//   RED_DOT_RE sum Re(conj(x_k) y_k) over `count` complex entries
+//   RED_ABS4   sum |x_k|^4 over `count` complex entries
+// partial: device buffer of >= norm_partials() doubles.
+enum RedKind { RED_SQ = 0, RED_DOT_RE = 1, RED_ABS4 = 2 };
 int norm_partials();
-hipError_t launch_norm2(const void* x, int64_t count, int is_f64, double* partial,
-                        double* result, hipStream_t s);
+hipError_t launch_reduce(int kind, const void* x, const void* y, int64_t count, int is_f64,
+                         double* partial, double* result, hipStream_t s);
 
 }  // namespace mm

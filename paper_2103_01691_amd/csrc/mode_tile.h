@@ -35,14 +35,13 @@
 // integrated exactly) is applied to the loaded fibres (prologue) and/or to
 // the results (epilogue), so no separate pass over the state is needed.
 
+#pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
-#include <cstdlib>
 
 #include "mm_internal.h"
 
 namespace mm {
-namespace {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
@@ -123,6 +122,30 @@ __device__ __forceinline__ void split_bf16(float x, __bf16* p) {
   }
 }
 
+// sin and cos of an FP32 argument: Cody-Waite reduction by pi/2 with a
+// three-term split of pi/2 (each term the FP32 rounding of what remains of
+// the FP64 value), then the Taylor series of sin (to x^9) and cos (to x^10)
+// on |r| <= pi/4, whose truncation errors (< 2e-9, < 2e-10) are below FP32
+// rounding.  Accurate to a few ulp for |x| up to ~1e5; needs no scratch.
+__device__ __forceinline__ void sincos_f32(float x, float* s, float* c) {
+  constexpr double PIO2 = 1.57079632679489661923;
+  constexpr float P1 = (float)PIO2;
+  constexpr float P2 = (float)(PIO2 - (double)P1);
+  constexpr float P3 = (float)(PIO2 - (double)P1 - (double)P2);
+  const float q = rintf(x * (float)(1.0 / PIO2));
+  float r = fmaf(-q, P1, x);
+  r = fmaf(-q, P2, r);
+  r = fmaf(-q, P3, r);
+  const float r2 = r * r;
+  const float sp = r * (1.0f + r2 * (-1.0f / 6 + r2 * (1.0f / 120 + r2 * (-1.0f / 5040 + r2 * (1.0f / 362880)))));
+  const float cp = 1.0f + r2 * (-0.5f + r2 * (1.0f / 24 + r2 * (-1.0f / 720 + r2 * (1.0f / 40320 + r2 * (-1.0f / 3628800)))));
+  const int qi = ((int)q) & 3;
+  const float ss = (qi & 1) ? cp : sp;
+  const float cc = (qi & 1) ? sp : cp;
+  *s = (qi & 2) ? -ss : ss;
+  *c = ((qi + 1) & 2) ? -cc : cc;
+}
+
 // exp(-i s |z|^2) z
 template <typename T>
 __device__ __forceinline__ void phase(T& re, T& im, T s) {
@@ -131,7 +154,7 @@ __device__ __forceinline__ void phase(T& re, T& im, T s) {
   if constexpr (sizeof(T) == 8) {
     sincos(th, &sn, &cs);
   } else {
-    sincosf(th, &sn, &cs);
+    sincos_f32(th, &sn, &cs);
   }
   T r = re * cs + im * sn;
   T i = im * cs - re * sn;
@@ -153,30 +176,34 @@ __device__ __forceinline__ int64_t fibre_base(int64_t f, int64_t P, int n, int c
 
 // ------------------------------------------------------------- kernel -----
 
-template <int PR, bool CPLX, int LD, int WMF, int WNF, int WAVES, int KCH, bool PRO, bool EPI>
-__global__ __launch_bounds__(64 * WAVES) void mode_kernel(ModeArgs a) {
+// One workgroup tile: fibres [tile_x * NT, tile_x * NT + NT), M-fragments of
+// row block tile_y.  WM x WN waves: wave (wm, wn) owns M-fragments
+// [(tile_y*WM + wm)*WMF, +WMF) and N-fragments [wn*WNF, +WNF) of the tile.
+template <int PR, bool CPLX, int LD, int WMF, int WNF, int WM, int WN, int KCH, bool PRO, bool EPI>
+__device__ __forceinline__ void mode_tile(const ModeArgs& a, int64_t tile_x, int tile_y,
+                                          typename Tr<PR>::pc* __restrict__ lds) {
   typedef Tr<PR> T;
   typedef typename T::st st;
   typedef typename T::pc pc;
   typedef typename T::afrag afrag;
   typedef typename T::acc acc_t;
   constexpr int MB = T::MB, NB = T::NB, KB = T::KB, KPL = T::KPL, NPC = T::NPC;
-  constexpr int THREADS = 64 * WAVES;
-  constexpr int NT = WNF * NB;           // fibres per workgroup
-  constexpr int NFR = WNF;               // N-fragments per workgroup
+  constexpr int THREADS = 64 * WM * WN;
+  constexpr int NT = WN * WNF * NB;      // fibres per workgroup
+  constexpr int NFR = WN * WNF;          // N-fragments per workgroup
   constexpr int CK = KCH * KB;           // real K values per chunk
   constexpr int BLK = 64 * KPL;          // scalars per (kb, nf, piece) block
   constexpr int CHUNK = KCH * NFR * NPC * BLK;
   constexpr int COMPS = CPLX ? 2 : 1;
   typedef Prods<NPC> PP;
 
-  __shared__ __attribute__((aligned(16))) pc lds[2 * CHUNK];
-
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
-  const int64_t f0 = (int64_t)blockIdx.x * NT;
-  const int mf0 = (blockIdx.y * WAVES + wave) * WMF;   // first M-fragment of this wave
+  const int wm = wave % WM, wn = wave / WM;
+  const int64_t f0 = tile_x * NT;
+  const int mf0 = (tile_y * WM + wm) * WMF;   // first M-fragment of this wave
+  const int nf0 = wn * WNF;                   // first N-fragment of this wave
 
   const st* __restrict__ in = (const st*)a.in;
   const st s_pre = (st)a.s_pre;
@@ -355,7 +382,9 @@ __global__ __launch_bounds__(64 * WAVES) void mode_kernel(ModeArgs a) {
       for (int r = 0; r < T::NACC; ++r) acc[i][j][r] = 0;
 
   const afrag* __restrict__ Aop = (const afrag*)a.A;
-  const int nchunks = (a.KBT + KCH - 1) / KCH;
+  // the prepared operator is padded to a whole number of chunks (K) and of
+  // 512-row tiles (M), so the inner loop needs no bounds checks
+  const int nchunks = a.KBT / KCH;
 
   load_chunk(0);
   store_chunk(0);
@@ -368,22 +397,19 @@ __global__ __launch_bounds__(64 * WAVES) void mode_kernel(ModeArgs a) {
 #pragma unroll
     for (int kk = 0; kk < KCH; ++kk) {
       const int kbg = c * KCH + kk;           // global K-block
-      if (kbg < a.KBT) {
+      {
         afrag af[WMF][NPC];
 #pragma unroll
         for (int i = 0; i < WMF; ++i)
 #pragma unroll
-          for (int p = 0; p < NPC; ++p) {
-            const int mf = mf0 + i;
-            af[i][p] = (mf < a.MFT) ? Aop[(((int64_t)kbg * a.MFT + mf) * NPC + p) * 64 + lane]
-                                    : afrag{};
-          }
+          for (int p = 0; p < NPC; ++p)
+            af[i][p] = Aop[(((int64_t)kbg * a.MFT + mf0 + i) * NPC + p) * 64 + lane];
         afrag bfr[WNF][NPC];
 #pragma unroll
         for (int j = 0; j < WNF; ++j)
 #pragma unroll
           for (int p = 0; p < NPC; ++p) {
-            const pc* blk = L + ((kk * NFR + j) * NPC + p) * BLK;
+            const pc* blk = L + ((kk * NFR + nf0 + j) * NPC + p) * BLK;
             if constexpr (KPL == 8) {
               const int g = lane / NB, nn = lane % NB;
               bfr[j][p] = *(const afrag*)(blk + (g * NB + swz(nn, kk, g)) * 8);
@@ -411,33 +437,39 @@ __global__ __launch_bounds__(64 * WAVES) void mode_kernel(ModeArgs a) {
 #pragma unroll
   for (int i = 0; i < WMF; ++i) {
     const int mf = mf0 + i;
-    if (mf >= a.MFT) continue;
 #pragma unroll
     for (int j = 0; j < WNF; ++j) {
-      const int64_t fg = f0 + j * NB + (lane % NB);
+      const int64_t fg = f0 + (nf0 + j) * NB + (lane % NB);
       if (fg >= a.F) continue;
       const int64_t obase = (LD == KL_KCONTIG) ? fg * (int64_t)a.m * COMPS : fibre_base(fg, a.P, a.m, COMPS);
       const int64_t ostride = (LD == KL_KCONTIG) ? COMPS : a.P * COMPS;   // between entries i, i+1
-      // rows of this lane: groups of 4 consecutive rows
+      // Rows of this lane, in groups of four accumulator registers.
+      //  32x32 fragments: register 4q+r holds row 8q + 4(lane/32) + r.
+      //  16x16 FP64 fragments: register r holds row lane/16 + 4r; for complex
+      //  operators the prepared rows are permuted so that registers (0,1)
+      //  and (2,3) are (re, im) of entries mf*8 + lane/16 and that + 4.
       constexpr int GROUPS = T::NACC / 4;
 #pragma unroll
       for (int gq = 0; gq < GROUPS; ++gq) {
-        int row0;
-        if constexpr (MB == 32) row0 = mf * 32 + 8 * gq + 4 * (lane / 32);
-        else row0 = mf * 16 + 4 * (lane / 16);
         st v4[4];
 #pragma unroll
         for (int r = 0; r < 4; ++r) v4[r] = (st)acc[i][j][gq * 4 + r];
         if constexpr (CPLX) {
-          // rows row0..row0+3 = (re, im) of entries i0 = row0/2 and i0 + 1
-          const int i0 = row0 / 2;
+          int e0, e1;   // entries held as (v4[0], v4[1]) and (v4[2], v4[3])
+          if constexpr (MB == 32) {
+            e0 = (mf * 32 + 8 * gq + 4 * (lane / 32)) / 2;
+            e1 = e0 + 1;
+          } else {
+            e0 = mf * 8 + lane / 16;
+            e1 = e0 + 4;
+          }
           if constexpr (EPI) {
             phase<st>(v4[0], v4[1], s_post);
             phase<st>(v4[2], v4[3], s_post);
           }
 #pragma unroll
           for (int h = 0; h < 2; ++h) {
-            const int ie = i0 + h;
+            const int ie = h ? e1 : e0;
             if (ie < a.m) {
               st* dst = out + obase + (int64_t)ie * ostride;
               if constexpr (sizeof(st) == 4) {
@@ -450,7 +482,7 @@ __global__ __launch_bounds__(64 * WAVES) void mode_kernel(ModeArgs a) {
         } else {
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
-            const int ie = row0 + r;
+            const int ie = (MB == 32) ? mf * 32 + 8 * gq + 4 * (lane / 32) + r : mf * 16 + lane / 16 + 4 * r;
             if (ie < a.m) out[obase + (int64_t)ie * ostride] = v4[r];
           }
         }
@@ -459,297 +491,148 @@ __global__ __launch_bounds__(64 * WAVES) void mode_kernel(ModeArgs a) {
   }
 }
 
-// ------------------------------------------------------------ configs -----
-
-// Tile shapes per precision: WMF x WNF fragments per wave, WAVES waves
-// stacked along M, KCH K-blocks per LDS chunk.
-template <int PR, int V = 0> struct Cfg;
-template <> struct Cfg<KP_F64, 0> { static constexpr int WMF = 8, WNF = 2, WAVES = 4, KCH = 8; };
-template <> struct Cfg<KP_F32, 0> { static constexpr int WMF = 4, WNF = 2, WAVES = 4, KCH = 32; };
-template <> struct Cfg<KP_BF16X3, 0> { static constexpr int WMF = 4, WNF = 2, WAVES = 4, KCH = 4; };
-template <> struct Cfg<KP_BF16, 0> { static constexpr int WMF = 4, WNF = 2, WAVES = 4, KCH = 4; };
-// alternative tile shapes of the split complex kernels (selected at run time)
-template <> struct Cfg<KP_BF16X3, 1> { static constexpr int WMF = 4, WNF = 4, WAVES = 4, KCH = 4; };
-template <> struct Cfg<KP_BF16X3, 2> { static constexpr int WMF = 4, WNF = 4, WAVES = 4, KCH = 2; };
-template <> struct Cfg<KP_BF16X3, 3> { static constexpr int WMF = 2, WNF = 2, WAVES = 8, KCH = 4; };
-constexpr int SPLIT_VARIANTS = 4;
-
-typedef void (*KernFn)(ModeArgs);
-
-template <int PR, bool CPLX, int LD, bool PRO, bool EPI, int V>
-KernFn pick5() {
-  typedef Cfg<PR, V> C;
-  return &mode_kernel<PR, CPLX, LD, C::WMF, C::WNF, C::WAVES, C::KCH, PRO, EPI>;
+template <int PR, bool CPLX, int LD, int WMF, int WNF, int WM, int WN, int KCH, bool PRO, bool EPI>
+__global__ __launch_bounds__(64 * WM * WN) void mode_kernel(ModeArgs a) {
+  typedef typename Tr<PR>::pc pc;
+  constexpr int CHUNK = KCH * WN * WNF * Tr<PR>::NPC * 64 * Tr<PR>::KPL;
+  __shared__ __attribute__((aligned(16))) pc lds[2 * CHUNK];
+  mode_tile<PR, CPLX, LD, WMF, WNF, WM, WN, KCH, PRO, EPI>(a, blockIdx.x, blockIdx.y, lds);
 }
 
-template <int PR, bool CPLX, int LD, bool PRO, bool EPI>
-KernFn pick4(int v) {
-  if constexpr (PR == KP_BF16X3 && CPLX && LD != KL_GENERIC) {
-    switch (v) {
-      case 1: return pick5<PR, CPLX, LD, PRO, EPI, 1>();
-      case 2: return pick5<PR, CPLX, LD, PRO, EPI, 2>();
-      case 3: return pick5<PR, CPLX, LD, PRO, EPI, 3>();
+template <int PR, bool CPLX, int LD, int WMF, int WNF, int WM, int WN, int KCH>
+__global__ __launch_bounds__(64 * WM * WN) void mode_batch_kernel(const BatchItem* __restrict__ items) {
+  typedef typename Tr<PR>::pc pc;
+  constexpr int CHUNK = KCH * WN * WNF * Tr<PR>::NPC * 64 * Tr<PR>::KPL;
+  __shared__ __attribute__((aligned(16))) pc lds[2 * CHUNK];
+  const BatchItem& it = items[blockIdx.x];
+  const ModeArgs a = it.a;
+  mode_tile<PR, CPLX, LD, WMF, WNF, WM, WN, KCH, false, false>(a, it.tile_x, it.tile_y, lds);
+}
+
+// ------------------------------------------------------------ configs -----
+
+// Tile shapes: class 0 is the default (WM waves stacked along M cover up to
+// 512 real rows), classes 1 and 2 regroup the same waves 2 x 2 and 1 x 4 for
+// operators with at most 256 / 128 real rows, classes 3..5 are alternative
+// shapes of the split complex kernels.
+template <int PR, int CLS> struct Cfg;
+template <> struct Cfg<KP_F64, 0> { static constexpr int WMF = 8, WNF = 2, WM = 4, WN = 1, KCH = 8; };
+template <> struct Cfg<KP_F64, 1> { static constexpr int WMF = 8, WNF = 1, WM = 2, WN = 2, KCH = 8; };
+template <> struct Cfg<KP_F64, 2> { static constexpr int WMF = 8, WNF = 1, WM = 1, WN = 4, KCH = 8; };
+template <> struct Cfg<KP_F32, 0> { static constexpr int WMF = 4, WNF = 2, WM = 4, WN = 1, KCH = 32; };
+template <> struct Cfg<KP_F32, 1> { static constexpr int WMF = 4, WNF = 1, WM = 2, WN = 2, KCH = 32; };
+template <> struct Cfg<KP_F32, 2> { static constexpr int WMF = 4, WNF = 1, WM = 1, WN = 4, KCH = 32; };
+template <> struct Cfg<KP_BF16X3, 0> { static constexpr int WMF = 4, WNF = 2, WM = 4, WN = 1, KCH = 4; };
+template <> struct Cfg<KP_BF16X3, 1> { static constexpr int WMF = 4, WNF = 1, WM = 2, WN = 2, KCH = 4; };
+template <> struct Cfg<KP_BF16X3, 2> { static constexpr int WMF = 4, WNF = 1, WM = 1, WN = 4, KCH = 4; };
+template <> struct Cfg<KP_BF16X3, 3> { static constexpr int WMF = 4, WNF = 4, WM = 4, WN = 1, KCH = 4; };
+template <> struct Cfg<KP_BF16X3, 4> { static constexpr int WMF = 4, WNF = 4, WM = 4, WN = 1, KCH = 2; };
+template <> struct Cfg<KP_BF16X3, 5> { static constexpr int WMF = 2, WNF = 2, WM = 8, WN = 1, KCH = 4; };
+template <> struct Cfg<KP_BF16, 0> { static constexpr int WMF = 4, WNF = 2, WM = 4, WN = 1, KCH = 4; };
+template <> struct Cfg<KP_BF16, 1> { static constexpr int WMF = 4, WNF = 1, WM = 2, WN = 2, KCH = 4; };
+template <> struct Cfg<KP_BF16, 2> { static constexpr int WMF = 4, WNF = 1, WM = 1, WN = 4, KCH = 4; };
+
+template <int PR> struct NumCls { static constexpr int N = 3; };
+template <> struct NumCls<KP_BF16X3> { static constexpr int N = 6; };
+
+template <int PR, int CLS> TileShape shape_of() {
+  typedef Cfg<PR, CLS> C;
+  return TileShape{C::WMF, C::WNF, C::WM, C::WN, C::KCH};
+}
+
+template <int PR, bool CPLX, int LD, bool PRO, bool EPI, int CLS>
+KernFn kfn() {
+  typedef Cfg<PR, CLS> C;
+  return &mode_kernel<PR, CPLX, LD, C::WMF, C::WNF, C::WM, C::WN, C::KCH, PRO, EPI>;
+}
+
+template <int PR, bool CPLX, int LD, int CLS>
+BatchFn bfn() {
+  typedef Cfg<PR, CLS> C;
+  return &mode_batch_kernel<PR, CPLX, LD, C::WMF, C::WNF, C::WM, C::WN, C::KCH>;
+}
+
+// Kernel table of one precision.  Instances that exist: every (complex,
+// load, prologue, epilogue) in class 0; classes 1, 2 without phases and not
+// for the generic gather; classes >= 3 only for complex split kernels with
+// contiguous or strided fibres.
+template <int PR>
+KernFn pick_kernel(int cplx, int ld, int pro, int epi, int cls) {
+#define MM_PH(C_, L_, K_)                                                     \
+  do {                                                                        \
+    if (pro && epi) return kfn<PR, C_, L_, true, true, K_>();                \
+    if (pro) return kfn<PR, C_, L_, true, false, K_>();                      \
+    if (epi) return kfn<PR, C_, L_, false, true, K_>();                      \
+    return kfn<PR, C_, L_, false, false, K_>();                              \
+  } while (0)
+  if (cls == 1 || cls == 2) {
+    if (pro || epi || ld == KL_GENERIC) return nullptr;
+    if (cls == 1) {
+      if (cplx) return ld == KL_KCONTIG ? kfn<PR, true, KL_KCONTIG, false, false, 1>() : kfn<PR, true, KL_FCONTIG, false, false, 1>();
+      return ld == KL_KCONTIG ? kfn<PR, false, KL_KCONTIG, false, false, 1>() : kfn<PR, false, KL_FCONTIG, false, false, 1>();
+    }
+    if (cplx) return ld == KL_KCONTIG ? kfn<PR, true, KL_KCONTIG, false, false, 2>() : kfn<PR, true, KL_FCONTIG, false, false, 2>();
+    return ld == KL_KCONTIG ? kfn<PR, false, KL_KCONTIG, false, false, 2>() : kfn<PR, false, KL_FCONTIG, false, false, 2>();
+  }
+  if constexpr (NumCls<PR>::N > 3) {
+    if (cls >= 3) {
+      if (!cplx || ld == KL_GENERIC) return nullptr;
+      switch (cls) {
+        case 3: if (ld == KL_KCONTIG) MM_PH(true, KL_KCONTIG, 3); else MM_PH(true, KL_FCONTIG, 3);
+        case 4: if (ld == KL_KCONTIG) MM_PH(true, KL_KCONTIG, 4); else MM_PH(true, KL_FCONTIG, 4);
+        default: if (ld == KL_KCONTIG) MM_PH(true, KL_KCONTIG, 5); else MM_PH(true, KL_FCONTIG, 5);
+      }
+    }
+  }
+  if (cls != 0) return nullptr;
+  if (cplx) {
+    switch (ld) {
+      case KL_KCONTIG: MM_PH(true, KL_KCONTIG, 0);
+      case KL_FCONTIG: MM_PH(true, KL_FCONTIG, 0);
+      default: MM_PH(true, KL_GENERIC, 0);
+    }
+  }
+  switch (ld) {
+    case KL_KCONTIG: return kfn<PR, false, KL_KCONTIG, false, false, 0>();
+    case KL_FCONTIG: return kfn<PR, false, KL_FCONTIG, false, false, 0>();
+    default: return kfn<PR, false, KL_GENERIC, false, false, 0>();
+  }
+#undef MM_PH
+}
+
+template <int PR>
+BatchFn pick_batch(int cplx, int ld, int cls) {
+  if (ld == KL_GENERIC || cls > 2) return nullptr;
+#define MM_B(K_)                                                                      \
+  do {                                                                                \
+    if (cplx) return ld == KL_KCONTIG ? bfn<PR, true, KL_KCONTIG, K_>() : bfn<PR, true, KL_FCONTIG, K_>(); \
+    return ld == KL_KCONTIG ? bfn<PR, false, KL_KCONTIG, K_>() : bfn<PR, false, KL_FCONTIG, K_>();       \
+  } while (0)
+  switch (cls) {
+    case 0: MM_B(0);
+    case 1: MM_B(1);
+    default: MM_B(2);
+  }
+#undef MM_B
+}
+
+template <int PR>
+bool shape_table(int cls, TileShape* out) {
+  switch (cls) {
+    case 0: *out = shape_of<PR, 0>(); return true;
+    case 1: *out = shape_of<PR, 1>(); return true;
+    case 2: *out = shape_of<PR, 2>(); return true;
+    default: break;
+  }
+  if constexpr (NumCls<PR>::N > 3) {
+    switch (cls) {
+      case 3: *out = shape_of<PR, 3>(); return true;
+      case 4: *out = shape_of<PR, 4>(); return true;
+      case 5: *out = shape_of<PR, 5>(); return true;
       default: break;
     }
   }
-  return pick5<PR, CPLX, LD, PRO, EPI, 0>();
-}
-
-template <int PR, bool CPLX, int LD>
-KernFn pick3(int pro, int epi, int v) {
-  if constexpr (CPLX) {
-    if (pro && epi) return pick4<PR, CPLX, LD, true, true>(v);
-    if (pro) return pick4<PR, CPLX, LD, true, false>(v);
-    if (epi) return pick4<PR, CPLX, LD, false, true>(v);
-  }
-  return pick4<PR, CPLX, LD, false, false>(v);
-}
-
-template <int PR, bool CPLX>
-KernFn pick2(int ld, int pro, int epi, int v) {
-  switch (ld) {
-    case KL_KCONTIG: return pick3<PR, CPLX, KL_KCONTIG>(pro, epi, v);
-    case KL_FCONTIG: return pick3<PR, CPLX, KL_FCONTIG>(pro, epi, v);
-    default: return pick3<PR, CPLX, KL_GENERIC>(pro, epi, v);
-  }
-}
-
-template <int PR>
-KernFn pick1(int cplx, int ld, int pro, int epi, int v) {
-  return cplx ? pick2<PR, true>(ld, pro, epi, v) : pick2<PR, false>(ld, pro, epi, v);
-}
-
-KernFn pick(int prec, int cplx, int ld, int pro, int epi, int v) {
-  switch (prec) {
-    case KP_F64: return pick1<KP_F64>(cplx, ld, pro, epi, 0);
-    case KP_F32: return pick1<KP_F32>(cplx, ld, pro, epi, 0);
-    case KP_BF16X3: return pick1<KP_BF16X3>(cplx, ld, pro, epi, v);
-    default: return pick1<KP_BF16>(cplx, ld, pro, epi, 0);
-  }
-}
-
-template <int PR, int V> void cfg_of(int& wmf, int& wnf, int& waves) {
-  wmf = Cfg<PR, V>::WMF;
-  wnf = Cfg<PR, V>::WNF;
-  waves = Cfg<PR, V>::WAVES;
-}
-
-// -------------------------------------------------------- preparation -----
-
-template <int PR>
-__global__ void prepare_kernel(const double* __restrict__ master, int64_t rows, int64_t cols,
-                               int64_t ld, int cplx, const double* __restrict__ rowph,
-                               const double* __restrict__ colph, void* __restrict__ outv, int KBT,
-                               int MFT) {
-  typedef Tr<PR> T;
-  typedef typename T::pc pc;
-  constexpr int MB = T::MB, KB = T::KB, KPL = T::KPL, NPC = T::NPC;
-  const int64_t slots = (int64_t)KBT * MFT * 64;   // (kb, mf, lane)
-  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= slots) return;
-  const int lane = (int)(s % 64);
-  const int64_t t = s / 64;
-  const int mf = (int)(t % MFT);
-  const int kb = (int)(t / MFT);
-  const int64_t Mr = cplx ? 2 * rows : rows;
-  const int64_t Kr = cplx ? 2 * cols : cols;
-  pc* out = (pc*)outv;
-  const int row = mf * MB + (lane % MB);
-  for (int e = 0; e < KPL; ++e) {
-    const int kap = kb * KB + KPL * (lane / MB) + e;
-    double x = 0.0;
-    if (row < Mr && kap < Kr) {
-      if (cplx) {
-        const int64_t i = row / 2, j = kap / 2;
-        const int cr = row & 1, ck = kap & 1;
-        double re = master[2 * (i + j * ld)], im = master[2 * (i + j * ld) + 1];
-        if (rowph) {
-          const double pr = rowph[2 * i], pi = rowph[2 * i + 1];
-          const double r2 = re * pr - im * pi;
-          im = re * pi + im * pr;
-          re = r2;
-        }
-        if (colph) {
-          const double qr = colph[2 * j], qi = colph[2 * j + 1];
-          const double r2 = re * qr - im * qi;
-          im = re * qi + im * qr;
-          re = r2;
-        }
-        x = (cr == ck) ? re : (cr == 0 ? -im : im);
-      } else {
-        x = master[row + kap * ld];
-      }
-    }
-    const int64_t base = (((int64_t)kb * MFT + mf) * NPC) * 64 * KPL + lane * KPL + e;
-    if constexpr (PR == KP_F64) {
-      out[base] = x;
-    } else if constexpr (PR == KP_F32) {
-      out[base] = (float)x;
-    } else {
-      double r = x;
-#pragma unroll
-      for (int p = 0; p < NPC; ++p) {
-        __bf16 h = (__bf16)(float)r;
-        out[base + (int64_t)p * 64 * KPL] = h;
-        r = r - (double)(float)h;
-      }
-    }
-  }
-}
-
-// ------------------------------------------------------------- norm2 ------
-
-constexpr int NORM_BLOCKS = 1024;
-constexpr int NORM_THREADS = 256;
-
-template <typename S>
-__global__ __launch_bounds__(NORM_THREADS) void norm_partial_kernel(const S* __restrict__ x,
-                                                                    int64_t count,
-                                                                    double* __restrict__ partial) {
-  __shared__ double red[NORM_THREADS];
-  double acc = 0.0;
-  for (int64_t i = (int64_t)blockIdx.x * NORM_THREADS + threadIdx.x; i < count;
-       i += (int64_t)gridDim.x * NORM_THREADS) {
-    const double v = (double)x[i];
-    acc += v * v;
-  }
-  red[threadIdx.x] = acc;
-  __syncthreads();
-  for (int w = NORM_THREADS / 2; w > 0; w >>= 1) {
-    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
-}
-
-__global__ __launch_bounds__(NORM_THREADS) void norm_final_kernel(const double* __restrict__ partial,
-                                                                  int nparts,
-                                                                  double* __restrict__ result) {
-  __shared__ double red[NORM_THREADS];
-  double acc = 0.0;
-  for (int i = threadIdx.x; i < nparts; i += NORM_THREADS) acc += partial[i];
-  red[threadIdx.x] = acc;
-  __syncthreads();
-  for (int w = NORM_THREADS / 2; w > 0; w >>= 1) {
-    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) result[0] = red[0];
-}
-
-}  // namespace
-
-// ---------------------------------------------------------- host side -----
-
-// Tile variant of the split complex kernels: MUMODE_SPLIT_TILE=0..3
-// (read once; default 0).
-int split_variant() {
-  static int v = [] {
-    const char* e = std::getenv("MUMODE_SPLIT_TILE");
-    int x = e ? std::atoi(e) : 0;
-    return (x >= 0 && x < SPLIT_VARIANTS) ? x : 0;
-  }();
-  return v;
-}
-
-FragGeom frag_geom(int prec) {
-  switch (prec) {
-    case KP_F64: return {16, 16, 4, 1, 1};
-    case KP_F32: return {32, 32, 2, 1, 1};
-    case KP_BF16X3: return {32, 32, 16, 8, 3};
-    default: return {32, 32, 16, 8, 1};
-  }
-}
-
-size_t prepared_bytes(int prec, int KBT, int MFT) {
-  FragGeom g = frag_geom(prec);
-  size_t elems = (size_t)KBT * MFT * g.NPC * 64 * g.KPL;
-  size_t es = prec == KP_F64 ? 8 : prec == KP_F32 ? 4 : 2;
-  return elems * es;
-}
-
-bool plan_mode(const ModeArgs& a, int prec, int cplx, bool want_pro, bool want_epi, bool fcontig_ok,
-               bool kcontig_ok, ModePlan* plan) {
-  int wmf = 0, wnf = 0, waves = 0;
-  const int load = kcontig_ok ? KL_KCONTIG : (fcontig_ok ? KL_FCONTIG : KL_GENERIC);
-  int v = 0;
-  if (prec == KP_BF16X3 && cplx && load != KL_GENERIC) v = split_variant();
-  switch (prec) {
-    case KP_F64: cfg_of<KP_F64, 0>(wmf, wnf, waves); break;
-    case KP_F32: cfg_of<KP_F32, 0>(wmf, wnf, waves); break;
-    case KP_BF16X3:
-      switch (v) {
-        case 1: cfg_of<KP_BF16X3, 1>(wmf, wnf, waves); break;
-        case 2: cfg_of<KP_BF16X3, 2>(wmf, wnf, waves); break;
-        case 3: cfg_of<KP_BF16X3, 3>(wmf, wnf, waves); break;
-        default: cfg_of<KP_BF16X3, 0>(wmf, wnf, waves); break;
-      }
-      break;
-    default: cfg_of<KP_BF16, 0>(wmf, wnf, waves); break;
-  }
-  plan->variant = v;
-  FragGeom g = frag_geom(prec);
-  const int nt = wnf * g.NB;
-  plan->prec = prec;
-  plan->cplx = cplx;
-  plan->pro = (want_pro && cplx) ? 1 : 0;
-  plan->epi = (want_epi && cplx) ? 1 : 0;
-  plan->load = load;
-  plan->threads = 64 * waves;
-  plan->mt_rows = waves * wmf * g.MB;
-  plan->grid_x = (int)((a.F + nt - 1) / nt);
-  plan->grid_y = (a.MFT + waves * wmf - 1) / (waves * wmf);
-  plan->covers_all_rows = plan->grid_y == 1;
-  return plan->grid_x > 0 && (int64_t)plan->grid_x * nt >= a.F;
-}
-
-hipError_t launch_mode(const ModePlan& p, const ModeArgs& a, hipStream_t s) {
-  KernFn fn = pick(p.prec, p.cplx, p.load, p.pro, p.epi, p.variant);
-  dim3 grid(p.grid_x, p.grid_y, 1);
-  hipLaunchKernelGGL(fn, grid, dim3(p.threads), 0, s, a);
-  return hipGetLastError();
-}
-
-hipError_t launch_prepare(int prec, int cplx, const double* master, int64_t rows, int64_t cols,
-                          int64_t ld, const double* rowph, const double* colph, void* out, int KBT,
-                          int MFT, hipStream_t s) {
-  const int64_t slots = (int64_t)KBT * MFT * 64;
-  const int threads = 256;
-  const int blocks = (int)((slots + threads - 1) / threads);
-  switch (prec) {
-    case KP_F64:
-      hipLaunchKernelGGL(prepare_kernel<KP_F64>, dim3(blocks), dim3(threads), 0, s, master, rows,
-                         cols, ld, cplx, rowph, colph, out, KBT, MFT);
-      break;
-    case KP_F32:
-      hipLaunchKernelGGL(prepare_kernel<KP_F32>, dim3(blocks), dim3(threads), 0, s, master, rows,
-                         cols, ld, cplx, rowph, colph, out, KBT, MFT);
-      break;
-    case KP_BF16X3:
-      hipLaunchKernelGGL(prepare_kernel<KP_BF16X3>, dim3(blocks), dim3(threads), 0, s, master,
-                         rows, cols, ld, cplx, rowph, colph, out, KBT, MFT);
-      break;
-    default:
-      hipLaunchKernelGGL(prepare_kernel<KP_BF16>, dim3(blocks), dim3(threads), 0, s, master, rows,
-                         cols, ld, cplx, rowph, colph, out, KBT, MFT);
-      break;
-  }
-  return hipGetLastError();
-}
-
-int norm_partials() { return NORM_BLOCKS; }
-
-hipError_t launch_norm2(const void* x, int64_t count, int is_f64, double* partial, double* result,
-                        hipStream_t s) {
-  if (is_f64)
-    hipLaunchKernelGGL(norm_partial_kernel<double>, dim3(NORM_BLOCKS), dim3(NORM_THREADS), 0, s,
-                       (const double*)x, count, partial);
-  else
-    hipLaunchKernelGGL(norm_partial_kernel<float>, dim3(NORM_BLOCKS), dim3(NORM_THREADS), 0, s,
-                       (const float*)x, count, partial);
-  hipLaunchKernelGGL(norm_final_kernel, dim3(1), dim3(NORM_THREADS), 0, s, partial, NORM_BLOCKS,
-                     result);
-  return hipGetLastError();
+  return false;
 }
 
 }  // namespace mm

@@ -34,6 +34,20 @@ struct mm_ctx_s {
   double* red_partial = nullptr;
   double* red_result = nullptr;
   double* host_result = nullptr; // pinned
+  // per-mode scratch for operators re-prepared every step (ho_strang_step)
+  void* step_prep[MM_MAXD] = {nullptr};
+  size_t step_prep_bytes[MM_MAXD] = {0};
+  double* x2 = nullptr;          // squared node coordinates, MM_MAXD * 4096 doubles
+  // batched integrator: work items of the last batch signature, its
+  // launch groups and the captured per-step graph
+  struct BatchGroup { mm::ModePlan plan; int offset, count; };
+  mm::BatchItem* bitems = nullptr;
+  size_t bitems_cap = 0;
+  std::vector<BatchGroup> bgroups;
+  std::vector<uint64_t> bsig;
+  hipGraph_t bgraph = nullptr;
+  hipGraphExec_t bexec = nullptr;
+  hipStream_t cap_stream = nullptr;
   // optional per-launch timing (mm_profile_begin / mm_profile_end)
   bool profiling = false;
   struct Rec { int kind; hipEvent_t a, b; };
@@ -112,11 +126,10 @@ mm_status check_op_dtype(mm_ctx ctx, mm_op L, mm_dtype t) {
 // Prepare (or reuse) the fragment-order operator for a given complexity.
 mm_status ensure_prepared(mm_ctx ctx, mm_op L, bool cplx, hipStream_t s, void** prep, int* KBT, int* MFT) {
   const int kp = kprec(L->prec);
-  mm::FragGeom g = mm::frag_geom(kp);
   const int64_t Mr = cplx ? 2 * L->rows : L->rows;
   const int64_t Kr = cplx ? 2 * L->cols : L->cols;
-  const int kbt = (int)((Kr + g.KB - 1) / g.KB);
-  const int mft = (int)((Mr + g.MB - 1) / g.MB);
+  int kbt = 0, mft = 0;
+  mm::op_blocks(kp, Mr, Kr, &kbt, &mft);
   if (cplx == (bool)L->cplx) {
     *prep = L->prep;
     *KBT = L->KBT;
@@ -132,7 +145,7 @@ mm_status ensure_prepared(mm_ctx ctx, mm_op L, bool cplx, hipStream_t s, void** 
     HIPCHK(ctx, hipMalloc((void**)&L->dev_master_c, 2 * nn * sizeof(double)));
     HIPCHK(ctx, hipMemcpy(L->dev_master_c, cm.data(), 2 * nn * sizeof(double), hipMemcpyHostToDevice));
     HIPCHK(ctx, hipMalloc(&L->prep_c, mm::prepared_bytes(kp, kbt, mft)));
-    HIPCHK(ctx, mm::launch_prepare(kp, 1, L->dev_master_c, L->rows, L->cols, L->rows, nullptr, nullptr,
+    HIPCHK(ctx, mm::launch_prepare(kp, 1, L->dev_master_c, L->rows, L->cols, L->rows, mm::PhaseScale(),
                                    L->prep_c, kbt, mft, s));
     L->KBT_c = kbt;
     L->MFT_c = mft;
@@ -148,17 +161,19 @@ mm_status ensure_prepared(mm_ctx ctx, mm_op L, bool cplx, hipStream_t s, void** 
 // all rows in one workgroup (checked by the caller through *in_place_ok).
 mm_status run_mode(mm_ctx ctx, const void* in, void* out, const int64_t* dims, int d, mm_dtype dt,
                    mm_op L, int mu, double s_pre, double s_post, hipStream_t s, mm::ModePlan* plan_out,
-                   bool dry) {
+                   bool dry, const void* prep_override = nullptr) {
   const bool cplx = is_complex(dt);
   void* prep = nullptr;
   int KBT = 0, MFT = 0;
-  if (!dry) {
+  if (prep_override) {
+    prep = (void*)prep_override;
+    KBT = L->KBT;
+    MFT = L->MFT;
+  } else if (!dry) {
     mm_status st = ensure_prepared(ctx, L, cplx, s, &prep, &KBT, &MFT);
     if (st != MM_OK) return st;
   } else {
-    mm::FragGeom g = mm::frag_geom(kprec(L->prec));
-    KBT = (int)(((cplx ? 2 : 1) * L->cols + g.KB - 1) / g.KB);
-    MFT = (int)(((cplx ? 2 : 1) * L->rows + g.MB - 1) / g.MB);
+    mm::op_blocks(kprec(L->prec), (cplx ? 2 : 1) * L->rows, (cplx ? 2 : 1) * L->cols, &KBT, &MFT);
   }
   mm::ModeArgs a;
   int64_t P = 1, Q = 1;
@@ -319,6 +334,13 @@ mm_status mm_destroy(mm_ctx ctx) {
     hipEventDestroy(r.b);
   }
   if (ctx->ws) hipFree(ctx->ws);
+  for (int k = 0; k < MM_MAXD; ++k)
+    if (ctx->step_prep[k]) hipFree(ctx->step_prep[k]);
+  if (ctx->x2) hipFree(ctx->x2);
+  if (ctx->bexec) hipGraphExecDestroy(ctx->bexec);
+  if (ctx->bgraph) hipGraphDestroy(ctx->bgraph);
+  if (ctx->bitems) hipFree(ctx->bitems);
+  if (ctx->cap_stream) hipStreamDestroy(ctx->cap_stream);
   if (ctx->red_partial) hipFree(ctx->red_partial);
   if (ctx->red_result) hipFree(ctx->red_result);
   if (ctx->host_result) hipHostFree(ctx->host_result);
@@ -358,9 +380,7 @@ mm_status mm_op_prepare(mm_ctx ctx, const mm_matrix* M, mm_prec prec, mm_op* out
   op->cplx = cplx;
   op->prec = prec;
   const int kp = kprec(prec);
-  mm::FragGeom g = mm::frag_geom(kp);
-  op->KBT = (int)((comps * M->cols + g.KB - 1) / g.KB);
-  op->MFT = (int)((comps * M->rows + g.MB - 1) / g.MB);
+  mm::op_blocks(kp, comps * M->rows, comps * M->cols, &op->KBT, &op->MFT);
   if (hipMalloc((void**)&op->dev_master, host.size() * sizeof(double)) != hipSuccess ||
       hipMalloc(&op->prep, mm::prepared_bytes(kp, op->KBT, op->MFT)) != hipSuccess) {
     if (op->dev_master) hipFree(op->dev_master);
@@ -369,7 +389,7 @@ mm_status mm_op_prepare(mm_ctx ctx, const mm_matrix* M, mm_prec prec, mm_op* out
   }
   ctx->ops.push_back(op);
   HIPCHK(ctx, hipMemcpy(op->dev_master, host.data(), host.size() * sizeof(double), hipMemcpyHostToDevice));
-  HIPCHK(ctx, mm::launch_prepare(kp, cplx, op->dev_master, op->rows, op->cols, op->rows, nullptr, nullptr,
+  HIPCHK(ctx, mm::launch_prepare(kp, cplx, op->dev_master, op->rows, op->cols, op->rows, mm::PhaseScale(),
                                  op->prep, op->KBT, op->MFT, 0));
   HIPCHK(ctx, hipDeviceSynchronize());
   *out = op;
@@ -520,6 +540,257 @@ mm_status gpe_strang_step(mm_ctx ctx, mm_tensor* psi, const mm_op* E, double tau
   return MM_OK;
 }
 
+mm_status ho_strang_step(mm_ctx ctx, mm_tensor* psi, const mm_op* Lh, const double* const* nodes, double t0,
+                         double tau, double eps, int nsteps, mm_stream stream) {
+  if (!ctx) return MM_ERR_ARG;
+  mm_status st = check_tensor(ctx, psi, "psi");
+  if (st != MM_OK) return st;
+  if (!is_complex(psi->dtype)) return fail(ctx, MM_ERR_DTYPE, "psi must be complex");
+  if (!Lh || !nodes) return fail(ctx, MM_ERR_ARG, "Lh / nodes is NULL");
+  if (nsteps < 0) return fail(ctx, MM_ERR_ARG, "nsteps < 0");
+  if (!std::isfinite(t0) || !std::isfinite(tau) || !std::isfinite(eps)) return fail(ctx, MM_ERR_ARG, "t0 / tau / eps not finite");
+  for (int k = 0; k < psi->d; ++k) {
+    if (!Lh[k] || !nodes[k]) return fail(ctx, MM_ERR_ARG, "Lh[%d] / nodes[%d] is NULL", k, k);
+    if (!Lh[k]->cplx) return fail(ctx, MM_ERR_DTYPE, "Lh[%d] must be complex", k);
+    if (Lh[k]->rows != Lh[k]->cols || Lh[k]->cols != psi->dims[k])
+      return fail(ctx, MM_ERR_SHAPE, "Lh[%d] must be %lld x %lld", k, (long long)psi->dims[k], (long long)psi->dims[k]);
+    st = check_op_dtype(ctx, Lh[k], psi->dtype);
+    if (st != MM_OK) return st;
+  }
+  HIPCHK(ctx, hipSetDevice(ctx->device));
+  hipStream_t s = (hipStream_t)stream;
+  if (!ctx->x2) {
+    if (hipMalloc((void**)&ctx->x2, sizeof(double) * MM_MAXD * 4096) != hipSuccess)
+      return fail(ctx, MM_ERR_NOMEM, "node buffer");
+  }
+  std::vector<double> hx2((size_t)MM_MAXD * 4096, 0.0);
+  for (int k = 0; k < psi->d; ++k)
+    for (int64_t i = 0; i < psi->dims[k]; ++i) hx2[(size_t)k * 4096 + i] = nodes[k][i] * nodes[k][i];
+  HIPCHK(ctx, hipMemcpyAsync(ctx->x2, hx2.data(), sizeof(double) * psi->d * 4096, hipMemcpyHostToDevice, s));
+  HIPCHK(ctx, hipStreamSynchronize(s));
+  for (int k = 0; k < psi->d; ++k) {
+    const size_t need = mm::prepared_bytes(kprec(Lh[k]->prec), Lh[k]->KBT, Lh[k]->MFT);
+    if (ctx->step_prep_bytes[k] < need) {
+      if (ctx->step_prep[k]) {
+        HIPCHK(ctx, hipDeviceSynchronize());
+        HIPCHK(ctx, hipFree(ctx->step_prep[k]));
+        ctx->step_prep[k] = nullptr;
+        ctx->step_prep_bytes[k] = 0;
+      }
+      if (hipMalloc(&ctx->step_prep[k], need) != hipSuccess) return fail(ctx, MM_ERR_NOMEM, "step operator");
+      ctx->step_prep_bytes[k] = need;
+    }
+  }
+  const size_t bytes = (size_t)numel(psi) * dsize(psi->dtype);
+  for (int it = 0; it < nsteps; ++it) {
+    // exact flow of the potential part over [a, b]: exp(-i (eps/2) |x|^2 (cos a - cos b)),
+    // separable over the modes, folded into the operators as diagonal factors
+    const double t = t0 + it * tau;
+    const double cb = 0.5 * eps * (std::cos(t) - std::cos(t + 0.5 * tau));
+    const double ca = 0.5 * eps * (std::cos(t + 0.5 * tau) - std::cos(t + tau));
+    void* cur = psi->data;
+    for (int k = 0; k < psi->d; ++k) {
+      mm::PhaseScale ph;
+      ph.rx2 = ctx->x2 + (size_t)k * 4096;
+      ph.rc = ca;
+      ph.cx2 = ph.rx2;
+      ph.cc = cb;
+      HIPCHK(ctx, mm::launch_prepare(kprec(Lh[k]->prec), 1, Lh[k]->dev_master, Lh[k]->rows, Lh[k]->cols,
+                                     Lh[k]->rows, ph, ctx->step_prep[k], Lh[k]->KBT, Lh[k]->MFT, s));
+      mm::ModePlan plan;
+      st = run_mode(ctx, cur, cur, psi->dims, psi->d, psi->dtype, Lh[k], k + 1, 0, 0, s, &plan, true);
+      if (st != MM_OK) return st;
+      void* dst = cur;
+      if (!plan.covers_all_rows) {
+        st = ensure_ws(ctx, bytes);
+        if (st != MM_OK) return st;
+        dst = (cur == psi->data) ? ctx->ws : psi->data;
+      }
+      st = run_mode(ctx, cur, dst, psi->dims, psi->d, psi->dtype, Lh[k], k + 1, 0, 0, s, nullptr, false,
+                    ctx->step_prep[k]);
+      if (st != MM_OK) return st;
+      cur = dst;
+    }
+    if (cur != psi->data) HIPCHK(ctx, hipMemcpyAsync(psi->data, cur, bytes, hipMemcpyDeviceToDevice, s));
+  }
+  return MM_OK;
+}
+
+mm_status mumode_expstep_batched(mm_ctx ctx, int count, mm_tensor* const* T, const mm_op* const* E, int nsteps,
+                                 mm_stream stream) {
+  if (!ctx) return MM_ERR_ARG;
+  if (count < 0 || nsteps < 0) return fail(ctx, MM_ERR_ARG, "count / nsteps < 0");
+  if (count == 0 || nsteps == 0) return MM_OK;
+  if (!T || !E) return fail(ctx, MM_ERR_ARG, "T / E is NULL");
+  mm_status st;
+  for (int i = 0; i < count; ++i) {
+    char nm[32];
+    snprintf(nm, sizeof nm, "T[%d]", i);
+    st = check_tensor(ctx, T[i], nm);
+    if (st != MM_OK) return st;
+    if (!E[i]) return fail(ctx, MM_ERR_ARG, "E[%d] is NULL", i);
+    for (int k = 0; k < T[i]->d; ++k) {
+      mm_op L = E[i][k];
+      if (!L) continue;
+      if (L->rows != L->cols || L->cols != T[i]->dims[k])
+        return fail(ctx, MM_ERR_SHAPE, "E[%d][%d] must be %lld x %lld", i, k, (long long)T[i]->dims[k], (long long)T[i]->dims[k]);
+      st = check_op_dtype(ctx, L, T[i]->dtype);
+      if (st != MM_OK) return st;
+    }
+    for (int j = 0; j < i; ++j)
+      if (overlap(T[i], T[j])) return fail(ctx, MM_ERR_ARG, "T[%d] overlaps T[%d]", i, j);
+  }
+  HIPCHK(ctx, hipSetDevice(ctx->device));
+  hipStream_t s = (hipStream_t)stream;
+  // signature of the batch: tensors and operators
+  std::vector<uint64_t> sig;
+  sig.push_back((uint64_t)count);
+  for (int i = 0; i < count; ++i) {
+    sig.push_back((uint64_t)(uintptr_t)T[i]->data);
+    sig.push_back((uint64_t)T[i]->d * 16 + (uint64_t)T[i]->dtype);
+    for (int k = 0; k < T[i]->d; ++k) {
+      sig.push_back((uint64_t)T[i]->dims[k]);
+      sig.push_back((uint64_t)(uintptr_t)E[i][k]);
+    }
+  }
+  if (sig != ctx->bsig || !ctx->bexec) {
+    // build the work items: per mode, one group per kernel (precision,
+    // complexity, load path, tile class); every product runs in place
+    std::vector<mm::BatchItem> items;
+    std::vector<mm_ctx_s::BatchGroup> groups;
+    for (int k = 0; k < MM_MAXD; ++k) {
+      std::vector<std::pair<uint64_t, std::vector<mm::BatchItem>>> byk;
+      std::vector<mm::ModePlan> plans;
+      for (int i = 0; i < count; ++i) {
+        if (k >= T[i]->d || !E[i][k]) continue;
+        mm_op L = E[i][k];
+        mm::ModePlan plan;
+        st = run_mode(ctx, T[i]->data, T[i]->data, T[i]->dims, T[i]->d, T[i]->dtype, L, k + 1, 0, 0, s, &plan, true);
+        if (st != MM_OK) return st;
+        if (!plan.covers_all_rows || plan.load == mm::KL_GENERIC)
+          return fail(ctx, MM_ERR_UNSUPPORTED, "batched step needs n_mu <= 256 (complex) / 512 (real) and "
+                                               "aligned fibres (instance %d, mode %d)", i, k + 1);
+        void* prep = nullptr;
+        int KBT = 0, MFT = 0;
+        st = ensure_prepared(ctx, L, is_complex(T[i]->dtype), s, &prep, &KBT, &MFT);
+        if (st != MM_OK) return st;
+        mm::ModeArgs a;
+        int64_t P = 1, Q = 1;
+        for (int q = 0; q < k; ++q) P *= T[i]->dims[q];
+        for (int q = k + 1; q < T[i]->d; ++q) Q *= T[i]->dims[q];
+        const bool cplx = is_complex(T[i]->dtype);
+        a.in = T[i]->data;
+        a.out = T[i]->data;
+        a.A = prep;
+        a.P = P;
+        a.Q = Q;
+        a.F = P * Q;
+        a.n = (int)T[i]->dims[k];
+        a.m = (int)L->rows;
+        a.Kr = (cplx ? 2 : 1) * a.n;
+        a.Mr = (cplx ? 2 : 1) * a.m;
+        a.KBT = KBT;
+        a.MFT = MFT;
+        a.s_pre = 0.0;
+        a.s_post = 0.0;
+        const uint64_t key = (uint64_t)plan.prec * 1000 + plan.cplx * 100 + plan.load * 10 + plan.cls;
+        size_t g = 0;
+        while (g < byk.size() && byk[g].first != key) ++g;
+        if (g == byk.size()) {
+          byk.push_back({key, {}});
+          plans.push_back(plan);
+        }
+        for (int tx = 0; tx < plan.grid_x; ++tx) byk[g].second.push_back(mm::BatchItem{a, tx, 0, 0});
+      }
+      for (size_t g = 0; g < byk.size(); ++g) {
+        groups.push_back({plans[g], (int)items.size(), (int)byk[g].second.size()});
+        items.insert(items.end(), byk[g].second.begin(), byk[g].second.end());
+      }
+    }
+    if (items.size() > ctx->bitems_cap) {
+      if (ctx->bitems) {
+        HIPCHK(ctx, hipDeviceSynchronize());
+        HIPCHK(ctx, hipFree(ctx->bitems));
+        ctx->bitems = nullptr;
+        ctx->bitems_cap = 0;
+      }
+      if (hipMalloc((void**)&ctx->bitems, items.size() * sizeof(mm::BatchItem)) != hipSuccess)
+        return fail(ctx, MM_ERR_NOMEM, "batch work items");
+      ctx->bitems_cap = items.size();
+    }
+    HIPCHK(ctx, hipStreamSynchronize(s));
+    HIPCHK(ctx, hipMemcpy(ctx->bitems, items.data(), items.size() * sizeof(mm::BatchItem), hipMemcpyHostToDevice));
+    ctx->bgroups = groups;
+    // capture one step (all modes, all groups) as a graph
+    if (ctx->bexec) {
+      HIPCHK(ctx, hipGraphExecDestroy(ctx->bexec));
+      ctx->bexec = nullptr;
+    }
+    if (ctx->bgraph) {
+      HIPCHK(ctx, hipGraphDestroy(ctx->bgraph));
+      ctx->bgraph = nullptr;
+    }
+    ctx->bsig.clear();
+    if (!ctx->cap_stream) HIPCHK(ctx, hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking));
+    HIPCHK(ctx, hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal));
+    hipError_t le = hipSuccess;
+    for (const auto& g : ctx->bgroups) {
+      le = mm::launch_mode_batch(g.plan, ctx->bitems + g.offset, g.count, ctx->cap_stream);
+      if (le != hipSuccess) break;
+    }
+    hipGraph_t graph = nullptr;
+    hipError_t ce = hipStreamEndCapture(ctx->cap_stream, &graph);
+    if (le != hipSuccess || ce != hipSuccess) {
+      if (graph) hipGraphDestroy(graph);
+      return fail(ctx, MM_ERR_HIP, "graph capture failed: %s", hipGetErrorString(le != hipSuccess ? le : ce));
+    }
+    ctx->bgraph = graph;
+    HIPCHK(ctx, hipGraphInstantiate(&ctx->bexec, ctx->bgraph, nullptr, nullptr, 0));
+    ctx->bsig = sig;
+  }
+  for (int it = 0; it < nsteps; ++it) HIPCHK(ctx, hipGraphLaunch(ctx->bexec, s));
+  return MM_OK;
+}
+
+mm_status mm_energy_gpe(mm_ctx ctx, const mm_tensor* psi, const mm_op* H, double beta, double cell,
+                        double* host_out, mm_stream stream) {
+  if (!ctx) return MM_ERR_ARG;
+  mm_status st = check_tensor(ctx, psi, "psi");
+  if (st != MM_OK) return st;
+  if (!is_complex(psi->dtype)) return fail(ctx, MM_ERR_DTYPE, "psi must be complex");
+  if (!H || !host_out) return fail(ctx, MM_ERR_ARG, "H / host_out is NULL");
+  for (int k = 0; k < psi->d; ++k) {
+    if (!H[k]) return fail(ctx, MM_ERR_ARG, "H[%d] is NULL", k);
+    if (H[k]->rows != H[k]->cols || H[k]->cols != psi->dims[k])
+      return fail(ctx, MM_ERR_SHAPE, "H[%d] must be %lld x %lld", k, (long long)psi->dims[k], (long long)psi->dims[k]);
+    st = check_op_dtype(ctx, H[k], psi->dtype);
+    if (st != MM_OK) return st;
+  }
+  HIPCHK(ctx, hipSetDevice(ctx->device));
+  hipStream_t s = (hipStream_t)stream;
+  const size_t bytes = (size_t)numel(psi) * dsize(psi->dtype);
+  st = ensure_ws(ctx, bytes);
+  if (st != MM_OK) return st;
+  const int64_t count = numel(psi);
+  const int f64 = is_f64(psi->dtype) ? 1 : 0;
+  double total = 0.0;
+  for (int k = 0; k < psi->d; ++k) {
+    st = run_mode(ctx, psi->data, ctx->ws, psi->dims, psi->d, psi->dtype, H[k], k + 1, 0, 0, s, nullptr, false);
+    if (st != MM_OK) return st;
+    HIPCHK(ctx, mm::launch_reduce(mm::RED_DOT_RE, psi->data, ctx->ws, count, f64, ctx->red_partial, ctx->red_result, s));
+    HIPCHK(ctx, hipMemcpyAsync(ctx->host_result, ctx->red_result, sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(ctx, hipStreamSynchronize(s));
+    total += ctx->host_result[0];
+  }
+  HIPCHK(ctx, mm::launch_reduce(mm::RED_ABS4, psi->data, nullptr, count, f64, ctx->red_partial, ctx->red_result, s));
+  HIPCHK(ctx, hipMemcpyAsync(ctx->host_result, ctx->red_result, sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPCHK(ctx, hipStreamSynchronize(s));
+  const double e = cell * (total + 0.5 * beta * ctx->host_result[0]);
+  *host_out = e;
+  if (!std::isfinite(e)) return fail(ctx, MM_ERR_NONFINITE, "energy is not finite");
+  return MM_OK;
+}
+
 mm_status mm_profile_begin(mm_ctx ctx) {
   if (!ctx) return MM_ERR_ARG;
   for (auto& r : ctx->recs) {
@@ -563,7 +834,8 @@ mm_status mm_norm2(mm_ctx ctx, const mm_tensor* T, double cell, double* host_out
   HIPCHK(ctx, hipSetDevice(ctx->device));
   hipStream_t s = (hipStream_t)stream;
   const int64_t count = numel(T) * (is_complex(T->dtype) ? 2 : 1);
-  HIPCHK(ctx, mm::launch_norm2(T->data, count, is_f64(T->dtype) ? 1 : 0, ctx->red_partial, ctx->red_result, s));
+  HIPCHK(ctx, mm::launch_reduce(mm::RED_SQ, T->data, nullptr, count, is_f64(T->dtype) ? 1 : 0, ctx->red_partial,
+                                ctx->red_result, s));
   HIPCHK(ctx, hipMemcpyAsync(ctx->host_result, ctx->red_result, sizeof(double), hipMemcpyDeviceToHost, s));
   HIPCHK(ctx, hipStreamSynchronize(s));
   const double v = ctx->host_result[0] * cell;
