@@ -90,6 +90,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--cpu-steps", type=int, default=4, help="oracle steps timed on the host (0: skip)")
     ap.add_argument("--no-side-paths", action="store_true", help="skip the FP64 / FP32 comparison paths")
+    ap.add_argument("--calib-copy-mb", type=int, default=0,
+                    help="after timing, run one plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); this build has no multi-GPU path",
@@ -123,6 +125,17 @@ def main():
             pms, _, _ = time_path(ctx, mm, torch, E, psi0, prec, k, 5, False)
             side[prec] = {"ms_per_step": pms, "steps_per_s": 1e3 / pms,
                           "tflops_effective": FLOPS_PER_STEP / (pms * 1e-3) / 1e12}
+
+    if args.calib_copy_mb > 0:
+        # a plain copy kernel of known size: its FETCH_SIZE / WRITE_SIZE
+        # counters calibrate the HBM traffic counters of the product kernels
+        nbytes = args.calib_copy_mb << 20
+        src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     # one GPU step vs the oracle on the identical cast input, plus the CPU baseline
     cpu = None

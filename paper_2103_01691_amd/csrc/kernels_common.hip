@@ -196,7 +196,7 @@ size_t prepared_bytes(int prec, int KBT, int MFT) {
 }
 
 bool plan_mode(const ModeArgs& a, int prec, int cplx, bool want_pro, bool want_epi, bool fcontig_ok,
-               bool kcontig_ok, ModePlan* plan) {
+               bool kcontig_ok, ModePlan* plan, bool batch) {
   FragGeom g = frag_geom(prec);
   const int load = kcontig_ok ? KL_KCONTIG : (fcontig_ok ? KL_FCONTIG : KL_GENERIC);
   const int pro = (want_pro && cplx) ? 1 : 0;
@@ -205,10 +205,10 @@ bool plan_mode(const ModeArgs& a, int prec, int cplx, bool want_pro, bool want_e
   if (!tile_shape(prec, 0, &t0)) return false;
   int cls = 0;
   const int rw = t0.WMF * g.MB;                      // rows per wave
-  if (prec == KP_BF16X3 && cplx && load != KL_GENERIC && split_class() >= 0) {
+  if (!batch && prec == KP_BF16X3 && cplx && load != KL_GENERIC && split_class() >= 0) {
     cls = split_class();
-  } else if (prec == KP_BF16X3 && cplx && load != KL_GENERIC && a.Mr > 2 * rw) {
-    cls = 3;   // measured fastest for 256-long complex modes (4 x 128 rows, 128 fibres)
+  } else if (!batch && prec == KP_BF16X3 && cplx && load != KL_GENERIC && a.Mr > 2 * rw) {
+    cls = 4;   // 4 x 128 rows, 128 fibres, 2 K-blocks per chunk: fastest for 256-long complex modes
   } else if (!pro && !epi && load != KL_GENERIC) {
     if (a.Mr <= rw) cls = 2;
     else if (a.Mr <= 2 * rw) cls = 1;
@@ -228,6 +228,7 @@ bool plan_mode(const ModeArgs& a, int prec, int cplx, bool want_pro, bool want_e
   const int mfr = (a.Mr + g.MB - 1) / g.MB;          // fragments holding real rows
   plan->grid_y = (mfr + t.WM * t.WMF - 1) / (t.WM * t.WMF);
   plan->covers_all_rows = plan->grid_y == 1;
+  if (batch) return plan->grid_x > 0 && pick_batch_any(prec, cplx, load, cls) != nullptr;
   return plan->grid_x > 0 && pick_kernel_any(prec, cplx, load, pro, epi, cls) != nullptr;
 }
 

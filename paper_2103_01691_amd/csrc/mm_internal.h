@@ -82,8 +82,9 @@ struct ModePlan {
 };
 
 // Fill `plan` for the given problem; returns false if no kernel fits.
+// batch: plan for the batched work-list kernel (tile classes 0..2 only).
 bool plan_mode(const ModeArgs& a, int prec, int cplx, bool want_pro, bool want_epi,
-               bool fcontig_ok, bool kcontig_ok, ModePlan* plan);
+               bool fcontig_ok, bool kcontig_ok, ModePlan* plan, bool batch = false);
 hipError_t launch_mode(const ModePlan& plan, const ModeArgs& a, hipStream_t s);
 // Batched launch: `count` work items (device array) that all use `plan`'s
 // kernel (same precision, complexity, load path and tile class).

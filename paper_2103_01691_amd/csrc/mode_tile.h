@@ -386,44 +386,69 @@ __device__ __forceinline__ void mode_tile(const ModeArgs& a, int64_t tile_x, int
   // 512-row tiles (M), so the inner loop needs no bounds checks
   const int nchunks = a.KBT / KCH;
 
+  // Operator fragments of one K-block for this wave (from L2).  The wave's
+  // fragments of one K-block are contiguous: WMF * NPC blocks of 64 lanes.
+  const afrag* __restrict__ Aw = Aop + (int64_t)mf0 * NPC * 64 + lane;
+  const int64_t a_kstride = (int64_t)a.MFT * NPC * 64;
+  auto load_a = [&](int kbg, afrag (&dst)[WMF][NPC]) {
+    const afrag* src = Aw + kbg * a_kstride;
+#pragma unroll
+    for (int i = 0; i < WMF; ++i)
+#pragma unroll
+      for (int p = 0; p < NPC; ++p) dst[i][p] = src[(i * NPC + p) * 64];
+  };
+
   load_chunk(0);
   store_chunk(0);
   __syncthreads();
 
+  // B fragments of one K-block (local index kk of the LDS chunk) for this wave.
+  auto read_b = [&](const pc* L, int kk, afrag (&dst)[WNF][NPC]) {
+#pragma unroll
+    for (int j = 0; j < WNF; ++j)
+#pragma unroll
+      for (int p = 0; p < NPC; ++p) {
+        const pc* blk = L + ((kk * NFR + nf0 + j) * NPC + p) * BLK;
+        if constexpr (KPL == 8) {
+          const int g = lane / NB, nn = lane % NB;
+          dst[j][p] = *(const afrag*)(blk + (g * NB + swz(nn, kk, g)) * 8);
+        } else {
+          dst[j][p] = blk[lane];
+        }
+      }
+  };
+
+  // Software pipeline over K-blocks.  While the MFMAs of K-block kb run, the
+  // operator fragments of kb+1 (from L2) are already being loaded into the
+  // other half of a register double buffer.  The
+  // fibre tile of the next chunk is fetched from HBM at the start of the
+  // current chunk, right after the operator loads of the chunk's second
+  // K-block: vector-memory counters retire in order, so with two K-blocks per
+  // chunk no wait for an operator fragment ever waits for that (slower) HBM
+  // fetch, which has a whole chunk of MFMAs to arrive.
+  static_assert(KCH % 2 == 0, "K-blocks per chunk must be even (register double buffer)");
+  afrag a_buf[2][WMF][NPC];
+  load_a(0, a_buf[0]);
+  const int kb_last = a.KBT - 1;
   for (int c = 0; c < nchunks; ++c) {
     const int buf = c & 1;
-    if (c + 1 < nchunks) load_chunk(c + 1);   // global loads in flight during the MFMAs
     const pc* L = lds + buf * CHUNK;
 #pragma unroll
     for (int kk = 0; kk < KCH; ++kk) {
-      const int kbg = c * KCH + kk;           // global K-block
-      {
-        afrag af[WMF][NPC];
+      const int cur = kk & 1, nxt = cur ^ 1;
+      const int kbg = c * KCH + kk;   // global K-block
+      load_a(min(kbg + 1, kb_last), a_buf[nxt]);
+      if (kk == 0 && c + 1 < nchunks) load_chunk(c + 1);
+      afrag bfr[WNF][NPC];
+      read_b(L, kk, bfr);
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int k = 0; k < PP::N; ++k)
 #pragma unroll
         for (int i = 0; i < WMF; ++i)
 #pragma unroll
-          for (int p = 0; p < NPC; ++p)
-            af[i][p] = Aop[(((int64_t)kbg * a.MFT + mf0 + i) * NPC + p) * 64 + lane];
-        afrag bfr[WNF][NPC];
-#pragma unroll
-        for (int j = 0; j < WNF; ++j)
-#pragma unroll
-          for (int p = 0; p < NPC; ++p) {
-            const pc* blk = L + ((kk * NFR + nf0 + j) * NPC + p) * BLK;
-            if constexpr (KPL == 8) {
-              const int g = lane / NB, nn = lane % NB;
-              bfr[j][p] = *(const afrag*)(blk + (g * NB + swz(nn, kk, g)) * 8);
-            } else {
-              bfr[j][p] = blk[lane];
-            }
-          }
-#pragma unroll
-        for (int k = 0; k < PP::N; ++k)
-#pragma unroll
-          for (int i = 0; i < WMF; ++i)
-#pragma unroll
-            for (int j = 0; j < WNF; ++j) mfma(acc[i][j], af[i][PP::a(k)], bfr[j][PP::b(k)]);
-      }
+          for (int j = 0; j < WNF; ++j) mfma(acc[i][j], a_buf[cur][i][PP::a(k)], bfr[j][PP::b(k)]);
+      __builtin_amdgcn_sched_barrier(0);
     }
     if (c + 1 < nchunks) {
       store_chunk(buf ^ 1);

@@ -161,7 +161,7 @@ mm_status ensure_prepared(mm_ctx ctx, mm_op L, bool cplx, hipStream_t s, void** 
 // all rows in one workgroup (checked by the caller through *in_place_ok).
 mm_status run_mode(mm_ctx ctx, const void* in, void* out, const int64_t* dims, int d, mm_dtype dt,
                    mm_op L, int mu, double s_pre, double s_post, hipStream_t s, mm::ModePlan* plan_out,
-                   bool dry, const void* prep_override = nullptr) {
+                   bool dry, const void* prep_override = nullptr, bool batch = false) {
   const bool cplx = is_complex(dt);
   void* prep = nullptr;
   int KBT = 0, MFT = 0;
@@ -196,7 +196,7 @@ mm_status run_mode(mm_ctx ctx, const void* in, void* out, const int64_t* dims, i
   const bool kcontig = (P == 1) && (a.Kr % 8 == 0);
   const bool fcontig = (P % 4 == 0);
   mm::ModePlan plan;
-  if (!mm::plan_mode(a, kprec(L->prec), cplx ? 1 : 0, s_pre != 0.0, s_post != 0.0, fcontig, kcontig, &plan))
+  if (!mm::plan_mode(a, kprec(L->prec), cplx ? 1 : 0, s_pre != 0.0, s_post != 0.0, fcontig, kcontig, &plan, batch))
     return fail(ctx, MM_ERR_UNSUPPORTED, "no kernel plan for this shape");
   if (plan_out) *plan_out = plan;
   if (dry) return MM_OK;
@@ -665,7 +665,8 @@ mm_status mumode_expstep_batched(mm_ctx ctx, int count, mm_tensor* const* T, con
         if (k >= T[i]->d || !E[i][k]) continue;
         mm_op L = E[i][k];
         mm::ModePlan plan;
-        st = run_mode(ctx, T[i]->data, T[i]->data, T[i]->dims, T[i]->d, T[i]->dtype, L, k + 1, 0, 0, s, &plan, true);
+        st = run_mode(ctx, T[i]->data, T[i]->data, T[i]->dims, T[i]->d, T[i]->dtype, L, k + 1, 0, 0, s, &plan, true,
+                      nullptr, true);
         if (st != MM_OK) return st;
         if (!plan.covers_all_rows || plan.load == mm::KL_GENERIC)
           return fail(ctx, MM_ERR_UNSUPPORTED, "batched step needs n_mu <= 256 (complex) / 512 (real) and "
