@@ -97,12 +97,14 @@ template <> struct Prods<1> {
   static constexpr int N = 1;
   __device__ static constexpr int a(int) { return 0; }
   __device__ static constexpr int b(int) { return 0; }
+  __device__ static constexpr int last_a(int) { return 0; }   // last product using operator piece p
 };
 template <> struct Prods<3> {
   static constexpr int N = 6;
   // (0,0) (0,1) (1,0) (0,2) (1,1) (2,0)
   __device__ static constexpr int a(int k) { return k == 2 ? 1 : k == 4 ? 1 : k == 5 ? 2 : 0; }
   __device__ static constexpr int b(int k) { return k == 1 ? 1 : k == 3 ? 2 : k == 4 ? 1 : 0; }
+  __device__ static constexpr int last_a(int p) { return p == 0 ? 3 : p == 1 ? 4 : 5; }
 };
 
 // Split a float into NPC round-to-nearest-even bfloat16 pieces.  Each
@@ -179,7 +181,8 @@ __device__ __forceinline__ int64_t fibre_base(int64_t f, int64_t P, int n, int c
 // One workgroup tile: fibres [tile_x * NT, tile_x * NT + NT), M-fragments of
 // row block tile_y.  WM x WN waves: wave (wm, wn) owns M-fragments
 // [(tile_y*WM + wm)*WMF, +WMF) and N-fragments [wn*WNF, +WNF) of the tile.
-template <int PR, bool CPLX, int LD, int WMF, int WNF, int WM, int WN, int KCH, bool PRO, bool EPI>
+template <int PR, bool CPLX, int LD, int WMF, int WNF, int WM, int WN, int KCH, bool PRO, bool EPI,
+          bool ILV = false>
 __device__ __forceinline__ void mode_tile(const ModeArgs& a, int64_t tile_x, int tile_y,
                                           typename Tr<PR>::pc* __restrict__ lds) {
   typedef Tr<PR> T;
@@ -231,21 +234,40 @@ __device__ __forceinline__ void mode_tile(const ModeArgs& a, int64_t tile_x, int
     }
   };
 
+  // Per-tile source pointers of chunk 0 and fibre validity, computed once:
+  // chunk c of a tile starts CSTRIDE * c scalars further on.
+  constexpr bool FAST = LD != KL_GENERIC;
+  const st* tsrc[TPT];
+  bool tok[TPT];
+  int tkl[TPT];   // first local real K of the tile within a chunk
+#pragma unroll
+  for (int u = 0; u < TPT; ++u) {
+    int tk, tf;
+    tile_coords(tid + u * THREADS, tk, tf);
+    const int64_t fg = f0 + (int64_t)tf * TF;
+    tok[u] = (TILES >= THREADS || tid < TILES) && fg < a.F;
+    tkl[u] = tk * TK;
+    if constexpr (LD == KL_KCONTIG) {
+      tsrc[u] = in + (tok[u] ? fg * (int64_t)a.Kr + tk * TK : 0);
+    } else if constexpr (LD == KL_FCONTIG) {
+      tsrc[u] = in + (tok[u] ? fibre_base(fg, a.P, a.n, COMPS) + (int64_t)(tk * TK / COMPS) * a.P * COMPS : 0);
+    } else {
+      tsrc[u] = in;
+    }
+  }
+  const int64_t cstride = (LD == KL_KCONTIG) ? (int64_t)CK : (int64_t)CK * a.P;
+
   // Load chunk `c` (real K values [c*CK, c*CK + CK)) into registers.
   auto load_chunk = [&](int c) {
+    const int klim = a.Kr - c * CK;   // local K values of this chunk that exist
 #pragma unroll
     for (int u = 0; u < TPT; ++u) {
       if (TILES < THREADS && tid >= TILES) break;
-      int tk, tf;
-      tile_coords(tid + u * THREADS, tk, tf);
-      const int k0 = c * CK + tk * TK;       // first real K of the tile
-      const int64_t fl = (int64_t)tf * TF;   // first local fibre
-      const int64_t fg = f0 + fl;
       st* v = stage[u];
       if constexpr (LD == KL_KCONTIG) {
-        // P == 1: fibre fg's K values are contiguous; TK of them, vectorised.
-        if (fg < a.F && k0 < a.Kr) {
-          const st* src = in + fg * (int64_t)a.Kr + k0;
+        // P == 1: fibre's K values are contiguous; TK of them, vectorised.
+        if (tok[u] && tkl[u] < klim) {
+          const st* src = tsrc[u] + c * cstride;
 #pragma unroll
           for (int w = 0; w < TK / VL; ++w) {
             if constexpr (sizeof(st) == 4) {
@@ -265,14 +287,12 @@ __device__ __forceinline__ void mode_tile(const ModeArgs& a, int64_t tile_x, int
       } else if constexpr (LD == KL_FCONTIG) {
         // Fibres contiguous: one 16-byte vector holds TF fibres at one row j.
         constexpr int ROWS = CPLX ? TK / 2 : TK;
-        const int64_t base = (fg < a.F) ? fibre_base(fg, a.P, a.n, COMPS) : 0;
-        const int j0 = CPLX ? k0 / 2 : k0;
+        const st* src0 = tsrc[u] + c * cstride;
 #pragma unroll
         for (int r = 0; r < ROWS; ++r) {
-          const int j = j0 + r;
           st xv[VL];
-          if (fg < a.F && j < a.n) {
-            const st* src = in + base + (int64_t)j * a.P * COMPS;
+          if (tok[u] && tkl[u] + r * COMPS < klim) {
+            const st* src = src0 + (int64_t)r * a.P * COMPS;
             if constexpr (sizeof(st) == 4) {
               f32x4 x = *(const f32x4*)src;
 #pragma unroll
@@ -296,6 +316,10 @@ __device__ __forceinline__ void mode_tile(const ModeArgs& a, int64_t tile_x, int
         }
       } else {
         // Generic gather: one fibre, TK real K values, scalar / pair loads.
+        int tk, tf;
+        tile_coords(tid + u * THREADS, tk, tf);
+        const int k0 = c * CK + tk * TK;
+        const int64_t fg = f0 + (int64_t)tf * TF;
         const bool fok = fg < a.F;
         const int64_t base = fok ? fibre_base(fg, a.P, a.n, COMPS) : 0;
 #pragma unroll
@@ -322,12 +346,12 @@ __device__ __forceinline__ void mode_tile(const ModeArgs& a, int64_t tile_x, int
     }
   };
 
-  // Write the staged registers into LDS buffer `buf`, split into pieces.
-  auto store_chunk = [&](int buf) {
+  // Write the staged registers of tile u into LDS buffer `buf`, split into
+  // pieces.
+  auto store_tile = [&](int u, int buf) {
     pc* L = lds + buf * CHUNK;
-#pragma unroll
-    for (int u = 0; u < TPT; ++u) {
-      if (TILES < THREADS && tid >= TILES) break;
+    {
+      if (TILES < THREADS && tid >= TILES) return;
       int tk, tf;
       tile_coords(tid + u * THREADS, tk, tf);
       const int kl0 = tk * TK;
@@ -393,21 +417,24 @@ __device__ __forceinline__ void mode_tile(const ModeArgs& a, int64_t tile_x, int
   auto load_a = [&](int kbg, afrag (&dst)[WMF][NPC]) {
     const afrag* src = Aw + kbg * a_kstride;
 #pragma unroll
-    for (int i = 0; i < WMF; ++i)
+    for (int p = 0; p < NPC; ++p)
 #pragma unroll
-      for (int p = 0; p < NPC; ++p) dst[i][p] = src[(i * NPC + p) * 64];
+      for (int i = 0; i < WMF; ++i) dst[i][p] = src[(i * NPC + p) * 64];
   };
 
-  load_chunk(0);
-  store_chunk(0);
-  __syncthreads();
+  auto store_chunk = [&](int buf) {
+#pragma unroll
+    for (int u = 0; u < TPT; ++u) store_tile(u, buf);
+  };
 
   // B fragments of one K-block (local index kk of the LDS chunk) for this wave.
+  // Piece-major order: the first products of a K-block need piece 0 of
+  // every fragment, so those reads are issued (and complete) first.
   auto read_b = [&](const pc* L, int kk, afrag (&dst)[WNF][NPC]) {
 #pragma unroll
-    for (int j = 0; j < WNF; ++j)
+    for (int p = 0; p < NPC; ++p)
 #pragma unroll
-      for (int p = 0; p < NPC; ++p) {
+      for (int j = 0; j < WNF; ++j) {
         const pc* blk = L + ((kk * NFR + nf0 + j) * NPC + p) * BLK;
         if constexpr (KPL == 8) {
           const int g = lane / NB, nn = lane % NB;
@@ -418,56 +445,87 @@ __device__ __forceinline__ void mode_tile(const ModeArgs& a, int64_t tile_x, int
       }
   };
 
+  // All MFMAs of one K-block: the piece products (outer), then the wave's
+  // WMF x WNF fragments, so that consecutive MFMAs use different
+  // accumulators.
+  auto mfma_kblock = [&](const afrag (&af)[WMF][NPC], const afrag (&bf)[WNF][NPC]) {
+#pragma unroll
+    for (int k = 0; k < PP::N; ++k)
+#pragma unroll
+      for (int i = 0; i < WMF; ++i)
+#pragma unroll
+        for (int j = 0; j < WNF; ++j) mfma(acc[i][j], af[i][PP::a(k)], bf[j][PP::b(k)]);
+  };
+
+  load_chunk(0);
+  store_chunk(0);
+  __syncthreads();
+
   // Software pipeline over K-blocks.  While the MFMAs of K-block kb run, the
-  // operator fragments of kb+1 (from L2) are already being loaded into the
-  // other half of a register double buffer.  The
-  // fibre tile of the next chunk is fetched from HBM at the start of the
-  // current chunk, right after the operator loads of the chunk's second
-  // K-block: vector-memory counters retire in order, so with two K-blocks per
-  // chunk no wait for an operator fragment ever waits for that (slower) HBM
-  // fetch, which has a whole chunk of MFMAs to arrive.
+  // operator fragments of kb+1 (from L2) and its B fragments (from LDS,
+  // within a chunk) are loaded into the other halves of register double
+  // buffers.  The fibre tile of the next chunk is fetched from HBM at the
+  // start of the current chunk, right after the operator loads of the
+  // chunk's second K-block (vector-memory counters retire in order, so no
+  // wait for an operator fragment of a later K-block has to wait for that
+  // slower fetch), then split and written to the idle LDS buffer after the
+  // chunk's MFMAs.
   static_assert(KCH % 2 == 0, "K-blocks per chunk must be even (register double buffer)");
   afrag a_buf[2][WMF][NPC];
+  afrag b_buf[2][WNF][NPC];
   load_a(0, a_buf[0]);
+  read_b(lds, 0, b_buf[0]);
   const int kb_last = a.KBT - 1;
   for (int c = 0; c < nchunks; ++c) {
     const int buf = c & 1;
+    const bool more = c + 1 < nchunks;
     const pc* L = lds + buf * CHUNK;
 #pragma unroll
     for (int kk = 0; kk < KCH; ++kk) {
       const int cur = kk & 1, nxt = cur ^ 1;
-      const int kbg = c * KCH + kk;   // global K-block
+      const int kbg = c * KCH + kk;
       load_a(min(kbg + 1, kb_last), a_buf[nxt]);
-      if (kk == 0 && c + 1 < nchunks) load_chunk(c + 1);
-      afrag bfr[WNF][NPC];
-      read_b(L, kk, bfr);
+      if (kk == 0 && more) load_chunk(c + 1);
+      if (kk + 1 < KCH) read_b(L, kk + 1, b_buf[nxt]);
       __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-      for (int k = 0; k < PP::N; ++k)
-#pragma unroll
-        for (int i = 0; i < WMF; ++i)
-#pragma unroll
-          for (int j = 0; j < WNF; ++j) mfma(acc[i][j], a_buf[cur][i][PP::a(k)], bfr[j][PP::b(k)]);
+      mfma_kblock(a_buf[cur], b_buf[cur]);
       __builtin_amdgcn_sched_barrier(0);
     }
-    if (c + 1 < nchunks) {
+    if (more) {
       store_chunk(buf ^ 1);
       __syncthreads();
+      read_b(lds + (buf ^ 1) * CHUNK, 0, b_buf[0]);
     }
   }
 
   // ------------------------------------------------------------- epilogue
   st* __restrict__ out = (st*)a.out;
   const st s_post = (st)a.s_post;
+  // output offset of this lane's fibre in each N-fragment (once per fragment)
+  int64_t obases[WNF];
+  bool fvalid[WNF];
+#pragma unroll
+  for (int j = 0; j < WNF; ++j) {
+    const int64_t fg = f0 + (nf0 + j) * NB + (lane % NB);
+    fvalid[j] = fg < a.F;
+    if constexpr (LD == KL_KCONTIG) {
+      obases[j] = fg * (int64_t)a.m * COMPS;
+    } else if (a.F <= 0x7fffffff) {
+      const uint32_t q = (uint32_t)fg / (uint32_t)a.P;
+      const uint32_t p = (uint32_t)fg - q * (uint32_t)a.P;
+      obases[j] = ((int64_t)p + a.P * (int64_t)a.m * q) * COMPS;
+    } else {
+      obases[j] = fibre_base(fg, a.P, a.m, COMPS);
+    }
+  }
+  const int64_t ostride = (LD == KL_KCONTIG) ? COMPS : a.P * COMPS;   // between entries i, i+1
 #pragma unroll
   for (int i = 0; i < WMF; ++i) {
     const int mf = mf0 + i;
 #pragma unroll
     for (int j = 0; j < WNF; ++j) {
-      const int64_t fg = f0 + (nf0 + j) * NB + (lane % NB);
-      if (fg >= a.F) continue;
-      const int64_t obase = (LD == KL_KCONTIG) ? fg * (int64_t)a.m * COMPS : fibre_base(fg, a.P, a.m, COMPS);
-      const int64_t ostride = (LD == KL_KCONTIG) ? COMPS : a.P * COMPS;   // between entries i, i+1
+      if (!fvalid[j]) continue;
+      const int64_t obase = obases[j];
       // Rows of this lane, in groups of four accumulator registers.
       //  32x32 fragments: register 4q+r holds row 8q + 4(lane/32) + r.
       //  16x16 FP64 fragments: register r holds row lane/16 + 4r; for complex
@@ -498,7 +556,8 @@ __device__ __forceinline__ void mode_tile(const ModeArgs& a, int64_t tile_x, int
             if (ie < a.m) {
               st* dst = out + obase + (int64_t)ie * ostride;
               if constexpr (sizeof(st) == 4) {
-                *(float2*)dst = make_float2(v4[2 * h], v4[2 * h + 1]);
+                typedef float f32x2 __attribute__((ext_vector_type(2)));
+                *(f32x2*)dst = f32x2{v4[2 * h], v4[2 * h + 1]};
               } else {
                 *(f64x2*)dst = f64x2{v4[2 * h], v4[2 * h + 1]};
               }
@@ -516,12 +575,12 @@ __device__ __forceinline__ void mode_tile(const ModeArgs& a, int64_t tile_x, int
   }
 }
 
-template <int PR, bool CPLX, int LD, int WMF, int WNF, int WM, int WN, int KCH, bool PRO, bool EPI>
+template <int PR, bool CPLX, int LD, int WMF, int WNF, int WM, int WN, int KCH, bool PRO, bool EPI, bool ILV>
 __global__ __launch_bounds__(64 * WM * WN) void mode_kernel(ModeArgs a) {
   typedef typename Tr<PR>::pc pc;
   constexpr int CHUNK = KCH * WN * WNF * Tr<PR>::NPC * 64 * Tr<PR>::KPL;
   __shared__ __attribute__((aligned(16))) pc lds[2 * CHUNK];
-  mode_tile<PR, CPLX, LD, WMF, WNF, WM, WN, KCH, PRO, EPI>(a, blockIdx.x, blockIdx.y, lds);
+  mode_tile<PR, CPLX, LD, WMF, WNF, WM, WN, KCH, PRO, EPI, ILV>(a, blockIdx.x, blockIdx.y, lds);
 }
 
 template <int PR, bool CPLX, int LD, int WMF, int WNF, int WM, int WN, int KCH>
@@ -541,21 +600,21 @@ __global__ __launch_bounds__(64 * WM * WN) void mode_batch_kernel(const BatchIte
 // operators with at most 256 / 128 real rows, classes 3..5 are alternative
 // shapes of the split complex kernels.
 template <int PR, int CLS> struct Cfg;
-template <> struct Cfg<KP_F64, 0> { static constexpr int WMF = 8, WNF = 2, WM = 4, WN = 1, KCH = 8; };
-template <> struct Cfg<KP_F64, 1> { static constexpr int WMF = 8, WNF = 1, WM = 2, WN = 2, KCH = 8; };
-template <> struct Cfg<KP_F64, 2> { static constexpr int WMF = 8, WNF = 1, WM = 1, WN = 4, KCH = 8; };
-template <> struct Cfg<KP_F32, 0> { static constexpr int WMF = 4, WNF = 2, WM = 4, WN = 1, KCH = 32; };
-template <> struct Cfg<KP_F32, 1> { static constexpr int WMF = 4, WNF = 1, WM = 2, WN = 2, KCH = 32; };
-template <> struct Cfg<KP_F32, 2> { static constexpr int WMF = 4, WNF = 1, WM = 1, WN = 4, KCH = 32; };
-template <> struct Cfg<KP_BF16X3, 0> { static constexpr int WMF = 4, WNF = 2, WM = 4, WN = 1, KCH = 4; };
-template <> struct Cfg<KP_BF16X3, 1> { static constexpr int WMF = 4, WNF = 1, WM = 2, WN = 2, KCH = 4; };
-template <> struct Cfg<KP_BF16X3, 2> { static constexpr int WMF = 4, WNF = 1, WM = 1, WN = 4, KCH = 4; };
-template <> struct Cfg<KP_BF16X3, 3> { static constexpr int WMF = 4, WNF = 4, WM = 4, WN = 1, KCH = 4; };
-template <> struct Cfg<KP_BF16X3, 4> { static constexpr int WMF = 4, WNF = 4, WM = 4, WN = 1, KCH = 2; };
-template <> struct Cfg<KP_BF16X3, 5> { static constexpr int WMF = 2, WNF = 2, WM = 8, WN = 1, KCH = 4; };
-template <> struct Cfg<KP_BF16, 0> { static constexpr int WMF = 4, WNF = 2, WM = 4, WN = 1, KCH = 4; };
-template <> struct Cfg<KP_BF16, 1> { static constexpr int WMF = 4, WNF = 1, WM = 2, WN = 2, KCH = 4; };
-template <> struct Cfg<KP_BF16, 2> { static constexpr int WMF = 4, WNF = 1, WM = 1, WN = 4, KCH = 4; };
+template <> struct Cfg<KP_F64, 0> { static constexpr int WMF = 8, WNF = 2, WM = 4, WN = 1, KCH = 8; static constexpr bool ILV = false; };
+template <> struct Cfg<KP_F64, 1> { static constexpr int WMF = 8, WNF = 1, WM = 2, WN = 2, KCH = 8; static constexpr bool ILV = false; };
+template <> struct Cfg<KP_F64, 2> { static constexpr int WMF = 8, WNF = 1, WM = 1, WN = 4, KCH = 8; static constexpr bool ILV = false; };
+template <> struct Cfg<KP_F32, 0> { static constexpr int WMF = 4, WNF = 2, WM = 4, WN = 1, KCH = 32; static constexpr bool ILV = false; };
+template <> struct Cfg<KP_F32, 1> { static constexpr int WMF = 4, WNF = 1, WM = 2, WN = 2, KCH = 32; static constexpr bool ILV = false; };
+template <> struct Cfg<KP_F32, 2> { static constexpr int WMF = 4, WNF = 1, WM = 1, WN = 4, KCH = 32; static constexpr bool ILV = false; };
+template <> struct Cfg<KP_BF16X3, 0> { static constexpr int WMF = 4, WNF = 2, WM = 4, WN = 1, KCH = 4; static constexpr bool ILV = false; };
+template <> struct Cfg<KP_BF16X3, 1> { static constexpr int WMF = 4, WNF = 1, WM = 2, WN = 2, KCH = 4; static constexpr bool ILV = false; };
+template <> struct Cfg<KP_BF16X3, 2> { static constexpr int WMF = 4, WNF = 1, WM = 1, WN = 4, KCH = 4; static constexpr bool ILV = false; };
+template <> struct Cfg<KP_BF16X3, 3> { static constexpr int WMF = 4, WNF = 4, WM = 4, WN = 1, KCH = 4; static constexpr bool ILV = false; };
+template <> struct Cfg<KP_BF16X3, 4> { static constexpr int WMF = 4, WNF = 4, WM = 4, WN = 1, KCH = 2; static constexpr bool ILV = false; };
+template <> struct Cfg<KP_BF16X3, 5> { static constexpr int WMF = 4, WNF = 4, WM = 4, WN = 1, KCH = 4; static constexpr bool ILV = true; };
+template <> struct Cfg<KP_BF16, 0> { static constexpr int WMF = 4, WNF = 2, WM = 4, WN = 1, KCH = 4; static constexpr bool ILV = false; };
+template <> struct Cfg<KP_BF16, 1> { static constexpr int WMF = 4, WNF = 1, WM = 2, WN = 2, KCH = 4; static constexpr bool ILV = false; };
+template <> struct Cfg<KP_BF16, 2> { static constexpr int WMF = 4, WNF = 1, WM = 1, WN = 4, KCH = 4; static constexpr bool ILV = false; };
 
 template <int PR> struct NumCls { static constexpr int N = 3; };
 template <> struct NumCls<KP_BF16X3> { static constexpr int N = 6; };
@@ -568,7 +627,7 @@ template <int PR, int CLS> TileShape shape_of() {
 template <int PR, bool CPLX, int LD, bool PRO, bool EPI, int CLS>
 KernFn kfn() {
   typedef Cfg<PR, CLS> C;
-  return &mode_kernel<PR, CPLX, LD, C::WMF, C::WNF, C::WM, C::WN, C::KCH, PRO, EPI>;
+  return &mode_kernel<PR, CPLX, LD, C::WMF, C::WNF, C::WM, C::WN, C::KCH, PRO, EPI, C::ILV>;
 }
 
 template <int PR, bool CPLX, int LD, int CLS>
