@@ -31,6 +31,46 @@ PEAK = {  # MI355X published dense peaks
 N, A, B, BETA, TAU, D = 256, -8.0, 8.0, 100.0, 1e-3, 3
 FLOPS_PER_PRODUCT = 8.0 * N * N ** D            # complex MAC = 8 flops, n per output entry
 FLOPS_PER_STEP = D * FLOPS_PER_PRODUCT
+BYTES_PER_PRODUCT = 2 * 8 * N ** D                 # one read and one write of the complex64 state
+
+
+# sources that determine the split product kernel; HBM traffic counters taken
+# on another build of them are not reported
+KERNEL_SOURCES = ["paper_2103_01691_amd/csrc/mode_tile.h", "paper_2103_01691_amd/csrc/mm_internal.h",
+                  "paper_2103_01691_amd/csrc/kern_bf16x3.hip", "paper_2103_01691_amd/csrc/kern_fp16x2.hip",
+                  "paper_2103_01691_amd/csrc/kernels_common.hip", "paper_2103_01691_amd/build.py"]
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for s in KERNEL_SOURCES:
+        p = os.path.join(ROOT, s)
+        if os.path.exists(p):
+            h.update(s.encode())
+            with open(p, "rb") as f:
+                h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def counter_traffic(summary):
+    """Scaled FETCH_SIZE + WRITE_SIZE bytes per product launch from a committed
+    rocprofv3 summary, or None when it was taken on other kernel sources."""
+    path = os.path.join(ROOT, "profiles", summary)
+    if not os.path.exists(path):
+        return None
+    fields = {}
+    with open(path) as f:
+        for line in f:
+            if ":" in line and not line.startswith(("|", "#", "`")):
+                k, _, v = line.partition(":")
+                fields[k.strip()] = v.strip()
+    if fields.get("kernel_source_sha256_16") != kernel_source_hash():
+        return None
+    try:
+        return float(fields["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
 
 
 def log(msg):
@@ -88,7 +128,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--cpu-steps", type=int, default=4, help="oracle steps timed on the host (0: skip)")
+    ap.add_argument("--cpu-steps", type=int, default=16, help="oracle steps timed on the host (0: skip)")
     ap.add_argument("--no-side-paths", action="store_true", help="skip the FP64 / FP32 comparison paths")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="after timing, run one plain device copy of this many MiB (counter calibration)")
@@ -154,6 +194,7 @@ def main():
         parity = float(np.linalg.norm((got - ref).ravel()) / np.linalg.norm(ref.ravel()))
         op.destroy()
 
+    traffic = counter_traffic("mode_kernel_bf16x3_gpe3d_n256.md")
     out = {
         "metric": "3D n=256 steps/s & achieved TFLOP/s: split-precision MFMA vs plain FP64",
         "value": 1e3 / ms,
@@ -173,7 +214,9 @@ def main():
         "tflops_effective": FLOPS_PER_STEP / (ms * 1e-3) / 1e12,
         "roofline": {
             "bound": "mfma", "achieved": achieved / 1e12 if achieved else None, "peak": PEAK["bf16"] / 1e12,
-            "unit": "TFLOP/s", "frac": (achieved / PEAK["bf16"]) if achieved else None, "traffic": None,
+            "unit": "TFLOP/s", "frac": (achieved / PEAK["bf16"]) if achieved else None, "traffic": traffic,
+            "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE x2 + WRITE_SIZE x1, copy-calibrated)",
+            "algorithmic_bytes_per_launch": BYTES_PER_PRODUCT,
             "kernel": "mode_kernel (split BF16x3, complex 256x256 operator, one mu-mode product per launch)",
             "avg_launch_ms": avg_launch_ms, "launches": len(prod_ms), "per_kind_ms": per_kind,
             "executed_mfma_frac": (6 * achieved / PEAK["bf16"]) if achieved else None,
