@@ -4,13 +4,15 @@ Workload: one Strang step of the 3-D cubic Gross-Pitaevskii equation
 i psi_t = -1/2 Laplace psi + 1/2 |x|^2 psi + beta |psi|^2 psi, beta = 100,
 n = 256 per direction on [-8, 8]^3 (homogeneous Dirichlet, second-order
 finite differences), tau = 1e-3, complex64 state, the three mu-mode products
-in split BF16x3 MFMA with FP32 accumulation, the nonlinear phase fused into
-the last product.  Synthetic seeded Thomas-Fermi-like initial state.
+in split-precision MFMA with FP32 accumulation (--split: FP16x2, three
+products, or BF16x3, six products), the nonlinear phase fused into the last
+product.  Synthetic seeded Thomas-Fermi-like initial state.
 
 Prints one JSON line.  The same step in plain FP64 (complex128 state, FP64
-MFMA) and in FP32 is timed beside it, the per-launch durations of the
-mode-product kernels come from HIP events recorded around each launch inside
-the timed region, and the FP64 CPU oracle is timed on a bounded sample.
+MFMA), in FP32 and in the other split scheme is timed beside it, the
+per-launch durations of the mode-product kernels come from HIP events
+recorded around each launch inside the timed region, and the FP64 CPU oracle
+is timed on a bounded sample.
 """
 from __future__ import annotations
 
@@ -32,6 +34,7 @@ N, A, B, BETA, TAU, D = 256, -8.0, 8.0, 100.0, 1e-3, 3
 FLOPS_PER_PRODUCT = 8.0 * N * N ** D            # complex MAC = 8 flops, n per output entry
 FLOPS_PER_STEP = D * FLOPS_PER_PRODUCT
 BYTES_PER_PRODUCT = 2 * 8 * N ** D                 # one read and one write of the complex64 state
+SPLIT_PRODUCTS = {"bf16x3": 6, "fp16x2": 3}        # MFMA products per algorithmic product
 
 
 # sources that determine the split product kernel; HBM traffic counters taken
@@ -130,6 +133,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--cpu-steps", type=int, default=16, help="oracle steps timed on the host (0: skip)")
     ap.add_argument("--no-side-paths", action="store_true", help="skip the FP64 / FP32 comparison paths")
+    ap.add_argument("--split", default="fp16x2", choices=list(SPLIT_PRODUCTS),
+                    help="split scheme of the timed path")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="after timing, run one plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -149,8 +154,9 @@ def main():
     psi0 = synth.thomas_fermi_initial(N, A, B, D, BETA, cfg_id=4)
     ctx = mm.Context(0)
 
-    log(f"timing split bf16x3: {args.warmup} warmup + {args.steps} steps")
-    ms, wall, recs = time_path(ctx, mm, torch, E, psi0, "bf16x3", args.steps, args.warmup, True)
+    split = args.split
+    log(f"timing split {split}: {args.warmup} warmup + {args.steps} steps")
+    ms, wall, recs = time_path(ctx, mm, torch, E, psi0, split, args.steps, args.warmup, True)
     prod_ms = [t for _, t in recs]
     kinds = sorted(set(k for k, _ in recs))
     per_kind = {str(k): float(np.mean([t for kk, t in recs if kk == k])) for k in kinds}
@@ -159,7 +165,7 @@ def main():
 
     side = {}
     if not args.no_side_paths:
-        for prec in ("fp64", "fp32"):
+        for prec in ["fp64", "fp32"] + [p for p in SPLIT_PRODUCTS if p != split]:
             k = max(10, args.steps // 4)
             log(f"timing {prec}: {k} steps")
             pms, _, _ = time_path(ctx, mm, torch, E, psi0, prec, k, 5, False)
@@ -187,14 +193,14 @@ def main():
         cpu = {"value": sps, "unit": "steps/s", "cores": threads, "kind": "oracle",
                "sample": f"{args.cpu_steps} unmerged FP64 Strang steps of the full 256^3 GPE workload ({dt:.1f} s)"}
         psi = torch.from_numpy(synth.to_device_layout(psi0.astype(np.complex64))).cuda()
-        op = ctx.mm_op_prepare(E, "bf16x3")
+        op = ctx.mm_op_prepare(E, split)
         ctx.gpe_strang_step(psi, [op] * D, TAU, BETA, args.cpu_steps)
         torch.cuda.synchronize()
         got = synth.from_device_layout(psi.cpu().numpy()).astype(np.complex128)
         parity = float(np.linalg.norm((got - ref).ravel()) / np.linalg.norm(ref.ravel()))
         op.destroy()
 
-    traffic = counter_traffic("mode_kernel_bf16x3_gpe3d_n256.md")
+    traffic = counter_traffic(f"mode_kernel_{split}_gpe3d_n256.md")
     out = {
         "metric": "3D n=256 steps/s & achieved TFLOP/s: split-precision MFMA vs plain FP64",
         "value": 1e3 / ms,
@@ -206,10 +212,10 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "bf16x3",
+        "dtype": split,
         "data": "synthetic",
-        "config": {"workload": "gpe3d_strang_n256_split_bf16x3", "d": D, "n": N, "beta": BETA, "tau": TAU,
-                   "domain": [A, B], "state": "complex64", "precision": "split_bf16x3_fp32acc",
+        "config": {"workload": f"gpe3d_strang_n256_split_{split}", "d": D, "n": N, "beta": BETA, "tau": TAU,
+                   "domain": [A, B], "state": "complex64", "precision": f"split_{split}_fp32acc",
                    "parallelism": "single_gpu"},
         "tflops_effective": FLOPS_PER_STEP / (ms * 1e-3) / 1e12,
         "roofline": {
@@ -217,9 +223,9 @@ def main():
             "unit": "TFLOP/s", "frac": (achieved / PEAK["bf16"]) if achieved else None, "traffic": traffic,
             "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE x2 + WRITE_SIZE x1, copy-calibrated)",
             "algorithmic_bytes_per_launch": BYTES_PER_PRODUCT,
-            "kernel": "mode_kernel (split BF16x3, complex 256x256 operator, one mu-mode product per launch)",
+            "kernel": f"mode_kernel (split {split}, complex 256x256 operator, one mu-mode product per launch)",
             "avg_launch_ms": avg_launch_ms, "launches": len(prod_ms), "per_kind_ms": per_kind,
-            "executed_mfma_frac": (6 * achieved / PEAK["bf16"]) if achieved else None,
+            "executed_mfma_frac": (SPLIT_PRODUCTS[split] * achieved / PEAK["bf16"]) if achieved else None,
         },
         "paths": side,
         "speedup_vs_fp64": (side["fp64"]["ms_per_step"] / ms) if "fp64" in side else None,

@@ -64,13 +64,26 @@ typedef enum { MM_R32 = 0, MM_R64 = 1, MM_C64 = 2, MM_C128 = 3 } mm_dtype;
  *                       pieces each (x = x0 + x1 + x2); the six piece
  *                       products x_a y_b with a + b <= 2 run on BF16 MFMA with
  *                       FP32 accumulation.
+ *  MM_PREC_SPLIT_FP16X2 operator and state split into two RNE half-precision
+ *                       pieces each, the low piece scaled by 2^11
+ *                       (x = h + 2^-11 l); the three products h_A h_B,
+ *                       h_A l_B, l_A h_B run on FP16 MFMA with FP32
+ *                       accumulation (half the MFMA work of BF16X3, about
+ *                       two bits less accurate).  The state is scaled by a
+ *                       power of two from a bound of its largest component
+ *                       that the library keeps on the device along each
+ *                       chain of products (one extra max-abs pass over the
+ *                       input at the start of every call); the operator by
+ *                       a power of two fixed at preparation.  Not available
+ *                       in mumode_expstep_batched (MM_ERR_UNSUPPORTED).
  *  MM_PREC_BF16         one bfloat16 piece each (single BF16 MFMA product);
  *                       reported for comparison only.                        */
 typedef enum {
   MM_PREC_FP64 = 0,
   MM_PREC_FP32 = 1,
   MM_PREC_SPLIT_BF16X3 = 2,
-  MM_PREC_BF16 = 3
+  MM_PREC_SPLIT_FP16X2 = 3,
+  MM_PREC_BF16 = 4
 } mm_prec;
 
 #define MM_MAXD 6

@@ -16,10 +16,10 @@ import numpy as np
 
 from . import _lib
 from ._lib import (MM_C64, MM_C128, MM_PREC_BF16, MM_PREC_FP32, MM_PREC_FP64,  # noqa: F401
-                   MM_PREC_SPLIT_BF16X3, MM_R32, MM_R64)
+                   MM_PREC_SPLIT_BF16X3, MM_PREC_SPLIT_FP16X2, MM_R32, MM_R64)
 
 PRECISIONS = {"fp64": MM_PREC_FP64, "fp32": MM_PREC_FP32, "bf16x3": MM_PREC_SPLIT_BF16X3,
-              "bf16": MM_PREC_BF16}
+              "fp16x2": MM_PREC_SPLIT_FP16X2, "bf16": MM_PREC_BF16}
 
 
 class MumodeError(RuntimeError):

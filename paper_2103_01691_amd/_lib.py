@@ -16,7 +16,7 @@ MM_MAXD = 6
 MM_OK, MM_ERR_ARG, MM_ERR_SHAPE, MM_ERR_DTYPE, MM_ERR_ALIGN, MM_ERR_NOMEM, MM_ERR_HIP, \
     MM_ERR_UNSUPPORTED, MM_ERR_NONFINITE, MM_ERR_NODEVICE = range(10)
 MM_R32, MM_R64, MM_C64, MM_C128 = range(4)
-MM_PREC_FP64, MM_PREC_FP32, MM_PREC_SPLIT_BF16X3, MM_PREC_BF16 = range(4)
+MM_PREC_FP64, MM_PREC_FP32, MM_PREC_SPLIT_BF16X3, MM_PREC_SPLIT_FP16X2, MM_PREC_BF16 = range(5)
 
 # every symbol include/mumode.h declares
 EXPORTS = [

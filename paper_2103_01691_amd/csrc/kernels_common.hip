@@ -4,6 +4,7 @@
 #include <stdint.h>
 
 #include <atomic>
+#include <cmath>
 #include <cstdlib>
 
 #include "mode_tile.h"
@@ -16,10 +17,10 @@ namespace {
 template <int PR>
 __global__ void prepare_kernel(const double* __restrict__ master, int64_t rows, int64_t cols,
                                int64_t ld, int cplx, PhaseScale ph, void* __restrict__ outv, int KBT,
-                               int MFT) {
+                               int MFT, int a_exp) {
   typedef Tr<PR> T;
   typedef typename T::pc pc;
-  constexpr int MB = T::MB, KB = T::KB, KPL = T::KPL, NPC = T::NPC;
+  constexpr int MB = T::MB, KB = T::KB, KPL = T::KPL, NPC = T::NPS;
   const int64_t slots = (int64_t)KBT * MFT * 64;   // (kb, mf, lane)
   const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= slots) return;
@@ -65,6 +66,14 @@ __global__ void prepare_kernel(const double* __restrict__ master, int64_t rows, 
       out[base] = x;
     } else if constexpr (PR == KP_F32) {
       out[base] = (float)x;
+    } else if constexpr (PR == KP_FP16X2) {
+      // stored pieces (h 2^11, l) of x 2^-a_exp = h + 2^-11 l (the kernel
+      // forms h itself); the residual is exact in FP64
+      const double xs = ldexp(x, -a_exp);
+      const _Float16 h = (_Float16)(float)xs;
+      const _Float16 l = (_Float16)(float)((xs - (double)h) * 2048.0);
+      out[base] = (_Float16)((float)h * 2048.0f);
+      out[base + (int64_t)64 * KPL] = l;
     } else {
       double r = x;
 #pragma unroll
@@ -125,6 +134,42 @@ __global__ __launch_bounds__(NORM_THREADS) void norm_final_kernel(const double* 
   if (threadIdx.x == 0) result[0] = red[0];
 }
 
+// ------------------------------------------------------------ maxabs ------
+
+// Bound of the state for the FP16X2 products: max |x_k| as float bits
+// (non-negative floats order like their bit patterns; NaN bits order above
+// every finite value).
+__global__ __launch_bounds__(NORM_THREADS) void maxabs_partial_kernel(const float* __restrict__ x,
+                                                                      int64_t count,
+                                                                      uint32_t* __restrict__ partial) {
+  __shared__ uint32_t red[NORM_THREADS];
+  uint32_t m = 0;
+  for (int64_t i = (int64_t)blockIdx.x * NORM_THREADS + threadIdx.x; i < count;
+       i += (int64_t)gridDim.x * NORM_THREADS)
+    m = max(m, __float_as_uint(fabsf(x[i])));
+  red[threadIdx.x] = m;
+  __syncthreads();
+  for (int w = NORM_THREADS / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] = max(red[threadIdx.x], red[threadIdx.x + w]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+}
+
+__global__ __launch_bounds__(NORM_THREADS) void maxabs_final_kernel(const uint32_t* __restrict__ partial,
+                                                                    int nparts, uint32_t* __restrict__ slots) {
+  __shared__ uint32_t red[NORM_THREADS];
+  uint32_t m = 0;
+  for (int i = threadIdx.x; i < nparts; i += NORM_THREADS) m = max(m, partial[i]);
+  red[threadIdx.x] = m;
+  __syncthreads();
+  for (int w = NORM_THREADS / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] = max(red[threadIdx.x], red[threadIdx.x + w]);
+    __syncthreads();
+  }
+  if (threadIdx.x < 3) slots[threadIdx.x] = threadIdx.x == 0 ? red[0] : 0u;
+}
+
 // ---------------------------------------------------------- host side -----
 
 std::atomic<int> g_split_cls{-2};   // -2: not read yet, -1: automatic
@@ -134,7 +179,7 @@ int split_class() {
   if (v == -2) {
     const char* e = std::getenv("MUMODE_SPLIT_TILE");
     int x = e ? std::atoi(e) : 0;
-    v = (x >= 1 && x <= 3) ? x + 2 : (x == 4 ? 0 : -1);
+    v = (x >= 3 && x <= 6) ? x : (x == 1 ? 0 : -1);   // 1: class 0, 3..6: that class
     g_split_cls.store(v);
   }
   return v;
@@ -145,6 +190,7 @@ KernFn pick_kernel_any(int prec, int cplx, int ld, int pro, int epi, int cls) {
     case KP_F64: return pick_kernel_f64(cplx, ld, pro, epi, cls);
     case KP_F32: return pick_kernel_f32(cplx, ld, pro, epi, cls);
     case KP_BF16X3: return pick_kernel_bf16x3(cplx, ld, pro, epi, cls);
+    case KP_FP16X2: return pick_kernel_fp16x2(cplx, ld, pro, epi, cls);
     default: return pick_kernel_bf16(cplx, ld, pro, epi, cls);
   }
 }
@@ -154,19 +200,21 @@ BatchFn pick_batch_any(int prec, int cplx, int ld, int cls) {
     case KP_F64: return pick_batch_f64(cplx, ld, cls);
     case KP_F32: return pick_batch_f32(cplx, ld, cls);
     case KP_BF16X3: return pick_batch_bf16x3(cplx, ld, cls);
+    case KP_FP16X2: return pick_batch_fp16x2(cplx, ld, cls);
     default: return pick_batch_bf16(cplx, ld, cls);
   }
 }
 
 }  // namespace
 
-void set_split_class(int cls) { g_split_cls.store((cls == 0 || (cls >= 3 && cls <= 5)) ? cls : -1); }
+void set_split_class(int cls) { g_split_cls.store((cls == 0 || (cls >= 3 && cls <= 6)) ? cls : -1); }
 
 bool tile_shape(int prec, int cls, TileShape* out) {
   switch (prec) {
     case KP_F64: return tile_shape_f64(cls, out);
     case KP_F32: return tile_shape_f32(cls, out);
     case KP_BF16X3: return tile_shape_bf16x3(cls, out);
+    case KP_FP16X2: return tile_shape_fp16x2(cls, out);
     default: return tile_shape_bf16(cls, out);
   }
 }
@@ -176,6 +224,7 @@ FragGeom frag_geom(int prec) {
     case KP_F64: return {16, 16, 4, 1, 1, 8, 32};
     case KP_F32: return {32, 32, 2, 1, 1, 32, 16};
     case KP_BF16X3: return {32, 32, 16, 8, 3, 4, 16};
+    case KP_FP16X2: return {32, 32, 16, 8, 2, 4, 16};
     default: return {32, 32, 16, 8, 1, 4, 16};
   }
 }
@@ -205,9 +254,10 @@ bool plan_mode(const ModeArgs& a, int prec, int cplx, bool want_pro, bool want_e
   if (!tile_shape(prec, 0, &t0)) return false;
   int cls = 0;
   const int rw = t0.WMF * g.MB;                      // rows per wave
-  if (!batch && prec == KP_BF16X3 && cplx && load != KL_GENERIC && split_class() >= 0) {
+  const bool split = prec == KP_BF16X3 || prec == KP_FP16X2;
+  if (!batch && split && cplx && load != KL_GENERIC && split_class() >= 0) {
     cls = split_class();
-  } else if (!batch && prec == KP_BF16X3 && cplx && load != KL_GENERIC && a.Mr > 2 * rw) {
+  } else if (!batch && split && cplx && load != KL_GENERIC && a.Mr > 2 * rw) {
     cls = 4;   // 4 x 128 rows, 128 fibres, 2 K-blocks per chunk: fastest for 256-long complex modes
   } else if (!pro && !epi && load != KL_GENERIC) {
     if (a.Mr <= rw) cls = 2;
@@ -249,32 +299,50 @@ hipError_t launch_mode_batch(const ModePlan& p, const BatchItem* items, int coun
 }
 
 hipError_t launch_prepare(int prec, int cplx, const double* master, int64_t rows, int64_t cols,
-                          int64_t ld, PhaseScale ph, void* out, int KBT, int MFT, hipStream_t s) {
+                          int64_t ld, PhaseScale ph, void* out, int KBT, int MFT, hipStream_t s,
+                          int a_exp) {
   const int64_t slots = (int64_t)KBT * MFT * 64;
   const int threads = 256;
   const int blocks = (int)((slots + threads - 1) / threads);
   switch (prec) {
     case KP_F64:
       hipLaunchKernelGGL(prepare_kernel<KP_F64>, dim3(blocks), dim3(threads), 0, s, master, rows,
-                         cols, ld, cplx, ph, out, KBT, MFT);
+                         cols, ld, cplx, ph, out, KBT, MFT, a_exp);
       break;
     case KP_F32:
       hipLaunchKernelGGL(prepare_kernel<KP_F32>, dim3(blocks), dim3(threads), 0, s, master, rows,
-                         cols, ld, cplx, ph, out, KBT, MFT);
+                         cols, ld, cplx, ph, out, KBT, MFT, a_exp);
       break;
     case KP_BF16X3:
       hipLaunchKernelGGL(prepare_kernel<KP_BF16X3>, dim3(blocks), dim3(threads), 0, s, master,
-                         rows, cols, ld, cplx, ph, out, KBT, MFT);
+                         rows, cols, ld, cplx, ph, out, KBT, MFT, a_exp);
+      break;
+    case KP_FP16X2:
+      hipLaunchKernelGGL(prepare_kernel<KP_FP16X2>, dim3(blocks), dim3(threads), 0, s, master,
+                         rows, cols, ld, cplx, ph, out, KBT, MFT, a_exp);
       break;
     default:
       hipLaunchKernelGGL(prepare_kernel<KP_BF16>, dim3(blocks), dim3(threads), 0, s, master, rows,
-                         cols, ld, cplx, ph, out, KBT, MFT);
+                         cols, ld, cplx, ph, out, KBT, MFT, a_exp);
       break;
   }
   return hipGetLastError();
 }
 
 int norm_partials() { return NORM_BLOCKS; }
+
+int fp16x2_op_exp(double amax) {
+  if (!(amax > 0.0) || !std::isfinite(amax)) return 0;
+  int e = 0;
+  std::frexp(amax, &e);   // amax in [2^(e-1), 2^e)
+  return e - 4;           // amax 2^-a_exp in [8, 16)
+}
+
+hipError_t launch_maxabs(const float* x, int64_t count, uint32_t* partial, uint32_t* slots, hipStream_t s) {
+  hipLaunchKernelGGL(maxabs_partial_kernel, dim3(NORM_BLOCKS), dim3(NORM_THREADS), 0, s, x, count, partial);
+  hipLaunchKernelGGL(maxabs_final_kernel, dim3(1), dim3(NORM_THREADS), 0, s, partial, NORM_BLOCKS, slots);
+  return hipGetLastError();
+}
 
 template <typename S>
 void reduce_dispatch(int kind, const void* x, const void* y, int64_t count, double* partial, hipStream_t s) {

@@ -6,11 +6,12 @@
 
 namespace mm {
 
-enum KPrec { KP_F64 = 0, KP_F32 = 1, KP_BF16X3 = 2, KP_BF16 = 3 };
+enum KPrec { KP_F64 = 0, KP_F32 = 1, KP_BF16X3 = 2, KP_FP16X2 = 3, KP_BF16 = 4 };
 enum KLoad { KL_KCONTIG = 0, KL_FCONTIG = 1, KL_GENERIC = 2 };
 
 // Geometry of the MFMA fragment a precision uses: M rows and K values per
-// fragment, K values each lane holds, operator pieces per value.
+// fragment, K values each lane holds, operator pieces per value (FP16X2
+// keeps three: hi * 2^11, hi, lo; see mode_tile.h).
 // KPAD / MPAD: the prepared operator's K-blocks and M-fragments are padded
 // (with zeros) to multiples of these, so that every tile shape reads whole
 // chunks and whole row tiles.
@@ -34,6 +35,15 @@ struct ModeArgs {
   int KBT, MFT;        // padded K-blocks and M-fragments of the prepared operator
   double s_pre;        // prologue phase: psi *= exp(-i s_pre |psi|^2) (0: off)
   double s_post;       // epilogue phase, same form
+  // FP16X2 only: running bound of the state.  smax_in holds the float bits of
+  // max |component| of `in`; the launch raises smax_out to that of `out` and
+  // clears smax_clr (the slot the launch before it read).  The operator
+  // pieces represent L * 2^-a_exp.
+  const uint32_t* smax_in;
+  uint32_t* smax_out;
+  uint32_t* smax_clr;
+  int a_exp;
+  int pad_;
 };
 
 // Per-workgroup work item of a batched launch.
@@ -50,23 +60,26 @@ typedef void (*BatchFn)(const BatchItem*);
 // Workgroup tile shape: WM x WN waves, each with WMF x WNF MFMA fragments,
 // KCH K-blocks per LDS chunk.
 struct TileShape {
-  int WMF, WNF, WM, WN, KCH;
+  int WMF, WNF, WM, WN, KCH, OCC;
 };
 
 // Kernel tables, one per precision (kern_<prec>.hip).  cls selects the tile
 // shape (0 default; 1, 2 regrouped waves for operators with at most 256 / 128
-// real rows; 3..5 alternative split shapes).  nullptr if no instance exists.
+// real rows; 3..6 alternative split shapes).  nullptr if no instance exists.
 KernFn pick_kernel_f64(int cplx, int ld, int pro, int epi, int cls);
 KernFn pick_kernel_f32(int cplx, int ld, int pro, int epi, int cls);
 KernFn pick_kernel_bf16x3(int cplx, int ld, int pro, int epi, int cls);
+KernFn pick_kernel_fp16x2(int cplx, int ld, int pro, int epi, int cls);
 KernFn pick_kernel_bf16(int cplx, int ld, int pro, int epi, int cls);
 BatchFn pick_batch_f64(int cplx, int ld, int cls);
 BatchFn pick_batch_f32(int cplx, int ld, int cls);
 BatchFn pick_batch_bf16x3(int cplx, int ld, int cls);
+BatchFn pick_batch_fp16x2(int cplx, int ld, int cls);
 BatchFn pick_batch_bf16(int cplx, int ld, int cls);
 bool tile_shape_f64(int cls, TileShape* out);
 bool tile_shape_f32(int cls, TileShape* out);
 bool tile_shape_bf16x3(int cls, TileShape* out);
+bool tile_shape_fp16x2(int cls, TileShape* out);
 bool tile_shape_bf16(int cls, TileShape* out);
 
 bool tile_shape(int prec, int cls, TileShape* out);
@@ -104,8 +117,16 @@ struct PhaseScale {
 };
 
 // Convert an FP64 master (device, column-major, ld) into fragment order.
+// a_exp (FP16X2 only): the pieces represent master * 2^-a_exp.
 hipError_t launch_prepare(int prec, int cplx, const double* master, int64_t rows, int64_t cols,
-                          int64_t ld, PhaseScale ph, void* out, int KBT, int MFT, hipStream_t s);
+                          int64_t ld, PhaseScale ph, void* out, int KBT, int MFT, hipStream_t s,
+                          int a_exp = 0);
+// Scale exponent of an operator whose largest |real component| is amax:
+// the scaled entries stay below 16 (so hi * 2^11 stays below 2^15).
+int fp16x2_op_exp(double amax);
+// FP16X2 chain start: slots[0] = float bits of max |x_k| over `count` floats,
+// slots[1] = slots[2] = 0.  partial: >= norm_partials() words.
+hipError_t launch_maxabs(const float* x, int64_t count, uint32_t* partial, uint32_t* slots, hipStream_t s);
 size_t prepared_bytes(int prec, int KBT, int MFT);
 
 // Two-pass deterministic FP64 reductions (fp32 or fp64 data):

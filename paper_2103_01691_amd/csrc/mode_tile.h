@@ -28,7 +28,16 @@
 //   KP_BF16X3  v_mfma_f32_32x32x16_bf16, operands split x = x0 + x1 + x2 into
 //              RNE bfloat16 pieces; the six products x_a y_b with a + b <= 2
 //              are accumulated in FP32.
-//   KP_BF16    same MFMA, one piece each (comparison only).
+//   KP_FP16X2  v_mfma_f32_32x32x16_f16, two-piece half-precision split with
+//              the low piece scaled by 2^11 (x = h + 2^-11 l).  With the
+//              operator kept as three pieces (h_A 2^11, h_A, l_A) one FP32
+//              accumulator collects  2^11 [A B - (A - h_A)(B - h_B)]  in
+//              three products; the epilogue scales it back.  Half precision
+//              has a narrow exponent range, so the state is scaled by a
+//              power of two from a running bound of max |component| that
+//              every launch passes to the next (smax slots), and the
+//              operator by a fixed power of two chosen at preparation.
+//   KP_BF16    same MFMA as BF16X3, one piece each (comparison only).
 //
 // Fused Gross-Pitaevskii phase.  The exact nonlinear subflow
 // psi <- exp(-i s beta |psi|^2) psi (Section 4.5: the nonlinear part is
@@ -44,6 +53,7 @@
 namespace mm {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef double f64x2 __attribute__((ext_vector_type(2)));
@@ -57,28 +67,37 @@ template <> struct Tr<KP_F64> {
   typedef double pc;     // operator / staged piece scalar
   typedef double afrag;  // per-lane fragment
   typedef f64x4 acc;
-  static constexpr int MB = 16, NB = 16, KB = 4, KPL = 1, NPC = 1, NACC = 4;
+  static constexpr int MB = 16, NB = 16, KB = 4, KPL = 1, NPA = 1, NPS = 1, NPB = 1, NACC = 4;
 };
 template <> struct Tr<KP_F32> {
   typedef float st;
   typedef float pc;
   typedef float afrag;
   typedef f32x16 acc;
-  static constexpr int MB = 32, NB = 32, KB = 2, KPL = 1, NPC = 1, NACC = 16;
+  static constexpr int MB = 32, NB = 32, KB = 2, KPL = 1, NPA = 1, NPS = 1, NPB = 1, NACC = 16;
 };
 template <> struct Tr<KP_BF16X3> {
   typedef float st;
   typedef __bf16 pc;
   typedef bf16x8 afrag;
   typedef f32x16 acc;
-  static constexpr int MB = 32, NB = 32, KB = 16, KPL = 8, NPC = 3, NACC = 16;
+  static constexpr int MB = 32, NB = 32, KB = 16, KPL = 8, NPA = 3, NPS = 3, NPB = 3, NACC = 16;
+};
+template <> struct Tr<KP_FP16X2> {
+  typedef float st;
+  typedef _Float16 pc;
+  typedef f16x8 afrag;
+  typedef f32x16 acc;
+  // operator pieces used (h 2^11, h, l), of which (h 2^11, l) are stored and
+  // h is formed in registers; state pieces (h, l)
+  static constexpr int MB = 32, NB = 32, KB = 16, KPL = 8, NPA = 3, NPS = 2, NPB = 2, NACC = 16;
 };
 template <> struct Tr<KP_BF16> {
   typedef float st;
   typedef __bf16 pc;
   typedef bf16x8 afrag;
   typedef f32x16 acc;
-  static constexpr int MB = 32, NB = 32, KB = 16, KPL = 8, NPC = 1, NACC = 16;
+  static constexpr int MB = 32, NB = 32, KB = 16, KPL = 8, NPA = 1, NPS = 1, NPB = 1, NACC = 16;
 };
 
 __device__ __forceinline__ void mfma(f64x4& c, double a, double b) {
@@ -90,21 +109,28 @@ __device__ __forceinline__ void mfma(f32x16& c, float a, float b) {
 __device__ __forceinline__ void mfma(f32x16& c, bf16x8 a, bf16x8 b) {
   c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
 }
+__device__ __forceinline__ void mfma(f32x16& c, f16x8 a, f16x8 b) {
+  c = __builtin_amdgcn_mfma_f32_32x32x16_f16(a, b, c, 0, 0, 0);
+}
 
-// Piece pairs (a, b) of the split product, a + b <= NPC - 1.
-template <int NPC> struct Prods;
-template <> struct Prods<1> {
+// Piece pairs (a, b) of the split product: operator piece a times state
+// piece b, in issue order.
+template <int PR> struct Prods {
   static constexpr int N = 1;
   __device__ static constexpr int a(int) { return 0; }
   __device__ static constexpr int b(int) { return 0; }
-  __device__ static constexpr int last_a(int) { return 0; }   // last product using operator piece p
 };
-template <> struct Prods<3> {
+template <> struct Prods<KP_BF16X3> {
+  // (0,0) (0,1) (1,0) (0,2) (1,1) (2,0): piece orders a + b <= 2
   static constexpr int N = 6;
-  // (0,0) (0,1) (1,0) (0,2) (1,1) (2,0)
   __device__ static constexpr int a(int k) { return k == 2 ? 1 : k == 4 ? 1 : k == 5 ? 2 : 0; }
   __device__ static constexpr int b(int k) { return k == 1 ? 1 : k == 3 ? 2 : k == 4 ? 1 : 0; }
-  __device__ static constexpr int last_a(int p) { return p == 0 ? 3 : p == 1 ? 4 : 5; }
+};
+template <> struct Prods<KP_FP16X2> {
+  // (h_A 2^11) h_B + h_A l_B + l_A h_B
+  static constexpr int N = 3;
+  __device__ static constexpr int a(int k) { return k; }
+  __device__ static constexpr int b(int k) { return k == 1 ? 1 : 0; }
 };
 
 // Split a float into NPC round-to-nearest-even bfloat16 pieces.  Each
@@ -122,6 +148,24 @@ __device__ __forceinline__ void split_bf16(float x, __bf16* p) {
       p[2] = (__bf16)r2;
     }
   }
+}
+
+// Split x 2^-e into two RNE half-precision pieces h + 2^-11 l.  The residual
+// x 2^-e - h is exact in FP32 (h is the value rounded to 11 bits) and is
+// stored scaled by 2^11 so that it keeps the range of h.
+__device__ __forceinline__ void split_f16x2(float x, int e, _Float16* p) {
+  const float xs = ldexpf(x, -e);
+  const _Float16 h = (_Float16)xs;
+  p[0] = h;
+  p[1] = (_Float16)((xs - (float)h) * 2048.0f);
+}
+
+// Exponent e with max * 2^-e < 2^15 for the float whose bits are `bits`
+// (a non-negative bound of the state); 0 for a zero bound.
+__device__ __forceinline__ int fp16x2_state_exp(uint32_t bits) {
+  const int be = (int)((bits >> 23) & 0xff);
+  if (be == 0) return 0;
+  return min(be - 127, 127) - 14;
 }
 
 // sin and cos of an FP32 argument: Cody-Waite reduction by pi/2 with a
@@ -181,8 +225,7 @@ __device__ __forceinline__ int64_t fibre_base(int64_t f, int64_t P, int n, int c
 // One workgroup tile: fibres [tile_x * NT, tile_x * NT + NT), M-fragments of
 // row block tile_y.  WM x WN waves: wave (wm, wn) owns M-fragments
 // [(tile_y*WM + wm)*WMF, +WMF) and N-fragments [wn*WNF, +WNF) of the tile.
-template <int PR, bool CPLX, int LD, int WMF, int WNF, int WM, int WN, int KCH, bool PRO, bool EPI,
-          bool ILV = false>
+template <int PR, bool CPLX, int LD, int WMF, int WNF, int WM, int WN, int KCH, bool PRO, bool EPI, int OCC>
 __device__ __forceinline__ void mode_tile(const ModeArgs& a, int64_t tile_x, int tile_y,
                                           typename Tr<PR>::pc* __restrict__ lds) {
   typedef Tr<PR> T;
@@ -190,15 +233,16 @@ __device__ __forceinline__ void mode_tile(const ModeArgs& a, int64_t tile_x, int
   typedef typename T::pc pc;
   typedef typename T::afrag afrag;
   typedef typename T::acc acc_t;
-  constexpr int MB = T::MB, NB = T::NB, KB = T::KB, KPL = T::KPL, NPC = T::NPC;
+  constexpr int MB = T::MB, NB = T::NB, KB = T::KB, KPL = T::KPL, NPA = T::NPA, NPS = T::NPS, NPB = T::NPB;
+  constexpr bool F16 = PR == KP_FP16X2;
   constexpr int THREADS = 64 * WM * WN;
   constexpr int NT = WN * WNF * NB;      // fibres per workgroup
   constexpr int NFR = WN * WNF;          // N-fragments per workgroup
   constexpr int CK = KCH * KB;           // real K values per chunk
   constexpr int BLK = 64 * KPL;          // scalars per (kb, nf, piece) block
-  constexpr int CHUNK = KCH * NFR * NPC * BLK;
+  constexpr int CHUNK = KCH * NFR * NPB * BLK;
   constexpr int COMPS = CPLX ? 2 : 1;
-  typedef Prods<NPC> PP;
+  typedef Prods<PR> PP;
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -210,6 +254,14 @@ __device__ __forceinline__ void mode_tile(const ModeArgs& a, int64_t tile_x, int
 
   const st* __restrict__ in = (const st*)a.in;
   const st s_pre = (st)a.s_pre;
+
+  // FP16X2: state scale from the running bound; the first workgroup clears
+  // the slot the previous launch read (it is complete: same stream)
+  int s_exp = 0;
+  if constexpr (F16) {
+    s_exp = fp16x2_state_exp(*a.smax_in);
+    if (tile_x == 0 && tile_y == 0 && tid == 0) *a.smax_clr = 0u;
+  }
 
   // ---------------------------------------------------------------- staging
   // Tile of TK real K values x TF fibres handled by one thread at a time.
@@ -365,16 +417,19 @@ __device__ __forceinline__ void mode_tile(const ModeArgs& a, int64_t tile_x, int
         for (int fi = 0; fi < TF; ++fi) {
           const int fl = fl0 + fi;
           const int nf = fl / NB, nn = fl % NB;
-          __bf16 pieces[8][NPC];
+          pc pieces[8][NPB];
 #pragma unroll
-          for (int e = 0; e < 8; ++e) split_bf16<NPC>((float)v[e * TF + fi], pieces[e]);
+          for (int e = 0; e < 8; ++e) {
+            if constexpr (F16) split_f16x2((float)v[e * TF + fi], s_exp, pieces[e]);
+            else split_bf16<NPB>((float)v[e * TF + fi], pieces[e]);
+          }
 #pragma unroll
-          for (int p = 0; p < NPC; ++p) {
-            bf16x8 w;
+          for (int p = 0; p < NPB; ++p) {
+            afrag w;
 #pragma unroll
             for (int e = 0; e < 8; ++e) w[e] = pieces[e][p];
-            const int off = ((kb * NFR + nf) * NPC + p) * BLK + (g * NB + swz(nn, kb, g)) * 8;
-            *(bf16x8*)(L + off) = w;
+            const int off = ((kb * NFR + nf) * NPB + p) * BLK + (g * NB + swz(nn, kb, g)) * 8;
+            *(afrag*)(L + off) = w;
           }
         }
       } else {
@@ -411,15 +466,30 @@ __device__ __forceinline__ void mode_tile(const ModeArgs& a, int64_t tile_x, int
   const int nchunks = a.KBT / KCH;
 
   // Operator fragments of one K-block for this wave (from L2).  The wave's
-  // fragments of one K-block are contiguous: WMF * NPC blocks of 64 lanes.
-  const afrag* __restrict__ Aw = Aop + (int64_t)mf0 * NPC * 64 + lane;
-  const int64_t a_kstride = (int64_t)a.MFT * NPC * 64;
-  auto load_a = [&](int kbg, afrag (&dst)[WMF][NPC]) {
+  // fragments of one K-block are contiguous: WMF * NPS blocks of 64 lanes.
+  const afrag* __restrict__ Aw = Aop + (int64_t)mf0 * NPS * 64 + lane;
+  const int64_t a_kstride = (int64_t)a.MFT * NPS * 64;
+  auto load_a = [&](int kbg, afrag (&dst)[WMF][NPA]) {
     const afrag* src = Aw + kbg * a_kstride;
+    if constexpr (F16) {
+      // stored (h 2^11, l); h = (h 2^11) 2^-11 is exact in half precision
 #pragma unroll
-    for (int p = 0; p < NPC; ++p)
+      for (int i = 0; i < WMF; ++i) dst[i][0] = src[(i * NPS + 0) * 64];
 #pragma unroll
-      for (int i = 0; i < WMF; ++i) dst[i][p] = src[(i * NPC + p) * 64];
+      for (int i = 0; i < WMF; ++i) dst[i][2] = src[(i * NPS + 1) * 64];
+    } else {
+#pragma unroll
+      for (int p = 0; p < NPA; ++p)
+#pragma unroll
+        for (int i = 0; i < WMF; ++i) dst[i][p] = src[(i * NPS + p) * 64];
+    }
+  };
+  // FP16X2: form the middle piece right before its products
+  auto finish_a = [&](afrag (&dst)[WMF][NPA]) {
+    if constexpr (F16) {
+#pragma unroll
+      for (int i = 0; i < WMF; ++i) dst[i][1] = dst[i][0] * (_Float16)(1.0f / 2048.0f);
+    }
   };
 
   auto store_chunk = [&](int buf) {
@@ -430,12 +500,12 @@ __device__ __forceinline__ void mode_tile(const ModeArgs& a, int64_t tile_x, int
   // B fragments of one K-block (local index kk of the LDS chunk) for this wave.
   // Piece-major order: the first products of a K-block need piece 0 of
   // every fragment, so those reads are issued (and complete) first.
-  auto read_b = [&](const pc* L, int kk, afrag (&dst)[WNF][NPC]) {
+  auto read_b = [&](const pc* L, int kk, afrag (&dst)[WNF][NPB]) {
 #pragma unroll
-    for (int p = 0; p < NPC; ++p)
+    for (int p = 0; p < NPB; ++p)
 #pragma unroll
       for (int j = 0; j < WNF; ++j) {
-        const pc* blk = L + ((kk * NFR + nf0 + j) * NPC + p) * BLK;
+        const pc* blk = L + ((kk * NFR + nf0 + j) * NPB + p) * BLK;
         if constexpr (KPL == 8) {
           const int g = lane / NB, nn = lane % NB;
           dst[j][p] = *(const afrag*)(blk + (g * NB + swz(nn, kk, g)) * 8);
@@ -448,7 +518,7 @@ __device__ __forceinline__ void mode_tile(const ModeArgs& a, int64_t tile_x, int
   // All MFMAs of one K-block: the piece products (outer), then the wave's
   // WMF x WNF fragments, so that consecutive MFMAs use different
   // accumulators.
-  auto mfma_kblock = [&](const afrag (&af)[WMF][NPC], const afrag (&bf)[WNF][NPC]) {
+  auto mfma_kblock = [&](const afrag (&af)[WMF][NPA], const afrag (&bf)[WNF][NPB]) {
 #pragma unroll
     for (int k = 0; k < PP::N; ++k)
 #pragma unroll
@@ -471,30 +541,56 @@ __device__ __forceinline__ void mode_tile(const ModeArgs& a, int64_t tile_x, int
   // slower fetch), then split and written to the idle LDS buffer after the
   // chunk's MFMAs.
   static_assert(KCH % 2 == 0, "K-blocks per chunk must be even (register double buffer)");
-  afrag a_buf[2][WMF][NPC];
-  afrag b_buf[2][WNF][NPC];
-  load_a(0, a_buf[0]);
-  read_b(lds, 0, b_buf[0]);
-  const int kb_last = a.KBT - 1;
-  for (int c = 0; c < nchunks; ++c) {
-    const int buf = c & 1;
-    const bool more = c + 1 < nchunks;
-    const pc* L = lds + buf * CHUNK;
+  if constexpr (OCC == 1) {
+    afrag a_buf[2][WMF][NPA];
+    afrag b_buf[2][WNF][NPB];
+    load_a(0, a_buf[0]);
+    read_b(lds, 0, b_buf[0]);
+    const int kb_last = a.KBT - 1;
+    for (int c = 0; c < nchunks; ++c) {
+      const int buf = c & 1;
+      const bool more = c + 1 < nchunks;
+      const pc* L = lds + buf * CHUNK;
 #pragma unroll
-    for (int kk = 0; kk < KCH; ++kk) {
-      const int cur = kk & 1, nxt = cur ^ 1;
-      const int kbg = c * KCH + kk;
-      load_a(min(kbg + 1, kb_last), a_buf[nxt]);
-      if (kk == 0 && more) load_chunk(c + 1);
-      if (kk + 1 < KCH) read_b(L, kk + 1, b_buf[nxt]);
-      __builtin_amdgcn_sched_barrier(0);
-      mfma_kblock(a_buf[cur], b_buf[cur]);
-      __builtin_amdgcn_sched_barrier(0);
+      for (int kk = 0; kk < KCH; ++kk) {
+        const int cur = kk & 1, nxt = cur ^ 1;
+        const int kbg = c * KCH + kk;
+        load_a(min(kbg + 1, kb_last), a_buf[nxt]);
+        if (kk == 0 && more) load_chunk(c + 1);
+        if (kk + 1 < KCH) read_b(L, kk + 1, b_buf[nxt]);
+        finish_a(a_buf[cur]);
+        __builtin_amdgcn_sched_barrier(0);
+        mfma_kblock(a_buf[cur], b_buf[cur]);
+        __builtin_amdgcn_sched_barrier(0);
+      }
+      if (more) {
+        store_chunk(buf ^ 1);
+        __syncthreads();
+        read_b(lds + (buf ^ 1) * CHUNK, 0, b_buf[0]);
+      }
     }
-    if (more) {
-      store_chunk(buf ^ 1);
-      __syncthreads();
-      read_b(lds + (buf ^ 1) * CHUNK, 0, b_buf[0]);
+  } else {
+    // Two workgroups share each CU (register budget of two waves per SIMD):
+    // single register buffers, the other workgroup's MFMAs cover the waits.
+    for (int c = 0; c < nchunks; ++c) {
+      const int buf = c & 1;
+      const bool more = c + 1 < nchunks;
+      const pc* L = lds + buf * CHUNK;
+#pragma unroll
+      for (int kk = 0; kk < KCH; ++kk) {
+        const int kbg = c * KCH + kk;
+        afrag af[WMF][NPA];
+        afrag bf[WNF][NPB];
+        load_a(kbg, af);
+        if (kk == KCH - 1 && more) load_chunk(c + 1);
+        read_b(L, kk, bf);
+        finish_a(af);
+        mfma_kblock(af, bf);
+      }
+      if (more) {
+        store_chunk(buf ^ 1);
+        __syncthreads();
+      }
     }
   }
 
@@ -519,6 +615,9 @@ __device__ __forceinline__ void mode_tile(const ModeArgs& a, int64_t tile_x, int
     }
   }
   const int64_t ostride = (LD == KL_KCONTIG) ? COMPS : a.P * COMPS;   // between entries i, i+1
+  // FP16X2: the accumulators hold 2^11 * 2^-(s_exp + a_exp) * result
+  const int o_exp = s_exp + a.a_exp - 11;
+  float vmax = 0.0f;   // FP16X2: max |component| stored by this lane
 #pragma unroll
   for (int i = 0; i < WMF; ++i) {
     const int mf = mf0 + i;
@@ -536,7 +635,10 @@ __device__ __forceinline__ void mode_tile(const ModeArgs& a, int64_t tile_x, int
       for (int gq = 0; gq < GROUPS; ++gq) {
         st v4[4];
 #pragma unroll
-        for (int r = 0; r < 4; ++r) v4[r] = (st)acc[i][j][gq * 4 + r];
+        for (int r = 0; r < 4; ++r) {
+          v4[r] = (st)acc[i][j][gq * 4 + r];
+          if constexpr (F16) v4[r] = ldexpf(v4[r], o_exp);
+        }
         if constexpr (CPLX) {
           int e0, e1;   // entries held as (v4[0], v4[1]) and (v4[2], v4[3])
           if constexpr (MB == 32) {
@@ -554,6 +656,7 @@ __device__ __forceinline__ void mode_tile(const ModeArgs& a, int64_t tile_x, int
           for (int h = 0; h < 2; ++h) {
             const int ie = h ? e1 : e0;
             if (ie < a.m) {
+              if constexpr (F16) vmax = fmaxf(vmax, fmaxf(fabsf(v4[2 * h]), fabsf(v4[2 * h + 1])));
               st* dst = out + obase + (int64_t)ie * ostride;
               if constexpr (sizeof(st) == 4) {
                 typedef float f32x2 __attribute__((ext_vector_type(2)));
@@ -567,67 +670,90 @@ __device__ __forceinline__ void mode_tile(const ModeArgs& a, int64_t tile_x, int
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
             const int ie = (MB == 32) ? mf * 32 + 8 * gq + 4 * (lane / 32) + r : mf * 16 + lane / 16 + 4 * r;
-            if (ie < a.m) out[obase + (int64_t)ie * ostride] = v4[r];
+            if (ie < a.m) {
+              if constexpr (F16) vmax = fmaxf(vmax, fabsf(v4[r]));
+              out[obase + (int64_t)ie * ostride] = v4[r];
+            }
           }
         }
       }
     }
   }
+  if constexpr (F16) {
+    // wave maximum, then one atomic per wave into the next launch's slot
+    // (non-negative floats order like their bit patterns)
+    uint32_t mb = __float_as_uint(vmax);
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) mb = max(mb, (uint32_t)__shfl_xor((int)mb, o));
+    if (lane == 0) atomicMax(a.smax_out, mb);
+  }
 }
 
-template <int PR, bool CPLX, int LD, int WMF, int WNF, int WM, int WN, int KCH, bool PRO, bool EPI, bool ILV>
-__global__ __launch_bounds__(64 * WM * WN) void mode_kernel(ModeArgs a) {
+template <int PR, bool CPLX, int LD, int WMF, int WNF, int WM, int WN, int KCH, bool PRO, bool EPI, int OCC>
+__global__ __launch_bounds__(64 * WM * WN) __attribute__((amdgpu_waves_per_eu(OCC, OCC)))
+void mode_kernel(ModeArgs a) {
   typedef typename Tr<PR>::pc pc;
-  constexpr int CHUNK = KCH * WN * WNF * Tr<PR>::NPC * 64 * Tr<PR>::KPL;
+  constexpr int CHUNK = KCH * WN * WNF * Tr<PR>::NPB * 64 * Tr<PR>::KPL;
   __shared__ __attribute__((aligned(16))) pc lds[2 * CHUNK];
-  mode_tile<PR, CPLX, LD, WMF, WNF, WM, WN, KCH, PRO, EPI, ILV>(a, blockIdx.x, blockIdx.y, lds);
+  mode_tile<PR, CPLX, LD, WMF, WNF, WM, WN, KCH, PRO, EPI, OCC>(a, blockIdx.x, blockIdx.y, lds);
 }
 
 template <int PR, bool CPLX, int LD, int WMF, int WNF, int WM, int WN, int KCH>
 __global__ __launch_bounds__(64 * WM * WN) void mode_batch_kernel(const BatchItem* __restrict__ items) {
   typedef typename Tr<PR>::pc pc;
-  constexpr int CHUNK = KCH * WN * WNF * Tr<PR>::NPC * 64 * Tr<PR>::KPL;
+  constexpr int CHUNK = KCH * WN * WNF * Tr<PR>::NPB * 64 * Tr<PR>::KPL;
   __shared__ __attribute__((aligned(16))) pc lds[2 * CHUNK];
   const BatchItem& it = items[blockIdx.x];
   const ModeArgs a = it.a;
-  mode_tile<PR, CPLX, LD, WMF, WNF, WM, WN, KCH, false, false>(a, it.tile_x, it.tile_y, lds);
+  mode_tile<PR, CPLX, LD, WMF, WNF, WM, WN, KCH, false, false, 1>(a, it.tile_x, it.tile_y, lds);
 }
 
 // ------------------------------------------------------------ configs -----
 
 // Tile shapes: class 0 is the default (WM waves stacked along M cover up to
 // 512 real rows), classes 1 and 2 regroup the same waves 2 x 2 and 1 x 4 for
-// operators with at most 256 / 128 real rows, classes 3..5 are alternative
-// shapes of the split complex kernels.
+// operators with at most 256 / 128 real rows, classes 3 and 4 are alternative
+// shapes of the split complex kernels (4 x 128 rows, 128 fibres, with 4 or 2
+// K-blocks per LDS chunk), classes 5 and 6 split shapes with 64 fibres sized
+// for two workgroups per CU (OCC = 2).
 template <int PR, int CLS> struct Cfg;
-template <> struct Cfg<KP_F64, 0> { static constexpr int WMF = 8, WNF = 2, WM = 4, WN = 1, KCH = 8; static constexpr bool ILV = false; };
-template <> struct Cfg<KP_F64, 1> { static constexpr int WMF = 8, WNF = 1, WM = 2, WN = 2, KCH = 8; static constexpr bool ILV = false; };
-template <> struct Cfg<KP_F64, 2> { static constexpr int WMF = 8, WNF = 1, WM = 1, WN = 4, KCH = 8; static constexpr bool ILV = false; };
-template <> struct Cfg<KP_F32, 0> { static constexpr int WMF = 4, WNF = 2, WM = 4, WN = 1, KCH = 32; static constexpr bool ILV = false; };
-template <> struct Cfg<KP_F32, 1> { static constexpr int WMF = 4, WNF = 1, WM = 2, WN = 2, KCH = 32; static constexpr bool ILV = false; };
-template <> struct Cfg<KP_F32, 2> { static constexpr int WMF = 4, WNF = 1, WM = 1, WN = 4, KCH = 32; static constexpr bool ILV = false; };
-template <> struct Cfg<KP_BF16X3, 0> { static constexpr int WMF = 4, WNF = 2, WM = 4, WN = 1, KCH = 4; static constexpr bool ILV = false; };
-template <> struct Cfg<KP_BF16X3, 1> { static constexpr int WMF = 4, WNF = 1, WM = 2, WN = 2, KCH = 4; static constexpr bool ILV = false; };
-template <> struct Cfg<KP_BF16X3, 2> { static constexpr int WMF = 4, WNF = 1, WM = 1, WN = 4, KCH = 4; static constexpr bool ILV = false; };
-template <> struct Cfg<KP_BF16X3, 3> { static constexpr int WMF = 4, WNF = 4, WM = 4, WN = 1, KCH = 4; static constexpr bool ILV = false; };
-template <> struct Cfg<KP_BF16X3, 4> { static constexpr int WMF = 4, WNF = 4, WM = 4, WN = 1, KCH = 2; static constexpr bool ILV = false; };
-template <> struct Cfg<KP_BF16X3, 5> { static constexpr int WMF = 4, WNF = 4, WM = 4, WN = 1, KCH = 4; static constexpr bool ILV = true; };
-template <> struct Cfg<KP_BF16, 0> { static constexpr int WMF = 4, WNF = 2, WM = 4, WN = 1, KCH = 4; static constexpr bool ILV = false; };
-template <> struct Cfg<KP_BF16, 1> { static constexpr int WMF = 4, WNF = 1, WM = 2, WN = 2, KCH = 4; static constexpr bool ILV = false; };
-template <> struct Cfg<KP_BF16, 2> { static constexpr int WMF = 4, WNF = 1, WM = 1, WN = 4, KCH = 4; static constexpr bool ILV = false; };
+template <> struct Cfg<KP_F64, 0> { static constexpr int WMF = 8, WNF = 2, WM = 4, WN = 1, KCH = 8; static constexpr int OCC = 1; };
+template <> struct Cfg<KP_F64, 1> { static constexpr int WMF = 8, WNF = 1, WM = 2, WN = 2, KCH = 8; static constexpr int OCC = 1; };
+template <> struct Cfg<KP_F64, 2> { static constexpr int WMF = 8, WNF = 1, WM = 1, WN = 4, KCH = 8; static constexpr int OCC = 1; };
+template <> struct Cfg<KP_F32, 0> { static constexpr int WMF = 4, WNF = 2, WM = 4, WN = 1, KCH = 32; static constexpr int OCC = 1; };
+template <> struct Cfg<KP_F32, 1> { static constexpr int WMF = 4, WNF = 1, WM = 2, WN = 2, KCH = 32; static constexpr int OCC = 1; };
+template <> struct Cfg<KP_F32, 2> { static constexpr int WMF = 4, WNF = 1, WM = 1, WN = 4, KCH = 32; static constexpr int OCC = 1; };
+template <> struct Cfg<KP_BF16X3, 0> { static constexpr int WMF = 4, WNF = 2, WM = 4, WN = 1, KCH = 4; static constexpr int OCC = 1; };
+template <> struct Cfg<KP_BF16X3, 1> { static constexpr int WMF = 4, WNF = 1, WM = 2, WN = 2, KCH = 4; static constexpr int OCC = 1; };
+template <> struct Cfg<KP_BF16X3, 2> { static constexpr int WMF = 4, WNF = 1, WM = 1, WN = 4, KCH = 4; static constexpr int OCC = 1; };
+template <> struct Cfg<KP_BF16X3, 3> { static constexpr int WMF = 4, WNF = 4, WM = 4, WN = 1, KCH = 4; static constexpr int OCC = 1; };
+template <> struct Cfg<KP_BF16X3, 4> { static constexpr int WMF = 4, WNF = 4, WM = 4, WN = 1, KCH = 2; static constexpr int OCC = 1; };
+template <> struct Cfg<KP_BF16X3, 5> { static constexpr int WMF = 4, WNF = 2, WM = 4, WN = 1, KCH = 4; static constexpr int OCC = 2; };
+template <> struct Cfg<KP_BF16X3, 6> { static constexpr int WMF = 4, WNF = 2, WM = 4, WN = 1, KCH = 2; static constexpr int OCC = 2; };
+template <> struct Cfg<KP_FP16X2, 0> { static constexpr int WMF = 4, WNF = 2, WM = 4, WN = 1, KCH = 4; static constexpr int OCC = 1; };
+template <> struct Cfg<KP_FP16X2, 1> { static constexpr int WMF = 4, WNF = 1, WM = 2, WN = 2, KCH = 4; static constexpr int OCC = 1; };
+template <> struct Cfg<KP_FP16X2, 2> { static constexpr int WMF = 4, WNF = 1, WM = 1, WN = 4, KCH = 4; static constexpr int OCC = 1; };
+template <> struct Cfg<KP_FP16X2, 3> { static constexpr int WMF = 4, WNF = 4, WM = 4, WN = 1, KCH = 4; static constexpr int OCC = 1; };
+template <> struct Cfg<KP_FP16X2, 4> { static constexpr int WMF = 4, WNF = 4, WM = 4, WN = 1, KCH = 2; static constexpr int OCC = 1; };
+template <> struct Cfg<KP_FP16X2, 5> { static constexpr int WMF = 4, WNF = 2, WM = 4, WN = 1, KCH = 4; static constexpr int OCC = 2; };
+template <> struct Cfg<KP_FP16X2, 6> { static constexpr int WMF = 4, WNF = 2, WM = 4, WN = 1, KCH = 2; static constexpr int OCC = 2; };
+template <> struct Cfg<KP_BF16, 0> { static constexpr int WMF = 4, WNF = 2, WM = 4, WN = 1, KCH = 4; static constexpr int OCC = 1; };
+template <> struct Cfg<KP_BF16, 1> { static constexpr int WMF = 4, WNF = 1, WM = 2, WN = 2, KCH = 4; static constexpr int OCC = 1; };
+template <> struct Cfg<KP_BF16, 2> { static constexpr int WMF = 4, WNF = 1, WM = 1, WN = 4, KCH = 4; static constexpr int OCC = 1; };
 
 template <int PR> struct NumCls { static constexpr int N = 3; };
-template <> struct NumCls<KP_BF16X3> { static constexpr int N = 6; };
+template <> struct NumCls<KP_BF16X3> { static constexpr int N = 7; };
+template <> struct NumCls<KP_FP16X2> { static constexpr int N = 7; };
 
 template <int PR, int CLS> TileShape shape_of() {
   typedef Cfg<PR, CLS> C;
-  return TileShape{C::WMF, C::WNF, C::WM, C::WN, C::KCH};
+  return TileShape{C::WMF, C::WNF, C::WM, C::WN, C::KCH, C::OCC};
 }
 
 template <int PR, bool CPLX, int LD, bool PRO, bool EPI, int CLS>
 KernFn kfn() {
   typedef Cfg<PR, CLS> C;
-  return &mode_kernel<PR, CPLX, LD, C::WMF, C::WNF, C::WM, C::WN, C::KCH, PRO, EPI, C::ILV>;
+  return &mode_kernel<PR, CPLX, LD, C::WMF, C::WNF, C::WM, C::WN, C::KCH, PRO, EPI, C::OCC>;
 }
 
 template <int PR, bool CPLX, int LD, int CLS>
@@ -664,7 +790,8 @@ KernFn pick_kernel(int cplx, int ld, int pro, int epi, int cls) {
       switch (cls) {
         case 3: if (ld == KL_KCONTIG) MM_PH(true, KL_KCONTIG, 3); else MM_PH(true, KL_FCONTIG, 3);
         case 4: if (ld == KL_KCONTIG) MM_PH(true, KL_KCONTIG, 4); else MM_PH(true, KL_FCONTIG, 4);
-        default: if (ld == KL_KCONTIG) MM_PH(true, KL_KCONTIG, 5); else MM_PH(true, KL_FCONTIG, 5);
+        case 5: if (ld == KL_KCONTIG) MM_PH(true, KL_KCONTIG, 5); else MM_PH(true, KL_FCONTIG, 5);
+        default: if (ld == KL_KCONTIG) MM_PH(true, KL_KCONTIG, 6); else MM_PH(true, KL_FCONTIG, 6);
       }
     }
   }
@@ -686,6 +813,8 @@ KernFn pick_kernel(int cplx, int ld, int pro, int epi, int cls) {
 
 template <int PR>
 BatchFn pick_batch(int cplx, int ld, int cls) {
+  // FP16X2 needs a state bound per instance: no batched instances
+  if constexpr (PR == KP_FP16X2) return nullptr;
   if (ld == KL_GENERIC || cls > 2) return nullptr;
 #define MM_B(K_)                                                                      \
   do {                                                                                \
@@ -713,6 +842,7 @@ bool shape_table(int cls, TileShape* out) {
       case 3: *out = shape_of<PR, 3>(); return true;
       case 4: *out = shape_of<PR, 4>(); return true;
       case 5: *out = shape_of<PR, 5>(); return true;
+      case 6: *out = shape_of<PR, 6>(); return true;
       default: break;
     }
   }

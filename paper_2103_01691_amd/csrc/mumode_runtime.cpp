@@ -20,6 +20,7 @@ struct mm_op_s {
   double* dev_master = nullptr;  // FP64 master on the device, ld = rows
   void* prep = nullptr;          // fragment-order operator (own complexity)
   int KBT = 0, MFT = 0;
+  int a_exp = 0;                 // FP16X2: the pieces represent L * 2^-a_exp
   void* prep_c = nullptr;        // real master promoted to complex (lazily)
   int KBT_c = 0, MFT_c = 0;
   double* dev_master_c = nullptr;
@@ -34,6 +35,15 @@ struct mm_ctx_s {
   double* red_partial = nullptr;
   double* red_result = nullptr;
   double* host_result = nullptr; // pinned
+  // FP16X2 state bounds: slots [0, 3) rotate along a chain of products
+  // (launch k reads slot k % 3, raises (k + 1) % 3, clears (k + 2) % 3);
+  // words [4, 4 + norm_partials()) are partial maxima.  chain_end is the
+  // output of the chain's last launch: a product whose input is anything
+  // else (or the first one of an API call) starts a new chain with a
+  // max-abs pass over its input.
+  uint32_t* smax = nullptr;
+  const void* chain_end = nullptr;
+  int sidx = 0;
   // per-mode scratch for operators re-prepared every step (ho_strang_step)
   void* step_prep[MM_MAXD] = {nullptr};
   size_t step_prep_bytes[MM_MAXD] = {0};
@@ -81,6 +91,7 @@ int kprec(mm_prec p) {
     case MM_PREC_FP64: return mm::KP_F64;
     case MM_PREC_FP32: return mm::KP_F32;
     case MM_PREC_SPLIT_BF16X3: return mm::KP_BF16X3;
+    case MM_PREC_SPLIT_FP16X2: return mm::KP_FP16X2;
     default: return mm::KP_BF16;
   }
 }
@@ -146,7 +157,7 @@ mm_status ensure_prepared(mm_ctx ctx, mm_op L, bool cplx, hipStream_t s, void** 
     HIPCHK(ctx, hipMemcpy(L->dev_master_c, cm.data(), 2 * nn * sizeof(double), hipMemcpyHostToDevice));
     HIPCHK(ctx, hipMalloc(&L->prep_c, mm::prepared_bytes(kp, kbt, mft)));
     HIPCHK(ctx, mm::launch_prepare(kp, 1, L->dev_master_c, L->rows, L->cols, L->rows, mm::PhaseScale(),
-                                   L->prep_c, kbt, mft, s));
+                                   L->prep_c, kbt, mft, s, L->a_exp));
     L->KBT_c = kbt;
     L->MFT_c = mft;
   }
@@ -193,6 +204,11 @@ mm_status run_mode(mm_ctx ctx, const void* in, void* out, const int64_t* dims, i
   a.MFT = MFT;
   a.s_pre = s_pre;
   a.s_post = s_post;
+  a.smax_in = nullptr;
+  a.smax_out = nullptr;
+  a.smax_clr = nullptr;
+  a.a_exp = L->a_exp;
+  a.pad_ = 0;
   const bool kcontig = (P == 1) && (a.Kr % 8 == 0);
   const bool fcontig = (P % 4 == 0);
   mm::ModePlan plan;
@@ -200,6 +216,19 @@ mm_status run_mode(mm_ctx ctx, const void* in, void* out, const int64_t* dims, i
     return fail(ctx, MM_ERR_UNSUPPORTED, "no kernel plan for this shape");
   if (plan_out) *plan_out = plan;
   if (dry) return MM_OK;
+  if (plan.prec == mm::KP_FP16X2) {
+    if (in != ctx->chain_end) {
+      int64_t count = (cplx ? 2 : 1);
+      for (int k = 0; k < d; ++k) count *= dims[k];
+      HIPCHK(ctx, mm::launch_maxabs((const float*)in, count, ctx->smax + 4, ctx->smax, s));
+      ctx->sidx = 0;
+    }
+    a.smax_in = ctx->smax + ctx->sidx;
+    a.smax_out = ctx->smax + (ctx->sidx + 1) % 3;
+    a.smax_clr = ctx->smax + (ctx->sidx + 2) % 3;
+    ctx->sidx = (ctx->sidx + 1) % 3;
+    ctx->chain_end = out;
+  }
   if (ctx->profiling) {
     hipEvent_t e0, e1;
     HIPCHK(ctx, hipEventCreate(&e0));
@@ -257,7 +286,10 @@ mm_status sweep(mm_ctx ctx, mm_tensor* T, const mm_op* E, double first_pre, doub
     if (st != MM_OK) return st;
     cur = dst;
   }
-  if (cur != T->data) HIPCHK(ctx, hipMemcpyAsync(T->data, cur, bytes, hipMemcpyDeviceToDevice, s));
+  if (cur != T->data) {
+    HIPCHK(ctx, hipMemcpyAsync(T->data, cur, bytes, hipMemcpyDeviceToDevice, s));
+    if (ctx->chain_end == cur) ctx->chain_end = T->data;
+  }
   return MM_OK;
 }
 
@@ -301,6 +333,7 @@ mm_status mm_create(mm_ctx* out, int device) {
   c->device = device;
   if (hipMalloc((void**)&c->red_partial, sizeof(double) * mm::norm_partials()) != hipSuccess ||
       hipMalloc((void**)&c->red_result, sizeof(double) * 4) != hipSuccess ||
+      hipMalloc((void**)&c->smax, sizeof(uint32_t) * (4 + mm::norm_partials())) != hipSuccess ||
       hipHostMalloc((void**)&c->host_result, sizeof(double) * 4, hipHostMallocDefault) != hipSuccess) {
     delete c;
     return fail(nullptr, MM_ERR_NOMEM, "context buffers");
@@ -343,6 +376,7 @@ mm_status mm_destroy(mm_ctx ctx) {
   if (ctx->cap_stream) hipStreamDestroy(ctx->cap_stream);
   if (ctx->red_partial) hipFree(ctx->red_partial);
   if (ctx->red_result) hipFree(ctx->red_result);
+  if (ctx->smax) hipFree(ctx->smax);
   if (ctx->host_result) hipHostFree(ctx->host_result);
   delete ctx;
   return MM_OK;
@@ -358,6 +392,7 @@ mm_status mm_op_prepare(mm_ctx ctx, const mm_matrix* M, mm_prec prec, mm_op* out
     return fail(ctx, MM_ERR_SHAPE, "operator %lld x %lld outside [1, 4096]", (long long)M->rows, (long long)M->cols);
   if (M->ld < M->rows) return fail(ctx, MM_ERR_SHAPE, "ld < rows");
   HIPCHK(ctx, hipSetDevice(ctx->device));
+  ctx->chain_end = nullptr;
   const int cplx = M->dtype == MM_C128;
   const int comps = cplx ? 2 : 1;
   // compact host copy (ld = rows)
@@ -372,13 +407,17 @@ mm_status mm_op_prepare(mm_ctx ctx, const mm_matrix* M, mm_prec prec, mm_op* out
     for (int64_t j = 0; j < M->cols; ++j)
       std::memcpy(&host[(size_t)j * M->rows * comps], src + (size_t)j * M->ld * comps, sizeof(double) * M->rows * comps);
   }
-  for (double v : host)
+  double amax = 0.0;
+  for (double v : host) {
     if (!std::isfinite(v)) return fail(ctx, MM_ERR_NONFINITE, "operator holds NaN / Inf");
+    amax = std::max(amax, std::fabs(v));
+  }
   mm_op op = new mm_op_s;
   op->rows = M->rows;
   op->cols = M->cols;
   op->cplx = cplx;
   op->prec = prec;
+  op->a_exp = prec == MM_PREC_SPLIT_FP16X2 ? mm::fp16x2_op_exp(amax) : 0;
   const int kp = kprec(prec);
   mm::op_blocks(kp, comps * M->rows, comps * M->cols, &op->KBT, &op->MFT);
   if (hipMalloc((void**)&op->dev_master, host.size() * sizeof(double)) != hipSuccess ||
@@ -390,7 +429,7 @@ mm_status mm_op_prepare(mm_ctx ctx, const mm_matrix* M, mm_prec prec, mm_op* out
   ctx->ops.push_back(op);
   HIPCHK(ctx, hipMemcpy(op->dev_master, host.data(), host.size() * sizeof(double), hipMemcpyHostToDevice));
   HIPCHK(ctx, mm::launch_prepare(kp, cplx, op->dev_master, op->rows, op->cols, op->rows, mm::PhaseScale(),
-                                 op->prep, op->KBT, op->MFT, 0));
+                                 op->prep, op->KBT, op->MFT, 0, op->a_exp));
   HIPCHK(ctx, hipDeviceSynchronize());
   *out = op;
   return MM_OK;
@@ -424,6 +463,7 @@ mm_status mumode_apply(mm_ctx ctx, mm_tensor* out, const mm_tensor* T, mm_op L, 
   if (st != MM_OK) return st;
   if (overlap(out, T)) return fail(ctx, MM_ERR_ARG, "out overlaps T");
   HIPCHK(ctx, hipSetDevice(ctx->device));
+  ctx->chain_end = nullptr;
   return run_mode(ctx, T->data, out->data, T->dims, T->d, T->dtype, L, mu, 0, 0, (hipStream_t)stream, nullptr, false);
 }
 
@@ -441,6 +481,7 @@ mm_status mumode_expstep(mm_ctx ctx, mm_tensor* T, const mm_op* E, int nsteps, m
     if (st != MM_OK) return st;
   }
   HIPCHK(ctx, hipSetDevice(ctx->device));
+  ctx->chain_end = nullptr;
   for (int it = 0; it < nsteps; ++it) {
     st = sweep(ctx, T, E, 0.0, 0.0, (hipStream_t)stream);
     if (st != MM_OK) return st;
@@ -467,6 +508,7 @@ mm_status mumode_transform(mm_ctx ctx, mm_tensor* out, const mm_tensor* in, cons
   }
   if (overlap(out, in)) return fail(ctx, MM_ERR_ARG, "out overlaps in");
   HIPCHK(ctx, hipSetDevice(ctx->device));
+  ctx->chain_end = nullptr;
   hipStream_t s = (hipStream_t)stream;
   // chain of rectangular products: in -> A -> B -> ... -> out, where the
   // intermediate tensors live in the workspace (two halves) and the last
@@ -530,6 +572,7 @@ mm_status gpe_strang_step(mm_ctx ctx, mm_tensor* psi, const mm_op* E, double tau
     if (st != MM_OK) return st;
   }
   HIPCHK(ctx, hipSetDevice(ctx->device));
+  ctx->chain_end = nullptr;
   const double half = 0.5 * tau * beta, full = tau * beta;
   for (int it = 0; it < nsteps; ++it) {
     const double pre = (it == 0) ? half : 0.0;
@@ -558,6 +601,7 @@ mm_status ho_strang_step(mm_ctx ctx, mm_tensor* psi, const mm_op* Lh, const doub
     if (st != MM_OK) return st;
   }
   HIPCHK(ctx, hipSetDevice(ctx->device));
+  ctx->chain_end = nullptr;
   hipStream_t s = (hipStream_t)stream;
   if (!ctx->x2) {
     if (hipMalloc((void**)&ctx->x2, sizeof(double) * MM_MAXD * 4096) != hipSuccess)
@@ -596,7 +640,7 @@ mm_status ho_strang_step(mm_ctx ctx, mm_tensor* psi, const mm_op* Lh, const doub
       ph.cx2 = ph.rx2;
       ph.cc = cb;
       HIPCHK(ctx, mm::launch_prepare(kprec(Lh[k]->prec), 1, Lh[k]->dev_master, Lh[k]->rows, Lh[k]->cols,
-                                     Lh[k]->rows, ph, ctx->step_prep[k], Lh[k]->KBT, Lh[k]->MFT, s));
+                                     Lh[k]->rows, ph, ctx->step_prep[k], Lh[k]->KBT, Lh[k]->MFT, s, Lh[k]->a_exp));
       mm::ModePlan plan;
       st = run_mode(ctx, cur, cur, psi->dims, psi->d, psi->dtype, Lh[k], k + 1, 0, 0, s, &plan, true);
       if (st != MM_OK) return st;
@@ -611,7 +655,10 @@ mm_status ho_strang_step(mm_ctx ctx, mm_tensor* psi, const mm_op* Lh, const doub
       if (st != MM_OK) return st;
       cur = dst;
     }
-    if (cur != psi->data) HIPCHK(ctx, hipMemcpyAsync(psi->data, cur, bytes, hipMemcpyDeviceToDevice, s));
+    if (cur != psi->data) {
+      HIPCHK(ctx, hipMemcpyAsync(psi->data, cur, bytes, hipMemcpyDeviceToDevice, s));
+      if (ctx->chain_end == cur) ctx->chain_end = psi->data;
+    }
   }
   return MM_OK;
 }
@@ -636,11 +683,15 @@ mm_status mumode_expstep_batched(mm_ctx ctx, int count, mm_tensor* const* T, con
         return fail(ctx, MM_ERR_SHAPE, "E[%d][%d] must be %lld x %lld", i, k, (long long)T[i]->dims[k], (long long)T[i]->dims[k]);
       st = check_op_dtype(ctx, L, T[i]->dtype);
       if (st != MM_OK) return st;
+      if (L->prec == MM_PREC_SPLIT_FP16X2)
+        return fail(ctx, MM_ERR_UNSUPPORTED, "E[%d][%d]: the batched step has no FP16X2 kernels "
+                                             "(a state bound per instance would be needed)", i, k);
     }
     for (int j = 0; j < i; ++j)
       if (overlap(T[i], T[j])) return fail(ctx, MM_ERR_ARG, "T[%d] overlaps T[%d]", i, j);
   }
   HIPCHK(ctx, hipSetDevice(ctx->device));
+  ctx->chain_end = nullptr;
   hipStream_t s = (hipStream_t)stream;
   // signature of the batch: tensors and operators
   std::vector<uint64_t> sig;
@@ -694,6 +745,11 @@ mm_status mumode_expstep_batched(mm_ctx ctx, int count, mm_tensor* const* T, con
         a.MFT = MFT;
         a.s_pre = 0.0;
         a.s_post = 0.0;
+        a.smax_in = nullptr;
+        a.smax_out = nullptr;
+        a.smax_clr = nullptr;
+        a.a_exp = 0;
+        a.pad_ = 0;
         const uint64_t key = (uint64_t)plan.prec * 1000 + plan.cplx * 100 + plan.load * 10 + plan.cls;
         size_t g = 0;
         while (g < byk.size() && byk[g].first != key) ++g;
@@ -768,6 +824,7 @@ mm_status mm_energy_gpe(mm_ctx ctx, const mm_tensor* psi, const mm_op* H, double
     if (st != MM_OK) return st;
   }
   HIPCHK(ctx, hipSetDevice(ctx->device));
+  ctx->chain_end = nullptr;
   hipStream_t s = (hipStream_t)stream;
   const size_t bytes = (size_t)numel(psi) * dsize(psi->dtype);
   st = ensure_ws(ctx, bytes);
@@ -807,6 +864,7 @@ mm_status mm_profile_end(mm_ctx ctx, int max_records, int* count, int* kinds, do
   if (!ctx || !count) return MM_ERR_ARG;
   ctx->profiling = false;
   HIPCHK(ctx, hipSetDevice(ctx->device));
+  ctx->chain_end = nullptr;
   int n = 0;
   for (auto& r : ctx->recs) {
     HIPCHK(ctx, hipEventSynchronize(r.b));
@@ -833,6 +891,7 @@ mm_status mm_norm2(mm_ctx ctx, const mm_tensor* T, double cell, double* host_out
   if (st != MM_OK) return st;
   if (!host_out) return fail(ctx, MM_ERR_ARG, "host_out is NULL");
   HIPCHK(ctx, hipSetDevice(ctx->device));
+  ctx->chain_end = nullptr;
   hipStream_t s = (hipStream_t)stream;
   const int64_t count = numel(T) * (is_complex(T->dtype) ? 2 : 1);
   HIPCHK(ctx, mm::launch_reduce(mm::RED_SQ, T->data, nullptr, count, is_f64(T->dtype) ? 1 : 0, ctx->red_partial,

@@ -10,8 +10,10 @@ import synth
 #   fp64   1e-12  (FP64 MFMA; rounding ~ 1e-16 sqrt(n) per product)
 #   fp32   1e-5   (FP32 MFMA)
 #   bf16x3 1e-6   (three-piece split, six products, FP32 accumulation)
+#   fp16x2 1e-6   (two-piece half-precision split, three products, FP32
+#                  accumulation)
 #   bf16   1e-2   (one piece; reported only)
-REL_TOL = {"fp64": 1e-12, "fp32": 1e-5, "bf16x3": 1e-6, "bf16": 1e-2}
+REL_TOL = {"fp64": 1e-12, "fp32": 1e-5, "bf16x3": 1e-6, "fp16x2": 1e-6, "bf16": 1e-2}
 
 
 def rel(a, b):

@@ -69,3 +69,13 @@ def test_batched_rejects_unsupported(ctx):
     with pytest.raises(mm.MumodeError) as e:
         ctx.mumode_expstep_batched([t], [[L, None]], 1)
     assert e.value.status in (2, 7)
+
+
+def test_batched_rejects_fp16x2(ctx):
+    import torch
+    import paper_2103_01691_amd as mm
+    L = ctx.mm_op_prepare(np.eye(8), "fp16x2")
+    t = torch.zeros((8, 8), dtype=torch.float32, device="cuda")
+    with pytest.raises(mm.MumodeError) as e:
+        ctx.mumode_expstep_batched([t], [[L, L]], 1)
+    assert e.value.status == 7

@@ -34,14 +34,15 @@ def _lib_ho_exp(mm, n, a, b, tau):
     return mm.expm(H, -1j * tau)
 
 
+@pytest.mark.parametrize("prec", ["bf16x3", "fp16x2"])
 @pytest.mark.parametrize("tau", [1e-3, 0.1])
-def test_gpe_256_split_one_step(ctx, tau):
+def test_gpe_256_split_one_step(ctx, tau, prec):
     import paper_2103_01691_amd as mm
     n, a, b, beta = 256, -8.0, 8.0, 100.0
-    note(f"gpe 256 tau={tau}: building inputs")
-    psi0 = cast(synth.thomas_fermi_initial(n, a, b, 3, beta, cfg_id=4), "bf16x3", True)
-    Eop = ctx.mm_op_prepare(_lib_ho_exp(mm, n, a, b, tau), "bf16x3")
-    psi = to_gpu(psi0, "bf16x3", True)
+    note(f"gpe 256 tau={tau} {prec}: building inputs")
+    psi0 = cast(synth.thomas_fermi_initial(n, a, b, 3, beta, cfg_id=4), prec, True)
+    Eop = ctx.mm_op_prepare(_lib_ho_exp(mm, n, a, b, tau), prec)
+    psi = to_gpu(psi0, prec, True)
     ctx.gpe_strang_step(psi, [Eop] * 3, tau, beta, 1)
     got = from_gpu(psi)
     del psi
@@ -49,11 +50,11 @@ def test_gpe_256_split_one_step(ctx, tau):
     Eo = op.ho_exponential(n, a, b, tau)
     ref = sc.gpe_strang(psi0, [Eo] * 3, tau, beta, 1)
     err = rel(got, ref)
-    note(f"gpe 256 tau={tau} split bf16x3 one step rel L2 {err:.3e}")
-    assert err < REL_TOL["bf16x3"]
+    note(f"gpe 256 tau={tau} split {prec} one step rel L2 {err:.3e}")
+    assert err < REL_TOL[prec]
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3", "fp16x2"])
 def test_free_schrodinger_256_one_step(ctx, prec):
     import paper_2103_01691_amd as mm
     n, a, b, tau = 256, -10.0, 10.0, 0.01
@@ -71,20 +72,21 @@ def test_free_schrodinger_256_one_step(ctx, prec):
     assert err < REL_TOL[prec]
 
 
-def test_ho_hermite_128_one_step(ctx):
+@pytest.mark.parametrize("prec", ["bf16x3", "fp16x2"])
+def test_ho_hermite_128_one_step(ctx, prec):
     import paper_2103_01691_amd as mm
     m, kmax, tau, eps, t0 = 128, 16, 0.02, 0.1, 0.0
     Phi, Psi, X = op.hermite_forward(m), op.hermite_backward(m), op.hermite_nodes(m)
     c = synth.hermite_coefficients(m, kmax, 3, cfg_id=3)
-    psi0 = cast(om.tucker(c, [Psi] * 3), "bf16x3", True)
+    psi0 = cast(om.tucker(c, [Psi] * 3), prec, True)
     ref = sc.ho_strang(psi0, [Phi] * 3, [Psi] * 3, [X] * 3, t0, tau, eps, 2)
     Xl, _ = mm.hermite_nodes(m)
-    Lh = ctx.mm_op_prepare(mm.hermite_ho_exponential(m, tau), "bf16x3")
-    psi = to_gpu(psi0, "bf16x3", True)
+    Lh = ctx.mm_op_prepare(mm.hermite_ho_exponential(m, tau), prec)
+    psi = to_gpu(psi0, prec, True)
     ctx.ho_strang_step(psi, [Lh] * 3, [Xl] * 3, t0, tau, eps, 2)
     err = rel(from_gpu(psi), ref)
-    note(f"ho 128 two steps rel L2 {err:.3e}")
-    assert err < 2 * REL_TOL["bf16x3"]
+    note(f"ho 128 {prec} two steps rel L2 {err:.3e}")
+    assert err < 2 * REL_TOL[prec]
 
 
 def test_heat_2d_64_twenty_steps_fp64(ctx):

@@ -16,7 +16,7 @@ from oracle import schemes as sc
 
 pytestmark = pytest.mark.gpu
 
-PRECS = ["fp64", "fp32", "bf16x3", "bf16"]
+PRECS = ["fp64", "fp32", "bf16x3", "fp16x2", "bf16"]
 
 
 @pytest.fixture(scope="module")
@@ -54,7 +54,7 @@ def test_apply_rectangular(ctx, prec, cplx, dims, mu):
     Lop.destroy()
 
 
-@pytest.mark.parametrize("prec", ["fp64", "bf16x3"])
+@pytest.mark.parametrize("prec", ["fp64", "bf16x3", "fp16x2"])
 def test_apply_real_operator_on_complex_state(ctx, prec):
     dims = (40, 24, 12)
     g = synth.rng(1002, 0)
@@ -67,7 +67,7 @@ def test_apply_real_operator_on_complex_state(ctx, prec):
     assert rel(from_gpu(out), ref) < REL_TOL[prec]
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3", "fp16x2"])
 def test_apply_large_fibres_and_rows(ctx, prec):
     # 256-long complex mode (the main workload's operator size), many tiles
     dims = (256, 24, 20)
@@ -85,7 +85,7 @@ def test_apply_large_fibres_and_rows(ctx, prec):
         assert err < REL_TOL[prec]
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3", "fp16x2"])
 @pytest.mark.parametrize("cplx", [True, False])
 def test_expstep_in_place(ctx, prec, cplx):
     dims = (32, 48, 24)
@@ -112,7 +112,7 @@ def test_expstep_identity_modes(ctx):
     assert rel(from_gpu(T), om.mode_product(U, E2, 2)) < 1e-12
 
 
-@pytest.mark.parametrize("prec", ["fp64", "bf16x3"])
+@pytest.mark.parametrize("prec", ["fp64", "bf16x3", "fp16x2"])
 def test_transform_rectangular(ctx, prec):
     dims = (40, 28, 20)
     outd = (24, 36, 20)
@@ -126,7 +126,7 @@ def test_transform_rectangular(ctx, prec):
     assert rel(from_gpu(out), ref) < REL_TOL[prec]
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3", "fp16x2"])
 @pytest.mark.parametrize("tau", [1e-3, 0.1])
 @pytest.mark.parametrize("nsteps", [1, 3])
 def test_gpe_strang_small(ctx, prec, tau, nsteps):
@@ -190,3 +190,73 @@ def test_deterministic(ctx):
     import torch
     torch.cuda.synchronize()
     assert torch.equal(a, b)
+
+
+@pytest.mark.parametrize("scale", [1e-9, 1e7])
+def test_fp16x2_state_range(ctx, scale):
+    # half precision spans 2^-24 .. 65504: the state is rescaled by a power
+    # of two from its largest component, so the relative error must not
+    # depend on the magnitude
+    dims = (64, 40, 24)
+    g = synth.rng(1009, int(scale > 1))
+    U = cast(synth.random_tensor(dims, True, g) * scale, "fp16x2", True)
+    E = [synth.random_matrix(n, n, True, g) for n in dims]
+    ref = om.expstep(U, E, 1)
+    ops = [ctx.mm_op_prepare(e, "fp16x2") for e in E]
+    T = to_gpu(U, "fp16x2", True)
+    ctx.mumode_expstep(T, ops, 1)
+    err = rel(from_gpu(T), ref)
+    note(f"fp16x2 state scale {scale:g} rel err {err:.3e}")
+    assert err < REL_TOL["fp16x2"]
+
+
+@pytest.mark.parametrize("scale", [1e-6, 1e4])
+def test_fp16x2_operator_range(ctx, scale):
+    dims = (48, 40, 36)
+    g = synth.rng(1010, int(scale > 1))
+    U = cast(synth.random_tensor(dims, False, g), "fp16x2", False)
+    L = synth.random_matrix(40, 40, False, g) * scale
+    ref = om.mode_product(U, L, 2)
+    out = empty_gpu(dims, "fp16x2", False)
+    ctx.mumode_apply(out, to_gpu(U, "fp16x2", False), ctx.mm_op_prepare(L, "fp16x2"), 2)
+    err = rel(from_gpu(out), ref)
+    note(f"fp16x2 operator scale {scale:g} rel err {err:.3e}")
+    assert err < REL_TOL["fp16x2"]
+
+
+@pytest.mark.parametrize("growth", [40.0, 1.0 / 40.0])
+def test_fp16x2_bound_follows_chain(ctx, growth):
+    # every product scales the state by ~growth: over 3 steps x 3 modes the
+    # magnitude moves by growth^9 (~2.6e14 or its inverse), far outside half
+    # precision, so each launch must pass the bound of its output on
+    dims = (32, 48, 24)
+    g = synth.rng(1011, int(growth > 1))
+    U = cast(synth.random_tensor(dims, True, g), "fp16x2", True)
+    E = [synth.random_matrix(n, n, True, g) * growth for n in dims]
+    ref = om.expstep(U, E, 3)
+    ops = [ctx.mm_op_prepare(e, "fp16x2") for e in E]
+    T = to_gpu(U, "fp16x2", True)
+    ctx.mumode_expstep(T, ops, 3)
+    err = rel(from_gpu(T), ref)
+    note(f"fp16x2 chain growth {growth:g} rel err {err:.3e}")
+    assert err < 3 * REL_TOL["fp16x2"]
+
+
+def test_fp16x2_state_changed_between_calls(ctx):
+    # a new call re-derives the bound from the data, so writes by the caller
+    # between calls are seen
+    import torch
+    dims = (32, 32, 16)
+    g = synth.rng(1012, 0)
+    U = synth.random_tensor(dims, True, g)
+    E = [synth.random_matrix(n, n, True, g) for n in dims]
+    ops = [ctx.mm_op_prepare(e, "fp16x2") for e in E]
+    T = to_gpu(cast(U, "fp16x2", True), "fp16x2", True)
+    ctx.mumode_expstep(T, ops, 1)
+    with torch.no_grad():
+        T.mul_(3.0e5)
+    mid = from_gpu(T)
+    ctx.mumode_expstep(T, ops, 1)
+    err = rel(from_gpu(T), om.expstep(mid, E, 1))
+    note(f"fp16x2 rescaled between calls rel err {err:.3e}")
+    assert err < REL_TOL["fp16x2"]

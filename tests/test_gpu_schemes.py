@@ -21,7 +21,7 @@ def ctx():
     c.close()
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3", "fp16x2"])
 @pytest.mark.parametrize("nsteps", [1, 4])
 def test_ho_strang_matches_oracle(ctx, prec, nsteps):
     import paper_2103_01691_amd as mm
