@@ -86,13 +86,20 @@ def build_operator(mm):
     return mm.expm(H, -1j * TAU)
 
 
-def time_path(ctx, mm, torch, E, psi0_np, prec, steps, warmup, profile):
+def time_path(ctx, mm, torch, E, psi0_np, prec, steps, warmup, profile, tune_ms=0):
     cdt = torch.complex128 if prec == "fp64" else torch.complex64
     npdt = np.complex128 if prec == "fp64" else np.complex64
     import synth
     psi = torch.from_numpy(synth.to_device_layout(psi0_np.astype(npdt))).cuda()
     op = ctx.mm_op_prepare(E, prec)
     ops = [op] * D
+    tuned = []
+    if tune_ms > 0:
+        # tile shape of every mode product chosen by timing (the library's autotuner)
+        ctx.mm_tune_clear()
+        ctx.mm_autotune(psi, ops, tune_ms)
+        tuned = [{"load": k[2], "rows": k[3], "fibres": k[5], "class": c, "us": round(us, 1)}
+                 for k, c, us in ctx.mm_tune_entries()]
     if warmup > 0:
         ctx.gpe_strang_step(psi, ops, TAU, BETA, warmup)
     torch.cuda.synchronize()
@@ -112,7 +119,7 @@ def time_path(ctx, mm, torch, E, psi0_np, prec, steps, warmup, profile):
     op.destroy()
     del psi
     torch.cuda.empty_cache()
-    return ms / steps, wall, recs
+    return ms / steps, wall, recs, tuned
 
 
 def cpu_baseline(psi0, nsteps):
@@ -135,6 +142,7 @@ def main():
     ap.add_argument("--no-side-paths", action="store_true", help="skip the FP64 / FP32 comparison paths")
     ap.add_argument("--split", default="fp16x2", choices=list(SPLIT_PRODUCTS),
                     help="split scheme of the timed path")
+    ap.add_argument("--tune-ms", type=int, default=1500, help="autotuner budget per path (0: built-in tiles)")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="after timing, run one plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -156,7 +164,8 @@ def main():
 
     split = args.split
     log(f"timing split {split}: {args.warmup} warmup + {args.steps} steps")
-    ms, wall, recs = time_path(ctx, mm, torch, E, psi0, split, args.steps, args.warmup, True)
+    ms, wall, recs, tuned = time_path(ctx, mm, torch, E, psi0, split, args.steps, args.warmup, True,
+                                      args.tune_ms)
     prod_ms = [t for _, t in recs]
     kinds = sorted(set(k for k, _ in recs))
     per_kind = {str(k): float(np.mean([t for kk, t in recs if kk == k])) for k in kinds}
@@ -168,7 +177,7 @@ def main():
         for prec in ["fp64", "fp32"] + [p for p in SPLIT_PRODUCTS if p != split]:
             k = max(10, args.steps // 4)
             log(f"timing {prec}: {k} steps")
-            pms, _, _ = time_path(ctx, mm, torch, E, psi0, prec, k, 5, False)
+            pms, _, _, _ = time_path(ctx, mm, torch, E, psi0, prec, k, 5, False, args.tune_ms)
             side[prec] = {"ms_per_step": pms, "steps_per_s": 1e3 / pms,
                           "tflops_effective": FLOPS_PER_STEP / (pms * 1e-3) / 1e12}
 
@@ -227,6 +236,7 @@ def main():
             "avg_launch_ms": avg_launch_ms, "launches": len(prod_ms), "per_kind_ms": per_kind,
             "executed_mfma_frac": (SPLIT_PRODUCTS[split] * achieved / PEAK["bf16"]) if achieved else None,
         },
+        "tuned_tiles": tuned,
         "paths": side,
         "speedup_vs_fp64": (side["fp64"]["ms_per_step"] / ms) if "fp64" in side else None,
         "parity_rel_l2_vs_oracle": parity,

@@ -198,6 +198,43 @@ mm_status mm_energy_gpe(mm_ctx ctx, const mm_tensor* psi, const mm_op* H, double
  * synchronises `stream`.  Returns MM_ERR_NONFINITE if T holds NaN / Inf. */
 mm_status mm_norm2(mm_ctx ctx, const mm_tensor* T, double cell, double* host_out, mm_stream stream);
 
+/* ---------------------------------------------------- tuning, memory ---- */
+
+/* Autotuner for the mode-product kernels.  For every mode k with E[k] !=
+ * NULL, times each tile shape (workgroup layout, fibres per workgroup, K
+ * depth of the LDS chunk, one or two workgroups per CU) that has a kernel
+ * for the product T x_{k+1} E[k], out of place into the context workspace
+ * (T is read, not modified), and records the fastest for that problem shape
+ * (precision, real / complex, fibre load path, rows, columns, number of
+ * fibres).  Later launches of the same shape on this context use the
+ * recorded shape, with or without the fused phases; shapes never tuned use
+ * the built-in choice.  budget_ms bounds the timing loop (at least two
+ * timed repetitions per candidate).  Synchronises `stream`.  The products
+ * along the modes of an expstep, a Strang step or a batch all have the shape
+ * tuned here when called with the same T and E. */
+mm_status mm_autotune(mm_ctx ctx, const mm_tensor* T, const mm_op* E, int budget_ms, mm_stream stream);
+/* Number of recorded tune entries, and entry `index` (0-based):
+ * key6 = {precision, complex, load path (0 contiguous fibres, 1 strided,
+ * 2 gather), real rows, real columns, fibres}, the tile class and its time in
+ * microseconds (any out pointer may be NULL). */
+mm_status mm_tune_count(mm_ctx ctx, int* count);
+mm_status mm_tune_get(mm_ctx ctx, int index, int64_t* key6, int* cls, double* us);
+/* Forget every recorded entry. */
+mm_status mm_tune_clear(mm_ctx ctx);
+/* Write the entries to a text file / add the entries of such a file (an
+ * entry already present is replaced).  MM_ERR_ARG if the file cannot be
+ * opened or is malformed (nothing is added then). */
+mm_status mm_tune_save(mm_ctx ctx, const char* path);
+mm_status mm_tune_load(mm_ctx ctx, const char* path);
+
+/* Hand the context a caller-owned device workspace (256-byte aligned) for
+ * products that cannot run in place and for the transform chain; the
+ * context then never allocates one and returns MM_ERR_NOMEM when a call
+ * needs more than `bytes`.  dev_ptr == NULL returns to a library-owned
+ * workspace.  The caller keeps the memory alive while the context may use
+ * it.  Synchronises the device (any earlier library workspace is freed). */
+mm_status mm_set_workspace(mm_ctx ctx, void* dev_ptr, size_t bytes);
+
 /* ------------------------------------------------------------ timing ---- */
 
 /* Start recording a pair of HIP events around every mode-product kernel

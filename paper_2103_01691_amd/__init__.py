@@ -240,6 +240,42 @@ class Context:
                   "mm_norm2")
         return out.value
 
+    # ------------------------------------------------- tuning, memory ----
+    def mm_autotune(self, T, E, budget_ms: int = 1000, stream=None):
+        t = as_mm_tensor(T)
+        self._chk(_lib.lib.mm_autotune(self.handle, C.byref(t), _op_array(E), int(budget_ms), _stream(stream)),
+                  "mm_autotune")
+
+    def mm_tune_entries(self):
+        """List of (key6 tuple, tile class, microseconds) of the recorded entries."""
+        n = C.c_int()
+        self._chk(_lib.lib.mm_tune_count(self.handle, C.byref(n)), "mm_tune_count")
+        out = []
+        for i in range(n.value):
+            key = (C.c_int64 * 6)()
+            cls = C.c_int()
+            us = C.c_double()
+            self._chk(_lib.lib.mm_tune_get(self.handle, i, key, C.byref(cls), C.byref(us)), "mm_tune_get")
+            out.append((tuple(key), cls.value, us.value))
+        return out
+
+    def mm_tune_clear(self):
+        self._chk(_lib.lib.mm_tune_clear(self.handle), "mm_tune_clear")
+
+    def mm_tune_save(self, path: str):
+        self._chk(_lib.lib.mm_tune_save(self.handle, str(path).encode()), "mm_tune_save")
+
+    def mm_tune_load(self, path: str):
+        self._chk(_lib.lib.mm_tune_load(self.handle, str(path).encode()), "mm_tune_load")
+
+    def mm_set_workspace(self, buf=None):
+        """buf: a torch CUDA tensor the caller keeps alive, or None."""
+        if buf is None:
+            self._chk(_lib.lib.mm_set_workspace(self.handle, None, 0), "mm_set_workspace")
+        else:
+            self._chk(_lib.lib.mm_set_workspace(self.handle, C.c_void_p(buf.data_ptr()),
+                                                buf.numel() * buf.element_size()), "mm_set_workspace")
+
     # --------------------------------------------------------- timing ----
     def mm_profile_begin(self):
         self._chk(_lib.lib.mm_profile_begin(self.handle), "mm_profile_begin")

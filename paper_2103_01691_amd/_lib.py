@@ -26,6 +26,8 @@ EXPORTS = [
     "mm_profile_begin", "mm_profile_end", "ho_strang_step", "mm_energy_gpe", "mm_hermite_ho_exponential",
     "mumode_expstep_batched",
     "mm_fd2_matrix", "mm_expm", "mm_hermite_nodes", "mm_hermite_matrices",
+    "mm_autotune", "mm_tune_count", "mm_tune_get", "mm_tune_clear", "mm_tune_save", "mm_tune_load",
+    "mm_set_workspace",
 ]
 
 
@@ -74,6 +76,13 @@ def _load():
         "mm_expm": (st, [C.c_int, C.POINTER(d), d, d, C.POINTER(d)]),
         "mm_hermite_nodes": (st, [C.c_int, C.POINTER(d), C.POINTER(d)]),
         "mm_hermite_matrices": (st, [C.c_int, C.POINTER(d), C.POINTER(d)]),
+        "mm_autotune": (st, [P, C.POINTER(MMTensor), C.POINTER(P), C.c_int, P]),
+        "mm_tune_count": (st, [P, C.POINTER(C.c_int)]),
+        "mm_tune_get": (st, [P, C.c_int, C.POINTER(C.c_int64), C.POINTER(C.c_int), C.POINTER(d)]),
+        "mm_tune_clear": (st, [P]),
+        "mm_tune_save": (st, [P, C.c_char_p]),
+        "mm_tune_load": (st, [P, C.c_char_p]),
+        "mm_set_workspace": (st, [P, P, C.c_size_t]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)

@@ -244,8 +244,12 @@ size_t prepared_bytes(int prec, int KBT, int MFT) {
   return elems * es;
 }
 
+int num_classes(int prec) {
+  return (prec == KP_BF16X3 || prec == KP_FP16X2) ? 7 : 3;
+}
+
 bool plan_mode(const ModeArgs& a, int prec, int cplx, bool want_pro, bool want_epi, bool fcontig_ok,
-               bool kcontig_ok, ModePlan* plan, bool batch) {
+               bool kcontig_ok, ModePlan* plan, bool batch, int force_cls) {
   FragGeom g = frag_geom(prec);
   const int load = kcontig_ok ? KL_KCONTIG : (fcontig_ok ? KL_FCONTIG : KL_GENERIC);
   const int pro = (want_pro && cplx) ? 1 : 0;
@@ -255,7 +259,12 @@ bool plan_mode(const ModeArgs& a, int prec, int cplx, bool want_pro, bool want_e
   int cls = 0;
   const int rw = t0.WMF * g.MB;                      // rows per wave
   const bool split = prec == KP_BF16X3 || prec == KP_FP16X2;
-  if (!batch && split && cplx && load != KL_GENERIC && split_class() >= 0) {
+  TileShape tf;
+  if (force_cls >= 0 && tile_shape(prec, force_cls, &tf) &&
+      (batch ? pick_batch_any(prec, cplx, load, force_cls) != nullptr
+             : pick_kernel_any(prec, cplx, load, pro, epi, force_cls) != nullptr)) {
+    cls = force_cls;
+  } else if (!batch && split && cplx && load != KL_GENERIC && split_class() >= 0) {
     cls = split_class();
   } else if (!batch && split && cplx && load != KL_GENERIC && a.Mr > 2 * rw) {
     cls = 4;   // 4 x 128 rows, 128 fibres, 2 K-blocks per chunk: fastest for 256-long complex modes

@@ -96,8 +96,12 @@ struct ModePlan {
 
 // Fill `plan` for the given problem; returns false if no kernel fits.
 // batch: plan for the batched work-list kernel (tile classes 0..2 only).
+// force_cls >= 0: use that tile class if an instance exists for the problem
+// (the autotuner's choice), else fall back to the built-in choice.
 bool plan_mode(const ModeArgs& a, int prec, int cplx, bool want_pro, bool want_epi,
-               bool fcontig_ok, bool kcontig_ok, ModePlan* plan, bool batch = false);
+               bool fcontig_ok, bool kcontig_ok, ModePlan* plan, bool batch = false, int force_cls = -1);
+// Number of tile classes of a precision (classes 0 .. n-1).
+int num_classes(int prec);
 hipError_t launch_mode(const ModePlan& plan, const ModeArgs& a, hipStream_t s);
 // Batched launch: `count` work items (device array) that all use `plan`'s
 // kernel (same precision, complexity, load path and tile class).

@@ -3,7 +3,9 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
+#include <map>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -32,6 +34,11 @@ struct mm_ctx_s {
   std::vector<mm_op> ops;
   void* ws = nullptr;            // ping-pong buffer for products that cannot run in place
   size_t ws_bytes = 0;
+  bool ws_user = false;          // ws belongs to the caller (mm_set_workspace)
+  // autotuned tile class per problem shape: key (precision, complex, load
+  // path, real rows Mr, real columns Kr, fibres F) -> (class, microseconds)
+  std::map<std::array<int64_t, 6>, std::pair<int, double>> tune;
+  int force_cls = -1;            // set while the autotuner times a class
   double* red_partial = nullptr;
   double* red_result = nullptr;
   double* host_result = nullptr; // pinned
@@ -211,8 +218,15 @@ mm_status run_mode(mm_ctx ctx, const void* in, void* out, const int64_t* dims, i
   a.pad_ = 0;
   const bool kcontig = (P == 1) && (a.Kr % 8 == 0);
   const bool fcontig = (P % 4 == 0);
+  int force = ctx->force_cls;
+  if (force < 0 && !ctx->tune.empty()) {
+    const int load = kcontig ? mm::KL_KCONTIG : (fcontig ? mm::KL_FCONTIG : mm::KL_GENERIC);
+    auto it = ctx->tune.find({(int64_t)kprec(L->prec), cplx ? 1 : 0, load, a.Mr, a.Kr, a.F});
+    if (it != ctx->tune.end()) force = it->second.first;
+  }
   mm::ModePlan plan;
-  if (!mm::plan_mode(a, kprec(L->prec), cplx ? 1 : 0, s_pre != 0.0, s_post != 0.0, fcontig, kcontig, &plan, batch))
+  if (!mm::plan_mode(a, kprec(L->prec), cplx ? 1 : 0, s_pre != 0.0, s_post != 0.0, fcontig, kcontig, &plan, batch,
+                     force))
     return fail(ctx, MM_ERR_UNSUPPORTED, "no kernel plan for this shape");
   if (plan_out) *plan_out = plan;
   if (dry) return MM_OK;
@@ -246,6 +260,8 @@ mm_status run_mode(mm_ctx ctx, const void* in, void* out, const int64_t* dims, i
 
 mm_status ensure_ws(mm_ctx ctx, size_t bytes) {
   if (ctx->ws_bytes >= bytes) return MM_OK;
+  if (ctx->ws_user)
+    return fail(ctx, MM_ERR_NOMEM, "caller workspace of %zu bytes, %zu needed", ctx->ws_bytes, bytes);
   if (ctx->ws) {
     HIPCHK(ctx, hipDeviceSynchronize());
     HIPCHK(ctx, hipFree(ctx->ws));
@@ -366,7 +382,7 @@ mm_status mm_destroy(mm_ctx ctx) {
     hipEventDestroy(r.a);
     hipEventDestroy(r.b);
   }
-  if (ctx->ws) hipFree(ctx->ws);
+  if (ctx->ws && !ctx->ws_user) hipFree(ctx->ws);
   for (int k = 0; k < MM_MAXD; ++k)
     if (ctx->step_prep[k]) hipFree(ctx->step_prep[k]);
   if (ctx->x2) hipFree(ctx->x2);
@@ -901,6 +917,186 @@ mm_status mm_norm2(mm_ctx ctx, const mm_tensor* T, double cell, double* host_out
   const double v = ctx->host_result[0] * cell;
   *host_out = v;
   if (!std::isfinite(v)) return fail(ctx, MM_ERR_NONFINITE, "norm is not finite");
+  return MM_OK;
+}
+
+mm_status mm_set_workspace(mm_ctx ctx, void* dev_ptr, size_t bytes) {
+  if (!ctx) return MM_ERR_ARG;
+  if (dev_ptr && ((uintptr_t)dev_ptr & 255)) return fail(ctx, MM_ERR_ALIGN, "workspace not 256-byte aligned");
+  HIPCHK(ctx, hipSetDevice(ctx->device));
+  HIPCHK(ctx, hipDeviceSynchronize());
+  if (ctx->ws && !ctx->ws_user) HIPCHK(ctx, hipFree(ctx->ws));
+  ctx->ws = dev_ptr;
+  ctx->ws_bytes = dev_ptr ? bytes : 0;
+  ctx->ws_user = dev_ptr != nullptr;
+  return MM_OK;
+}
+
+mm_status mm_autotune(mm_ctx ctx, const mm_tensor* T, const mm_op* E, int budget_ms, mm_stream stream) {
+  if (!ctx) return MM_ERR_ARG;
+  mm_status st = check_tensor(ctx, T, "T");
+  if (st != MM_OK) return st;
+  if (!E) return fail(ctx, MM_ERR_ARG, "E is NULL");
+  if (budget_ms < 1) budget_ms = 1;
+  for (int k = 0; k < T->d; ++k) {
+    if (!E[k]) continue;
+    if (E[k]->cols != T->dims[k])
+      return fail(ctx, MM_ERR_SHAPE, "E[%d] has %lld columns, n_%d = %lld", k, (long long)E[k]->cols, k + 1,
+                  (long long)T->dims[k]);
+    st = check_op_dtype(ctx, E[k], T->dtype);
+    if (st != MM_OK) return st;
+  }
+  HIPCHK(ctx, hipSetDevice(ctx->device));
+  ctx->chain_end = nullptr;
+  hipStream_t s = (hipStream_t)stream;
+  const bool cplx = is_complex(T->dtype);
+  int modes = 0;
+  for (int k = 0; k < T->d; ++k) modes += E[k] ? 1 : 0;
+  if (modes == 0) return MM_OK;
+  hipEvent_t e0, e1;
+  HIPCHK(ctx, hipEventCreate(&e0));
+  HIPCHK(ctx, hipEventCreate(&e1));
+  struct Ev {
+    hipEvent_t a, b;
+    ~Ev() { hipEventDestroy(a); hipEventDestroy(b); }
+  } guard{e0, e1};
+  const double per_mode_ms = (double)budget_ms / modes;
+  for (int k = 0; k < T->d; ++k) {
+    mm_op L = E[k];
+    if (!L) continue;
+    // product of mode k+1 of T, out of place into the workspace
+    int64_t odims[MM_MAXD];
+    for (int q = 0; q < T->d; ++q) odims[q] = T->dims[q];
+    odims[k] = L->rows;
+    int64_t onum = 1;
+    for (int q = 0; q < T->d; ++q) onum *= odims[q];
+    st = ensure_ws(ctx, (size_t)onum * dsize(T->dtype));
+    if (st != MM_OK) return st;
+    const int kp = kprec(L->prec);
+    const int ncls = mm::num_classes(kp);
+    std::vector<int> cands;
+    for (int c = 0; c < ncls; ++c) {
+      mm::ModePlan plan;
+      ctx->force_cls = c;
+      st = run_mode(ctx, T->data, ctx->ws, T->dims, T->d, T->dtype, L, k + 1, 0, 0, s, &plan, true);
+      ctx->force_cls = -1;
+      if (st == MM_OK && plan.cls == c) cands.push_back(c);
+    }
+    if (cands.empty()) continue;
+    const double per_cand_ms = per_mode_ms / cands.size();
+    int best = -1;
+    double best_ms = 0.0;
+    std::array<int64_t, 6> key{};
+    for (int c : cands) {
+      ctx->force_cls = c;
+      mm::ModePlan plan;
+      // first launch: warm-up (and, for FP16X2, the bound of T in slot 0)
+      ctx->chain_end = nullptr;
+      st = run_mode(ctx, T->data, ctx->ws, T->dims, T->d, T->dtype, L, k + 1, 0, 0, s, &plan, false);
+      if (st == MM_OK) {
+        key = {(int64_t)kp, cplx ? 1 : 0, plan.load, (cplx ? 2 : 1) * L->rows, (cplx ? 2 : 1) * T->dims[k],
+               plan.grid_x > 0 ? onum / odims[k] : 0};
+        HIPCHK(ctx, hipEventRecord(e0, s));
+        ctx->chain_end = T->data;
+        ctx->sidx = 0;
+        st = run_mode(ctx, T->data, ctx->ws, T->dims, T->d, T->dtype, L, k + 1, 0, 0, s, nullptr, false);
+        HIPCHK(ctx, hipEventRecord(e1, s));
+      }
+      if (st != MM_OK) {
+        ctx->force_cls = -1;
+        return st;
+      }
+      HIPCHK(ctx, hipEventSynchronize(e1));
+      float t1 = 0.f;
+      HIPCHK(ctx, hipEventElapsedTime(&t1, e0, e1));
+      int reps = (int)std::min(20.0, std::max(2.0, per_cand_ms / std::max(1e-3, (double)t1)));
+      HIPCHK(ctx, hipEventRecord(e0, s));
+      for (int r = 0; r < reps && st == MM_OK; ++r) {
+        ctx->chain_end = T->data;   // every repetition reads the bound of T (slot 0)
+        ctx->sidx = 0;
+        st = run_mode(ctx, T->data, ctx->ws, T->dims, T->d, T->dtype, L, k + 1, 0, 0, s, nullptr, false);
+      }
+      HIPCHK(ctx, hipEventRecord(e1, s));
+      ctx->force_cls = -1;
+      if (st != MM_OK) return st;
+      HIPCHK(ctx, hipEventSynchronize(e1));
+      float tr = 0.f;
+      HIPCHK(ctx, hipEventElapsedTime(&tr, e0, e1));
+      const double avg = (double)tr / reps;
+      if (best < 0 || avg < best_ms) {
+        best = c;
+        best_ms = avg;
+      }
+    }
+    ctx->tune[key] = {best, best_ms * 1e3};
+  }
+  ctx->chain_end = nullptr;
+  return MM_OK;
+}
+
+mm_status mm_tune_count(mm_ctx ctx, int* count) {
+  if (!ctx || !count) return MM_ERR_ARG;
+  *count = (int)ctx->tune.size();
+  return MM_OK;
+}
+
+mm_status mm_tune_get(mm_ctx ctx, int index, int64_t* key6, int* cls, double* us) {
+  if (!ctx || index < 0 || index >= (int)ctx->tune.size()) return MM_ERR_ARG;
+  auto it = ctx->tune.begin();
+  std::advance(it, index);
+  if (key6)
+    for (int q = 0; q < 6; ++q) key6[q] = it->first[q];
+  if (cls) *cls = it->second.first;
+  if (us) *us = it->second.second;
+  return MM_OK;
+}
+
+mm_status mm_tune_clear(mm_ctx ctx) {
+  if (!ctx) return MM_ERR_ARG;
+  ctx->tune.clear();
+  return MM_OK;
+}
+
+mm_status mm_tune_save(mm_ctx ctx, const char* path) {
+  if (!ctx || !path) return MM_ERR_ARG;
+  FILE* f = std::fopen(path, "w");
+  if (!f) return fail(ctx, MM_ERR_ARG, "cannot write %s", path);
+  std::fprintf(f, "mumode-tune 1\n");
+  for (const auto& e : ctx->tune)
+    std::fprintf(f, "%lld %lld %lld %lld %lld %lld %d %.3f\n", (long long)e.first[0], (long long)e.first[1],
+                 (long long)e.first[2], (long long)e.first[3], (long long)e.first[4], (long long)e.first[5],
+                 e.second.first, e.second.second);
+  const bool ok = std::fclose(f) == 0;
+  return ok ? MM_OK : fail(ctx, MM_ERR_ARG, "write of %s failed", path);
+}
+
+mm_status mm_tune_load(mm_ctx ctx, const char* path) {
+  if (!ctx || !path) return MM_ERR_ARG;
+  FILE* f = std::fopen(path, "r");
+  if (!f) return fail(ctx, MM_ERR_ARG, "cannot read %s", path);
+  char head[32] = {0};
+  int ver = 0;
+  if (std::fscanf(f, "%31s %d", head, &ver) != 2 || std::strcmp(head, "mumode-tune") != 0 || ver != 1) {
+    std::fclose(f);
+    return fail(ctx, MM_ERR_ARG, "%s is not a tune file", path);
+  }
+  std::map<std::array<int64_t, 6>, std::pair<int, double>> t;
+  long long k[6];
+  int c;
+  double us;
+  int n;
+  while ((n = std::fscanf(f, "%lld %lld %lld %lld %lld %lld %d %lf", &k[0], &k[1], &k[2], &k[3], &k[4], &k[5], &c,
+                          &us)) == 8) {
+    if (k[0] < 0 || k[0] > mm::KP_BF16 || c < 0 || c >= mm::num_classes((int)k[0])) {
+      std::fclose(f);
+      return fail(ctx, MM_ERR_ARG, "%s: bad entry", path);
+    }
+    t[{k[0], k[1], k[2], k[3], k[4], k[5]}] = {c, us};
+  }
+  const bool eof = n == EOF;
+  std::fclose(f);
+  if (!eof) return fail(ctx, MM_ERR_ARG, "%s: malformed line", path);
+  for (const auto& e : t) ctx->tune[e.first] = e.second;
   return MM_OK;
 }
 

@@ -1,0 +1,124 @@
+"""GPU tests of the autotuner, the tune cache and the caller-owned workspace.
+
+Every tile class of the split kernels is forced in turn through a tune file
+and checked against the FP64 oracle, so each class the autotuner may pick is
+parity-tested."""
+import numpy as np
+import pytest
+
+import synth
+from gpu_util import REL_TOL, cast, empty_gpu, from_gpu, note, rel, to_gpu
+from oracle import mumode as om
+
+pytestmark = pytest.mark.gpu
+
+DIMS = (256, 48, 40)          # mode 1: contiguous fibres, 512 real rows; modes 2, 3: strided
+PREC_CODE = {"fp64": 0, "fp32": 1, "bf16x3": 2, "fp16x2": 3, "bf16": 4}
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import paper_2103_01691_amd as mm
+    c = mm.Context(0)
+    yield c
+    c.close()
+
+
+def _keys(prec, dims, cplx=True):
+    c = 2 if cplx else 1
+    keys = []
+    for k, n in enumerate(dims):
+        P = int(np.prod(dims[:k]))
+        F = int(np.prod(dims)) // n
+        load = 0 if (P == 1 and (c * n) % 8 == 0) else (1 if P % 4 == 0 else 2)
+        keys.append((PREC_CODE[prec], int(cplx), load, c * n, c * n, F))
+    return keys
+
+
+def _problem(prec):
+    g = synth.rng(1101, PREC_CODE[prec])
+    U = cast(synth.random_tensor(DIMS, True, g), prec, True)
+    E = [synth.random_matrix(n, n, True, g) for n in DIMS]
+    return U, E
+
+
+@pytest.mark.parametrize("prec", ["bf16x3", "fp16x2"])
+@pytest.mark.parametrize("cls", list(range(7)))
+def test_every_split_class_matches_oracle(ctx, tmp_path, prec, cls):
+    U, E = _problem(prec)
+    f = tmp_path / "t.txt"
+    f.write_text("mumode-tune 1\n" + "".join(" ".join(map(str, k)) + f" {cls} 0.0\n" for k in _keys(prec, DIMS)))
+    ctx.mm_tune_clear()
+    ctx.mm_tune_load(f)
+    ops = [ctx.mm_op_prepare(e, prec) for e in E]
+    T = to_gpu(U, prec, True)
+    ctx.mumode_expstep(T, ops, 1)
+    err = rel(from_gpu(T), om.expstep(U, E, 1))
+    ctx.mm_tune_clear()
+    note(f"forced class {cls} {prec} rel err {err:.3e}")
+    assert err < REL_TOL[prec]
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp16x2"])
+def test_autotune_records_and_round_trips(ctx, tmp_path, prec):
+    U, E = _problem(prec)
+    ops = [ctx.mm_op_prepare(e, prec) for e in E]
+    T = to_gpu(U, prec, True)
+    ctx.mm_tune_clear()
+    ctx.mm_autotune(T, ops, 300)
+    assert rel(from_gpu(T), U) == 0.0                      # the tuner does not touch T
+    ent = ctx.mm_tune_entries()
+    note(f"autotune {prec}: {[(k, c, round(us, 1)) for k, c, us in ent]}")
+    assert sorted(k for k, _, _ in ent) == sorted(_keys(prec, DIMS))
+    assert all(0 <= c < 7 and us > 0 for _, c, us in ent)
+    ctx.mumode_expstep(T, ops, 1)                          # runs with the tuned classes
+    assert rel(from_gpu(T), om.expstep(U, E, 1)) < REL_TOL[prec]
+    f = tmp_path / "tune.txt"
+    ctx.mm_tune_save(f)
+    ctx.mm_tune_clear()
+    assert ctx.mm_tune_entries() == []
+    ctx.mm_tune_load(f)
+    back = ctx.mm_tune_entries()
+    assert [(k, c) for k, c, _ in back] == [(k, c) for k, c, _ in ent]
+    ctx.mm_tune_clear()
+
+
+def test_tune_load_rejects_malformed(ctx, tmp_path):
+    import paper_2103_01691_amd as mm
+    f = tmp_path / "bad.txt"
+    f.write_text("mumode-tune 1\n2 1 0 512 512\n")
+    with pytest.raises(mm.MumodeError) as e:
+        ctx.mm_tune_load(f)
+    assert e.value.status == 1
+    f.write_text("something else\n")
+    with pytest.raises(mm.MumodeError):
+        ctx.mm_tune_load(f)
+    f.write_text("mumode-tune 1\n2 1 0 512 512 100 9 1.0\n")   # class out of range
+    with pytest.raises(mm.MumodeError):
+        ctx.mm_tune_load(f)
+    assert ctx.mm_tune_entries() == []
+
+
+def test_caller_workspace(ctx):
+    import torch
+    import paper_2103_01691_amd as mm
+    dims, outd = (40, 28, 20), (24, 36, 20)
+    g = synth.rng(1102, 0)
+    U = synth.random_tensor(dims, True, g)
+    Phi = [synth.random_matrix(outd[k], dims[k], False, g) for k in range(2)] + [None]
+    ops = [ctx.mm_op_prepare(p, "fp64") if p is not None else None for p in Phi]
+    need = 2 * 16 * max(24 * 28 * 20, 24 * 36 * 20)
+    small = torch.empty(256, dtype=torch.uint8, device="cuda")
+    ctx.mm_set_workspace(small)
+    out = empty_gpu(outd, "fp64", True)
+    with pytest.raises(mm.MumodeError) as e:
+        ctx.mumode_transform(out, to_gpu(U, "fp64", True), ops)
+    assert e.value.status == 6
+    big = torch.empty(need + 4096, dtype=torch.uint8, device="cuda")
+    ctx.mm_set_workspace(big)
+    ctx.mumode_transform(out, to_gpu(U, "fp64", True), ops)
+    assert rel(from_gpu(out), om.tucker(U, Phi)) < 1e-12
+    ctx.mm_set_workspace(None)
+    ctx.mumode_transform(out, to_gpu(U, "fp64", True), ops)
+    assert rel(from_gpu(out), om.tucker(U, Phi)) < 1e-12
+    del small, big
