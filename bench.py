@@ -86,7 +86,7 @@ def build_operator(mm):
     return mm.expm(H, -1j * TAU)
 
 
-def time_path(ctx, mm, torch, E, psi0_np, prec, steps, warmup, profile, tune_ms=0):
+def time_path(ctx, mm, torch, E, psi0_np, prec, steps, warmup, profile, tune_ms=0, tune_file=None):
     cdt = torch.complex128 if prec == "fp64" else torch.complex64
     npdt = np.complex128 if prec == "fp64" else np.complex64
     import synth
@@ -94,10 +94,16 @@ def time_path(ctx, mm, torch, E, psi0_np, prec, steps, warmup, profile, tune_ms=
     op = ctx.mm_op_prepare(E, prec)
     ops = [op] * D
     tuned = []
-    if tune_ms > 0:
-        # tile shape of every mode product chosen by timing (the library's autotuner)
+    if tune_ms > 0 or tune_file:
+        # tile shape of every mode product chosen by timing (the library's
+        # autotuner), or read back from a tune file of an earlier run
         ctx.mm_tune_clear()
-        ctx.mm_autotune(psi, ops, tune_ms)
+        if tune_file and os.path.exists(tune_file):
+            ctx.mm_tune_load(tune_file)
+        else:
+            ctx.mm_autotune(psi, ops, max(tune_ms, 1))
+            if tune_file:
+                ctx.mm_tune_save(tune_file)
         tuned = [{"load": k[2], "rows": k[3], "fibres": k[5], "class": c, "us": round(us, 1)}
                  for k, c, us in ctx.mm_tune_entries()]
     if warmup > 0:
@@ -143,6 +149,8 @@ def main():
     ap.add_argument("--split", default="fp16x2", choices=list(SPLIT_PRODUCTS),
                     help="split scheme of the timed path")
     ap.add_argument("--tune-ms", type=int, default=1500, help="autotuner budget per path (0: built-in tiles)")
+    ap.add_argument("--tune-file", default=None,
+                    help="timed path: load the tile choice from this file if it exists, else tune and save it")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="after timing, run one plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -165,7 +173,7 @@ def main():
     split = args.split
     log(f"timing split {split}: {args.warmup} warmup + {args.steps} steps")
     ms, wall, recs, tuned = time_path(ctx, mm, torch, E, psi0, split, args.steps, args.warmup, True,
-                                      args.tune_ms)
+                                      args.tune_ms, args.tune_file)
     prod_ms = [t for _, t in recs]
     kinds = sorted(set(k for k, _ in recs))
     per_kind = {str(k): float(np.mean([t for kk, t in recs if kk == k])) for k in kinds}

@@ -113,7 +113,7 @@ def test_caller_workspace(ctx):
     out = empty_gpu(outd, "fp64", True)
     with pytest.raises(mm.MumodeError) as e:
         ctx.mumode_transform(out, to_gpu(U, "fp64", True), ops)
-    assert e.value.status == 6
+    assert e.value.status == 5          # MM_ERR_NOMEM
     big = torch.empty(need + 4096, dtype=torch.uint8, device="cuda")
     ctx.mm_set_workspace(big)
     ctx.mumode_transform(out, to_gpu(U, "fp64", True), ops)
