@@ -2,8 +2,8 @@
 #include "mode_tile.h"
 
 namespace mm {
-KernFn pick_kernel_bf16x3(int cplx, int ld, int pro, int epi, int cls) {
-  return pick_kernel<KP_BF16X3>(cplx, ld, pro, epi, cls);
+KernFn pick_kernel_bf16x3(int cplx, int ld, int pro, int epi, int cls, int full) {
+  return pick_kernel<KP_BF16X3>(cplx, ld, pro, epi, cls, full);
 }
 BatchFn pick_batch_bf16x3(int cplx, int ld, int cls) { return pick_batch<KP_BF16X3>(cplx, ld, cls); }
 bool tile_shape_bf16x3(int cls, TileShape* out) { return shape_table<KP_BF16X3>(cls, out); }

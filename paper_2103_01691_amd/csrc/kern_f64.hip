@@ -2,8 +2,8 @@
 #include "mode_tile.h"
 
 namespace mm {
-KernFn pick_kernel_f64(int cplx, int ld, int pro, int epi, int cls) {
-  return pick_kernel<KP_F64>(cplx, ld, pro, epi, cls);
+KernFn pick_kernel_f64(int cplx, int ld, int pro, int epi, int cls, int full) {
+  return pick_kernel<KP_F64>(cplx, ld, pro, epi, cls, full);
 }
 BatchFn pick_batch_f64(int cplx, int ld, int cls) { return pick_batch<KP_F64>(cplx, ld, cls); }
 bool tile_shape_f64(int cls, TileShape* out) { return shape_table<KP_F64>(cls, out); }

@@ -185,13 +185,13 @@ int split_class() {
   return v;
 }
 
-KernFn pick_kernel_any(int prec, int cplx, int ld, int pro, int epi, int cls) {
+KernFn pick_kernel_any(int prec, int cplx, int ld, int pro, int epi, int cls, int full = 0) {
   switch (prec) {
-    case KP_F64: return pick_kernel_f64(cplx, ld, pro, epi, cls);
-    case KP_F32: return pick_kernel_f32(cplx, ld, pro, epi, cls);
-    case KP_BF16X3: return pick_kernel_bf16x3(cplx, ld, pro, epi, cls);
-    case KP_FP16X2: return pick_kernel_fp16x2(cplx, ld, pro, epi, cls);
-    default: return pick_kernel_bf16(cplx, ld, pro, epi, cls);
+    case KP_F64: return pick_kernel_f64(cplx, ld, pro, epi, cls, full);
+    case KP_F32: return pick_kernel_f32(cplx, ld, pro, epi, cls, full);
+    case KP_BF16X3: return pick_kernel_bf16x3(cplx, ld, pro, epi, cls, full);
+    case KP_FP16X2: return pick_kernel_fp16x2(cplx, ld, pro, epi, cls, full);
+    default: return pick_kernel_bf16(cplx, ld, pro, epi, cls, full);
   }
 }
 
@@ -287,12 +287,19 @@ bool plan_mode(const ModeArgs& a, int prec, int cplx, bool want_pro, bool want_e
   const int mfr = (a.Mr + g.MB - 1) / g.MB;          // fragments holding real rows
   plan->grid_y = (mfr + t.WM * t.WMF - 1) / (t.WM * t.WMF);
   plan->covers_all_rows = plan->grid_y == 1;
+  {
+    const int64_t out_bytes = (int64_t)a.Mr * a.F * (prec == KP_F64 ? 8 : 4);
+    plan->full = (a.F % plan->nt == 0 && a.Mr % plan->mt_rows == 0 && out_bytes < ((int64_t)1 << 32) &&
+                  load != KL_GENERIC && (cls == 0 || cls >= 3))
+                     ? 1
+                     : 0;
+  }
   if (batch) return plan->grid_x > 0 && pick_batch_any(prec, cplx, load, cls) != nullptr;
   return plan->grid_x > 0 && pick_kernel_any(prec, cplx, load, pro, epi, cls) != nullptr;
 }
 
 hipError_t launch_mode(const ModePlan& p, const ModeArgs& a, hipStream_t s) {
-  KernFn fn = pick_kernel_any(p.prec, p.cplx, p.load, p.pro, p.epi, p.cls);
+  KernFn fn = pick_kernel_any(p.prec, p.cplx, p.load, p.pro, p.epi, p.cls, p.full);
   if (!fn) return hipErrorInvalidDeviceFunction;
   dim3 grid(p.grid_x, p.grid_y, 1);
   hipLaunchKernelGGL(fn, grid, dim3(p.threads), 0, s, a);

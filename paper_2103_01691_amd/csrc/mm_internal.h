@@ -66,11 +66,11 @@ struct TileShape {
 // Kernel tables, one per precision (kern_<prec>.hip).  cls selects the tile
 // shape (0 default; 1, 2 regrouped waves for operators with at most 256 / 128
 // real rows; 3..6 alternative split shapes).  nullptr if no instance exists.
-KernFn pick_kernel_f64(int cplx, int ld, int pro, int epi, int cls);
-KernFn pick_kernel_f32(int cplx, int ld, int pro, int epi, int cls);
-KernFn pick_kernel_bf16x3(int cplx, int ld, int pro, int epi, int cls);
-KernFn pick_kernel_fp16x2(int cplx, int ld, int pro, int epi, int cls);
-KernFn pick_kernel_bf16(int cplx, int ld, int pro, int epi, int cls);
+KernFn pick_kernel_f64(int cplx, int ld, int pro, int epi, int cls, int full);
+KernFn pick_kernel_f32(int cplx, int ld, int pro, int epi, int cls, int full);
+KernFn pick_kernel_bf16x3(int cplx, int ld, int pro, int epi, int cls, int full);
+KernFn pick_kernel_fp16x2(int cplx, int ld, int pro, int epi, int cls, int full);
+KernFn pick_kernel_bf16(int cplx, int ld, int pro, int epi, int cls, int full);
 BatchFn pick_batch_f64(int cplx, int ld, int cls);
 BatchFn pick_batch_f32(int cplx, int ld, int cls);
 BatchFn pick_batch_bf16x3(int cplx, int ld, int cls);
@@ -92,6 +92,7 @@ struct ModePlan {
   int nt;              // fibres per workgroup
   int mt_rows;         // real rows covered by one workgroup (multiple of MB)
   bool covers_all_rows;
+  int full;            // every tile complete and output offsets fit 32 bits
 };
 
 // Fill `plan` for the given problem; returns false if no kernel fits.

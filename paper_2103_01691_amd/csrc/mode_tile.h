@@ -48,6 +48,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "mm_internal.h"
 
 namespace mm {
@@ -174,6 +176,13 @@ __device__ __forceinline__ int fp16x2_state_exp(uint32_t bits) {
 // on |r| <= pi/4, whose truncation errors (< 2e-9, < 2e-10) are below FP32
 // rounding.  Accurate to a few ulp for |x| up to ~1e5; needs no scratch.
 __device__ __forceinline__ void sincos_f32(float x, float* s, float* c) {
+  if (__all(fabsf(x) <= 0.78539816f)) {
+    // every active lane already in [-pi/4, pi/4]: no reduction needed
+    const float r2 = x * x;
+    *s = x * (1.0f + r2 * (-1.0f / 6 + r2 * (1.0f / 120 + r2 * (-1.0f / 5040 + r2 * (1.0f / 362880)))));
+    *c = 1.0f + r2 * (-0.5f + r2 * (1.0f / 24 + r2 * (-1.0f / 720 + r2 * (1.0f / 40320 + r2 * (-1.0f / 3628800)))));
+    return;
+  }
   constexpr double PIO2 = 1.57079632679489661923;
   constexpr float P1 = (float)PIO2;
   constexpr float P2 = (float)(PIO2 - (double)P1);
@@ -225,7 +234,8 @@ __device__ __forceinline__ int64_t fibre_base(int64_t f, int64_t P, int n, int c
 // One workgroup tile: fibres [tile_x * NT, tile_x * NT + NT), M-fragments of
 // row block tile_y.  WM x WN waves: wave (wm, wn) owns M-fragments
 // [(tile_y*WM + wm)*WMF, +WMF) and N-fragments [wn*WNF, +WNF) of the tile.
-template <int PR, bool CPLX, int LD, int WMF, int WNF, int WM, int WN, int KCH, bool PRO, bool EPI, int OCC>
+template <int PR, bool CPLX, int LD, int WMF, int WNF, int WM, int WN, int KCH, bool PRO, bool EPI, int OCC,
+          bool FULL = false>
 __device__ __forceinline__ void mode_tile(const ModeArgs& a, int64_t tile_x, int tile_y,
                                           typename Tr<PR>::pc* __restrict__ lds) {
   typedef Tr<PR> T;
@@ -246,7 +256,7 @@ __device__ __forceinline__ void mode_tile(const ModeArgs& a, int64_t tile_x, int
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
-  const int wave = tid >> 6;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int wm = wave % WM, wn = wave / WM;
   const int64_t f0 = tile_x * NT;
   const int mf0 = (tile_y * WM + wm) * WMF;   // first M-fragment of this wave
@@ -595,84 +605,153 @@ __device__ __forceinline__ void mode_tile(const ModeArgs& a, int64_t tile_x, int
   }
 
   // ------------------------------------------------------------- epilogue
-  st* __restrict__ out = (st*)a.out;
-  const st s_post = (st)a.s_post;
-  // output offset of this lane's fibre in each N-fragment (once per fragment)
-  int64_t obases[WNF];
-  bool fvalid[WNF];
-#pragma unroll
-  for (int j = 0; j < WNF; ++j) {
-    const int64_t fg = f0 + (nf0 + j) * NB + (lane % NB);
-    fvalid[j] = fg < a.F;
-    if constexpr (LD == KL_KCONTIG) {
-      obases[j] = fg * (int64_t)a.m * COMPS;
-    } else if (a.F <= 0x7fffffff) {
-      const uint32_t q = (uint32_t)fg / (uint32_t)a.P;
-      const uint32_t p = (uint32_t)fg - q * (uint32_t)a.P;
-      obases[j] = ((int64_t)p + a.P * (int64_t)a.m * q) * COMPS;
-    } else {
-      obases[j] = fibre_base(fg, a.P, a.m, COMPS);
-    }
-  }
-  const int64_t ostride = (LD == KL_KCONTIG) ? COMPS : a.P * COMPS;   // between entries i, i+1
   // FP16X2: the accumulators hold 2^11 * 2^-(s_exp + a_exp) * result
   const int o_exp = s_exp + a.a_exp - 11;
   float vmax = 0.0f;   // FP16X2: max |component| stored by this lane
-#pragma unroll
-  for (int i = 0; i < WMF; ++i) {
-    const int mf = mf0 + i;
+  if constexpr (FULL) {
+    // Every row and fibre of the tile exists and every byte offset of the
+    // output fits in 32 bits (checked by the planner): a store address is
+    // a wave-uniform base (row) plus a per-fragment lane offset (fibre).
+    st* __restrict__ out = (st*)a.out;
+    const st s_post = (st)a.s_post;
+    const int64_t ostride = (LD == KL_KCONTIG) ? COMPS : a.P * COMPS;   // between entries i, i+1
+    //  32x32 fragments: register 4q+r holds row 8q + 4(lane/32) + r.
+    //  16x16 FP64 fragments: register r holds row lane/16 + 4r (complex rows
+    //  permuted at preparation: (0,1) and (2,3) are entries mf*8 + lane/16
+    //  and that + 4).
+    const int lp = (MB == 32) ? (CPLX ? 2 : 4) * (lane / 32) : lane / 16;
+    uint32_t voff[WNF];
 #pragma unroll
     for (int j = 0; j < WNF; ++j) {
-      if (!fvalid[j]) continue;
-      const int64_t obase = obases[j];
-      // Rows of this lane, in groups of four accumulator registers.
-      //  32x32 fragments: register 4q+r holds row 8q + 4(lane/32) + r.
-      //  16x16 FP64 fragments: register r holds row lane/16 + 4r; for complex
-      //  operators the prepared rows are permuted so that registers (0,1)
-      //  and (2,3) are (re, im) of entries mf*8 + lane/16 and that + 4.
-      constexpr int GROUPS = T::NACC / 4;
+      const uint32_t fg = (uint32_t)(f0 + (nf0 + j) * NB + (lane % NB));
+      uint32_t ob;
+      if constexpr (LD == KL_KCONTIG) {
+        ob = fg * (uint32_t)(a.m * COMPS);
+      } else {
+        const uint32_t q = fg / (uint32_t)a.P;
+        const uint32_t p = fg - q * (uint32_t)a.P;
+        ob = (p + (uint32_t)a.P * (uint32_t)a.m * q) * COMPS;
+      }
+      voff[j] = (ob + (uint32_t)lp * (uint32_t)ostride) * (uint32_t)sizeof(st);
+    }
+    const int64_t obytes = ostride * (int64_t)sizeof(st);
+    typedef float f32x2 __attribute__((ext_vector_type(2)));
+    typedef typename std::conditional<sizeof(st) == 4, f32x2, f64x2>::type st2;
 #pragma unroll
-      for (int gq = 0; gq < GROUPS; ++gq) {
-        st v4[4];
+    for (int i = 0; i < WMF; ++i) {
+      const int mf = mf0 + i;
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          v4[r] = (st)acc[i][j][gq * 4 + r];
-          if constexpr (F16) v4[r] = ldexpf(v4[r], o_exp);
-        }
-        if constexpr (CPLX) {
-          int e0, e1;   // entries held as (v4[0], v4[1]) and (v4[2], v4[3])
-          if constexpr (MB == 32) {
-            e0 = (mf * 32 + 8 * gq + 4 * (lane / 32)) / 2;
-            e1 = e0 + 1;
-          } else {
-            e0 = mf * 8 + lane / 16;
-            e1 = e0 + 4;
-          }
-          if constexpr (EPI) {
-            phase<st>(v4[0], v4[1], s_post);
-            phase<st>(v4[2], v4[3], s_post);
-          }
+      for (int j = 0; j < WNF; ++j) {
+        constexpr int GROUPS = T::NACC / 4;
 #pragma unroll
-          for (int h = 0; h < 2; ++h) {
-            const int ie = h ? e1 : e0;
-            if (ie < a.m) {
-              if constexpr (F16) vmax = fmaxf(vmax, fmaxf(fabsf(v4[2 * h]), fabsf(v4[2 * h + 1])));
-              st* dst = out + obase + (int64_t)ie * ostride;
-              if constexpr (sizeof(st) == 4) {
-                typedef float f32x2 __attribute__((ext_vector_type(2)));
-                *(f32x2*)dst = f32x2{v4[2 * h], v4[2 * h + 1]};
-              } else {
-                *(f64x2*)dst = f64x2{v4[2 * h], v4[2 * h + 1]};
-              }
-            }
-          }
-        } else {
+        for (int gq = 0; gq < GROUPS; ++gq) {
+          st v4[4];
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
-            const int ie = (MB == 32) ? mf * 32 + 8 * gq + 4 * (lane / 32) + r : mf * 16 + lane / 16 + 4 * r;
-            if (ie < a.m) {
+            v4[r] = (st)acc[i][j][gq * 4 + r];
+            if constexpr (F16) v4[r] = ldexpf(v4[r], o_exp);
+          }
+          if constexpr (CPLX) {
+            if constexpr (EPI) {
+              phase<st>(v4[0], v4[1], s_post);
+              phase<st>(v4[2], v4[3], s_post);
+            }
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+              const int u = (MB == 32) ? mf * 16 + 4 * gq + h : mf * 8 + 4 * h;
+              if constexpr (F16) vmax = fmaxf(vmax, fmaxf(fabsf(v4[2 * h]), fabsf(v4[2 * h + 1])));
+              char* sb = (char*)out + (int64_t)u * obytes;
+              *(st2*)(sb + voff[j]) = st2{v4[2 * h], v4[2 * h + 1]};
+            }
+          } else {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+              const int u = (MB == 32) ? mf * 32 + 8 * gq + r : mf * 16 + 4 * r;
               if constexpr (F16) vmax = fmaxf(vmax, fabsf(v4[r]));
-              out[obase + (int64_t)ie * ostride] = v4[r];
+              char* sb = (char*)out + (int64_t)u * obytes;
+              *(st*)(sb + voff[j]) = v4[r];
+            }
+          }
+        }
+      }
+    }
+  } else {
+    st* __restrict__ out = (st*)a.out;
+    const st s_post = (st)a.s_post;
+    // output offset of this lane's fibre in each N-fragment (once per fragment)
+    int64_t obases[WNF];
+    bool fvalid[WNF];
+  #pragma unroll
+    for (int j = 0; j < WNF; ++j) {
+      const int64_t fg = f0 + (nf0 + j) * NB + (lane % NB);
+      fvalid[j] = fg < a.F;
+      if constexpr (LD == KL_KCONTIG) {
+        obases[j] = fg * (int64_t)a.m * COMPS;
+      } else if (a.F <= 0x7fffffff) {
+        const uint32_t q = (uint32_t)fg / (uint32_t)a.P;
+        const uint32_t p = (uint32_t)fg - q * (uint32_t)a.P;
+        obases[j] = ((int64_t)p + a.P * (int64_t)a.m * q) * COMPS;
+      } else {
+        obases[j] = fibre_base(fg, a.P, a.m, COMPS);
+      }
+    }
+    const int64_t ostride = (LD == KL_KCONTIG) ? COMPS : a.P * COMPS;   // between entries i, i+1
+  #pragma unroll
+    for (int i = 0; i < WMF; ++i) {
+      const int mf = mf0 + i;
+  #pragma unroll
+      for (int j = 0; j < WNF; ++j) {
+        if (!fvalid[j]) continue;
+        const int64_t obase = obases[j];
+        // Rows of this lane, in groups of four accumulator registers.
+        //  32x32 fragments: register 4q+r holds row 8q + 4(lane/32) + r.
+        //  16x16 FP64 fragments: register r holds row lane/16 + 4r; for complex
+        //  operators the prepared rows are permuted so that registers (0,1)
+        //  and (2,3) are (re, im) of entries mf*8 + lane/16 and that + 4.
+        constexpr int GROUPS = T::NACC / 4;
+  #pragma unroll
+        for (int gq = 0; gq < GROUPS; ++gq) {
+          st v4[4];
+  #pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            v4[r] = (st)acc[i][j][gq * 4 + r];
+            if constexpr (F16) v4[r] = ldexpf(v4[r], o_exp);
+          }
+          if constexpr (CPLX) {
+            int e0, e1;   // entries held as (v4[0], v4[1]) and (v4[2], v4[3])
+            if constexpr (MB == 32) {
+              e0 = (mf * 32 + 8 * gq + 4 * (lane / 32)) / 2;
+              e1 = e0 + 1;
+            } else {
+              e0 = mf * 8 + lane / 16;
+              e1 = e0 + 4;
+            }
+            if constexpr (EPI) {
+              phase<st>(v4[0], v4[1], s_post);
+              phase<st>(v4[2], v4[3], s_post);
+            }
+  #pragma unroll
+            for (int h = 0; h < 2; ++h) {
+              const int ie = h ? e1 : e0;
+              if (ie < a.m) {
+                if constexpr (F16) vmax = fmaxf(vmax, fmaxf(fabsf(v4[2 * h]), fabsf(v4[2 * h + 1])));
+                st* dst = out + obase + (int64_t)ie * ostride;
+                if constexpr (sizeof(st) == 4) {
+                  typedef float f32x2 __attribute__((ext_vector_type(2)));
+                  *(f32x2*)dst = f32x2{v4[2 * h], v4[2 * h + 1]};
+                } else {
+                  *(f64x2*)dst = f64x2{v4[2 * h], v4[2 * h + 1]};
+                }
+              }
+            }
+          } else {
+  #pragma unroll
+            for (int r = 0; r < 4; ++r) {
+              const int ie = (MB == 32) ? mf * 32 + 8 * gq + 4 * (lane / 32) + r : mf * 16 + lane / 16 + 4 * r;
+              if (ie < a.m) {
+                if constexpr (F16) vmax = fmaxf(vmax, fabsf(v4[r]));
+                out[obase + (int64_t)ie * ostride] = v4[r];
+              }
             }
           }
         }
@@ -689,13 +768,14 @@ __device__ __forceinline__ void mode_tile(const ModeArgs& a, int64_t tile_x, int
   }
 }
 
-template <int PR, bool CPLX, int LD, int WMF, int WNF, int WM, int WN, int KCH, bool PRO, bool EPI, int OCC>
+template <int PR, bool CPLX, int LD, int WMF, int WNF, int WM, int WN, int KCH, bool PRO, bool EPI, int OCC,
+          bool FULL>
 __global__ __launch_bounds__(64 * WM * WN) __attribute__((amdgpu_waves_per_eu(OCC, OCC)))
 void mode_kernel(ModeArgs a) {
   typedef typename Tr<PR>::pc pc;
   constexpr int CHUNK = KCH * WN * WNF * Tr<PR>::NPB * 64 * Tr<PR>::KPL;
   __shared__ __attribute__((aligned(16))) pc lds[2 * CHUNK];
-  mode_tile<PR, CPLX, LD, WMF, WNF, WM, WN, KCH, PRO, EPI, OCC>(a, blockIdx.x, blockIdx.y, lds);
+  mode_tile<PR, CPLX, LD, WMF, WNF, WM, WN, KCH, PRO, EPI, OCC, FULL>(a, blockIdx.x, blockIdx.y, lds);
 }
 
 template <int PR, bool CPLX, int LD, int WMF, int WNF, int WM, int WN, int KCH>
@@ -750,10 +830,16 @@ template <int PR, int CLS> TileShape shape_of() {
   return TileShape{C::WMF, C::WNF, C::WM, C::WN, C::KCH, C::OCC};
 }
 
-template <int PR, bool CPLX, int LD, bool PRO, bool EPI, int CLS>
+template <int PR, bool CPLX, int LD, bool PRO, bool EPI, int CLS, bool FULL = false>
 KernFn kfn() {
   typedef Cfg<PR, CLS> C;
-  return &mode_kernel<PR, CPLX, LD, C::WMF, C::WNF, C::WM, C::WN, C::KCH, PRO, EPI, C::OCC>;
+  return &mode_kernel<PR, CPLX, LD, C::WMF, C::WNF, C::WM, C::WN, C::KCH, PRO, EPI, C::OCC, FULL>;
+}
+
+// Full-tile variant when the planner allows it.
+template <int PR, bool CPLX, int LD, bool PRO, bool EPI, int CLS>
+KernFn kfx(int full) {
+  return full ? kfn<PR, CPLX, LD, PRO, EPI, CLS, true>() : kfn<PR, CPLX, LD, PRO, EPI, CLS, false>();
 }
 
 template <int PR, bool CPLX, int LD, int CLS>
@@ -765,15 +851,17 @@ BatchFn bfn() {
 // Kernel table of one precision.  Instances that exist: every (complex,
 // load, prologue, epilogue) in class 0; classes 1, 2 without phases and not
 // for the generic gather; classes >= 3 only for complex split kernels with
-// contiguous or strided fibres.
+// contiguous or strided fibres.  Classes 0 and >= 3 also have a full-tile
+// variant (full != 0: no per-store bounds checks, 32-bit output offsets) for
+// contiguous and strided fibres.
 template <int PR>
-KernFn pick_kernel(int cplx, int ld, int pro, int epi, int cls) {
+KernFn pick_kernel(int cplx, int ld, int pro, int epi, int cls, int full) {
 #define MM_PH(C_, L_, K_)                                                     \
   do {                                                                        \
-    if (pro && epi) return kfn<PR, C_, L_, true, true, K_>();                \
-    if (pro) return kfn<PR, C_, L_, true, false, K_>();                      \
-    if (epi) return kfn<PR, C_, L_, false, true, K_>();                      \
-    return kfn<PR, C_, L_, false, false, K_>();                              \
+    if (pro && epi) return kfx<PR, C_, L_, true, true, K_>(full);            \
+    if (pro) return kfx<PR, C_, L_, true, false, K_>(full);                  \
+    if (epi) return kfx<PR, C_, L_, false, true, K_>(full);                  \
+    return kfx<PR, C_, L_, false, false, K_>(full);                          \
   } while (0)
   if (cls == 1 || cls == 2) {
     if (pro || epi || ld == KL_GENERIC) return nullptr;
@@ -800,12 +888,12 @@ KernFn pick_kernel(int cplx, int ld, int pro, int epi, int cls) {
     switch (ld) {
       case KL_KCONTIG: MM_PH(true, KL_KCONTIG, 0);
       case KL_FCONTIG: MM_PH(true, KL_FCONTIG, 0);
-      default: MM_PH(true, KL_GENERIC, 0);
+      default: full = 0; MM_PH(true, KL_GENERIC, 0);
     }
   }
   switch (ld) {
-    case KL_KCONTIG: return kfn<PR, false, KL_KCONTIG, false, false, 0>();
-    case KL_FCONTIG: return kfn<PR, false, KL_FCONTIG, false, false, 0>();
+    case KL_KCONTIG: return kfx<PR, false, KL_KCONTIG, false, false, 0>(full);
+    case KL_FCONTIG: return kfx<PR, false, KL_FCONTIG, false, false, 0>(full);
     default: return kfn<PR, false, KL_GENERIC, false, false, 0>();
   }
 #undef MM_PH
