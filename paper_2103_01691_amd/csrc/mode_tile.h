@@ -571,13 +571,17 @@ __device__ __forceinline__ void mode_tile(const ModeArgs& a, int64_t tile_x, int
         finish_a(a_buf[cur]);
         __builtin_amdgcn_sched_barrier(0);
         mfma_kblock(a_buf[cur], b_buf[cur]);
-        __builtin_amdgcn_sched_barrier(0);
+        if (kk + 1 < KCH) {
+          __builtin_amdgcn_sched_barrier(0);
+        } else {
+          // split and LDS writes of the next chunk, free to interleave with
+          // this K-block's MFMAs (on the last chunk this rewrites the idle
+          // buffer with stale data nobody reads)
+          store_chunk(buf ^ 1);
+        }
       }
-      if (more) {
-        store_chunk(buf ^ 1);
-        __syncthreads();
-        read_b(lds + (buf ^ 1) * CHUNK, 0, b_buf[0]);
-      }
+      __syncthreads();
+      read_b(lds + (buf ^ 1) * CHUNK, 0, b_buf[0]);
     }
   } else {
     // Two workgroups share each CU (register budget of two waves per SIMD):
