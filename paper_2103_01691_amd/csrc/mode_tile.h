@@ -398,13 +398,6 @@ __device__ __forceinline__ void mode_tile(const ModeArgs& a, int64_t tile_x, int
           }
         }
       }
-      if constexpr (PRO && CPLX) {
-        // entries (kappa even, odd) of one fibre are (re, im) of one value
-#pragma unroll
-        for (int fi = 0; fi < TF; ++fi)
-#pragma unroll
-          for (int kl = 0; kl < TK; kl += 2) phase<st>(v[kl * TF + fi], v[(kl + 1) * TF + fi], s_pre);
-      }
     }
   };
 
@@ -418,7 +411,16 @@ __device__ __forceinline__ void mode_tile(const ModeArgs& a, int64_t tile_x, int
       tile_coords(tid + u * THREADS, tk, tf);
       const int kl0 = tk * TK;
       const int fl0 = tf * TF;
-      const st* v = stage[u];
+      st* v = stage[u];
+      if constexpr (PRO && CPLX) {
+        // prologue phase, applied as the tile is staged (not when it is
+        // fetched, so the wave does not wait for the fetch early); entries
+        // (kappa even, odd) of one fibre are (re, im) of one value
+#pragma unroll
+        for (int fi = 0; fi < TF; ++fi)
+#pragma unroll
+          for (int kl = 0; kl < TK; kl += 2) phase<st>(v[kl * TF + fi], v[(kl + 1) * TF + fi], s_pre);
+      }
       if constexpr (KPL == 8) {
         // each fibre of the tile gets 8 consecutive K values = one lane slot
         const int kb = kl0 / KB;

@@ -589,10 +589,13 @@ mm_status gpe_strang_step(mm_ctx ctx, mm_tensor* psi, const mm_op* E, double tau
   }
   HIPCHK(ctx, hipSetDevice(ctx->device));
   ctx->chain_end = nullptr;
+  // merged steps: N(tau/2) [L N(tau)]^(nsteps-1) L N(tau/2); each N(tau)
+  // between steps is fused into the staging of the next step's first product
+  // (where it overlaps MFMA work), the last N(tau/2) into the final epilogue
   const double half = 0.5 * tau * beta, full = tau * beta;
   for (int it = 0; it < nsteps; ++it) {
-    const double pre = (it == 0) ? half : 0.0;
-    const double post = (it + 1 < nsteps) ? full : half;
+    const double pre = (it == 0) ? half : full;
+    const double post = (it + 1 < nsteps) ? 0.0 : half;
     st = sweep(ctx, psi, E, pre, post, (hipStream_t)stream);
     if (st != MM_OK) return st;
   }
