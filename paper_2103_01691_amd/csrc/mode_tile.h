@@ -175,8 +175,9 @@ __device__ __forceinline__ int fp16x2_state_exp(uint32_t bits) {
 // the FP64 value), then the Taylor series of sin (to x^9) and cos (to x^10)
 // on |r| <= pi/4, whose truncation errors (< 2e-9, < 2e-10) are below FP32
 // rounding.  Accurate to a few ulp for |x| up to ~1e5; needs no scratch.
+template <bool VOTE = true>
 __device__ __forceinline__ void sincos_f32(float x, float* s, float* c) {
-  if (__all(fabsf(x) <= 0.78539816f)) {
+  if (VOTE && __all(fabsf(x) <= 0.78539816f)) {
     // every active lane already in [-pi/4, pi/4]: no reduction needed
     const float r2 = x * x;
     *s = x * (1.0f + r2 * (-1.0f / 6 + r2 * (1.0f / 120 + r2 * (-1.0f / 5040 + r2 * (1.0f / 362880)))));
@@ -201,15 +202,17 @@ __device__ __forceinline__ void sincos_f32(float x, float* s, float* c) {
   *c = ((qi + 1) & 2) ? -cc : cc;
 }
 
-// exp(-i s |z|^2) z
-template <typename T>
+// exp(-i s |z|^2) z.  VOTE: take the reduction-free path when every active
+// lane allows it (a wave-uniform branch); without it the code is branch-free
+// and can be interleaved with MFMA work by the scheduler.
+template <typename T, bool VOTE = true>
 __device__ __forceinline__ void phase(T& re, T& im, T s) {
   T th = s * (re * re + im * im);
   T sn, cs;
   if constexpr (sizeof(T) == 8) {
     sincos(th, &sn, &cs);
   } else {
-    sincos_f32(th, &sn, &cs);
+    sincos_f32<VOTE>(th, &sn, &cs);
   }
   T r = re * cs + im * sn;
   T i = im * cs - re * sn;
@@ -419,7 +422,7 @@ __device__ __forceinline__ void mode_tile(const ModeArgs& a, int64_t tile_x, int
 #pragma unroll
         for (int fi = 0; fi < TF; ++fi)
 #pragma unroll
-          for (int kl = 0; kl < TK; kl += 2) phase<st>(v[kl * TF + fi], v[(kl + 1) * TF + fi], s_pre);
+          for (int kl = 0; kl < TK; kl += 2) phase<st, false>(v[kl * TF + fi], v[(kl + 1) * TF + fi], s_pre);
       }
       if constexpr (KPL == 8) {
         // each fibre of the tile gets 8 consecutive K values = one lane slot
