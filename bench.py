@@ -128,6 +128,86 @@ def time_path(ctx, mm, torch, E, psi0_np, prec, steps, warmup, profile, tune_ms=
     return ms / steps, wall, recs, tuned
 
 
+def timed(torch, fn, reps):
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record()
+    fn(reps)
+    ev1.record()
+    torch.cuda.synchronize()
+    return ev0.elapsed_time(ev1) * 1e-3
+
+
+def other_workloads(ctx, mm, torch):
+    """Throughput of the other scope workloads (their parity is tested in
+    tests/); not the headline metric."""
+    import synth
+    out = {}
+    # batched: 512 instances of the mixed heat / Schroedinger workload, one
+    # exponential step each, FP32, one captured graph per step; operators
+    # shared per (kind, n) at tau = 1e-3 (the step's cost does not depend on tau)
+    mix = synth.batch_mix(512, cfg_id=5)
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(5)
+    cache, tensors, ops = {}, [], []
+    ideal = 0.0
+    for inst in mix:
+        cplx = inst["kind"] == "schrodinger"
+        row = []
+        for n in inst["dims"]:
+            key = (inst["kind"], n)
+            if key not in cache:
+                if cplx:
+                    E = mm.expm(mm.fd2_matrix(n, -10.0, 10.0), 0.5j * 1e-3)
+                else:
+                    E = mm.expm(mm.fd2_matrix(n, 0.0, 1.0), 1e-3).real.copy()
+                cache[key] = ctx.mm_op_prepare(E, "fp32")
+            row.append(cache[key])
+        ops.append(row)
+        shape = tuple(reversed(inst["dims"]))
+        tensors.append(torch.randn(shape, dtype=torch.complex64 if cplx else torch.float32, device="cuda",
+                                   generator=gen))
+        N = float(np.prod(inst["dims"]))
+        for n in inst["dims"]:
+            flops = (8.0 if cplx else 2.0) * n * N
+            nbytes = 2.0 * N * (8 if cplx else 4)
+            ideal += max(flops / PEAK["fp32"], nbytes / PEAK["hbm"])
+    ctx.mumode_expstep_batched(tensors, ops, 1)               # capture + first replay
+    K = 20
+    t = timed(torch, lambda k: ctx.mumode_expstep_batched(tensors, ops, k), K)
+    out["batch512_fp32"] = {"instances_per_s": 512 * K / t, "ms_per_batch_step": 1e3 * t / K,
+                            "roofline_frac": ideal / (t / K),
+                            "roofline": "sum over instances of max(flops / FP32 MFMA peak, bytes / HBM peak)"}
+    del tensors
+    # harmonic oscillator, Hermite n = 128, complex64, time-dependent potential
+    m = 128
+    Xl, _ = mm.hermite_nodes(m)
+    for prec in ("fp32", "fp16x2"):
+        Lh = ctx.mm_op_prepare(mm.hermite_ho_exponential(m, 0.02), prec)
+        psi = torch.randn((m, m, m), dtype=torch.complex64, device="cuda", generator=gen)
+        ctx.ho_strang_step(psi, [Lh] * 3, [Xl] * 3, 0.0, 0.02, 0.1, 2)
+        K = 50
+        t = timed(torch, lambda k: ctx.ho_strang_step(psi, [Lh] * 3, [Xl] * 3, 0.0, 0.02, 0.1, k), K)
+        out[f"ho128_{prec}"] = {"steps_per_s": K / t, "ms_per_step": 1e3 * t / K,
+                                "tflops_effective": 3 * 8.0 * m * m ** 3 / (t / K) / 1e12}
+        Lh.destroy()
+        del psi
+    # heat, d = 2, n = 64, FP64, 20 steps per call (launch-latency bound)
+    E = mm.expm(mm.fd2_matrix(64, 0.0, 1.0), 1e-3).real.copy()
+    Eop = ctx.mm_op_prepare(E, "fp64")
+    u = torch.rand((64, 64), dtype=torch.float64, device="cuda", generator=gen)
+    ctx.mumode_expstep(u, [Eop] * 2, 20)
+    K = 20
+    t = timed(torch, lambda k: [ctx.mumode_expstep(u, [Eop] * 2, 20) for _ in range(k)], K)
+    out["heat64x64_fp64_20steps"] = {"calls_per_s": K / t, "us_per_step": 1e6 * t / (20 * K)}
+    for o in cache.values():
+        o.destroy()
+    Eop.destroy()
+    torch.cuda.empty_cache()
+    return out
+
+
 def cpu_baseline(psi0, nsteps):
     from oracle import operators as op
     from oracle import schemes as sc
@@ -151,6 +231,7 @@ def main():
     ap.add_argument("--tune-ms", type=int, default=1500, help="autotuner budget per path (0: built-in tiles)")
     ap.add_argument("--tune-file", default=None,
                     help="timed path: load the tile choice from this file if it exists, else tune and save it")
+    ap.add_argument("--no-workloads", action="store_true", help="skip the batched / HO / heat side measurements")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="after timing, run one plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -188,6 +269,11 @@ def main():
             pms, _, _, _ = time_path(ctx, mm, torch, E, psi0, prec, k, 5, False, args.tune_ms)
             side[prec] = {"ms_per_step": pms, "steps_per_s": 1e3 / pms,
                           "tflops_effective": FLOPS_PER_STEP / (pms * 1e-3) / 1e12}
+
+    workloads = None
+    if not args.no_workloads:
+        log("timing the other workloads (batched, harmonic oscillator, small heat)")
+        workloads = other_workloads(ctx, mm, torch)
 
     if args.calib_copy_mb > 0:
         # a plain copy kernel of known size: its FETCH_SIZE / WRITE_SIZE
@@ -249,6 +335,7 @@ def main():
         "speedup_vs_fp64": (side["fp64"]["ms_per_step"] / ms) if "fp64" in side else None,
         "parity_rel_l2_vs_oracle": parity,
         "cpu_baseline": cpu,
+        "other_workloads": workloads,
         "wall_s_timed": wall,
     }
     print(json.dumps(out), flush=True)
