@@ -133,3 +133,23 @@ def hermite_backward(m: int) -> np.ndarray:
     spec2real, evaluation points = quadrature nodes)."""
     X = hermite_nodes(m)
     return hermite_functions(m, X).T.copy()
+
+
+def hermite_ho_generator(m: int) -> np.ndarray:
+    """(i/2)(d^2/dx^2 - x^2) in nodal Hermite space: Psi diag(-i (k + 1/2)) Phi
+    (phi_k is an eigenfunction of d^2/dx^2 - x^2 with eigenvalue -(2k+1),
+    Section 3)."""
+    Phi, Psi = hermite_forward(m), hermite_backward(m)
+    return Psi @ np.diag(-1j * (np.arange(m) + 0.5)) @ Phi
+
+
+def hkmp_problem(m: int):
+    """Mode generators of the time-dependent Schroedinger problem of Section
+    4.3 in nodal Hermite space: psi_t = (i/2)(Laplace - |x|^2 - 2 x_3 sin^2 t) psi,
+    i.e. A_mu = hermite_ho_generator for every mode plus, on mode 3,
+    -i sin^2(t) diag(x_3).  Returns (B, d, g) for schemes.magnus_midpoint."""
+    X = hermite_nodes(m)
+    Bm = hermite_ho_generator(m)
+    B = [Bm, Bm, Bm]
+    d = [None, None, X]
+    return B, d, (lambda mu, t: -1j * np.sin(t) ** 2 if mu == 2 else 0.0)

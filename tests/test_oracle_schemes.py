@@ -148,3 +148,69 @@ def test_energy_of_fd_eigenvectors():
     e1 = sc.energy_gpe(psi, [H, H, H], beta, h ** 3)
     quartic = np.prod([np.sum(v ** 4) for v in vs]) * h ** 3
     assert abs(e1 - e0 - 0.5 * beta * quartic) < 1e-11
+
+
+# ------------------------------------------- exponential midpoint rule ----
+
+def test_magnus_without_time_dependence_is_exact_ho():
+    m, tau = 10, 0.3
+    Phi, Psi, X = _ho_mats(m)
+    B = [op.hermite_ho_generator(m)] * 3
+    g = synth.rng(211, 0)
+    psi = synth.random_tensor((m, m, m), True, g)
+    got = sc.magnus_midpoint(psi, B, [None] * 3, lambda mu, t: 0.0, tau, 2)
+    ref = sc.ho_linear(sc.ho_linear(psi, [Phi] * 3, [Psi] * 3, tau), [Phi] * 3, [Psi] * 3, tau)
+    assert _rel(got, ref) < 1e-12
+
+
+def test_magnus_constant_generator_exact_in_time():
+    m, tau = 8, 0.4
+    B, d, _ = op.hkmp_problem(m)
+    g = synth.rng(212, 0)
+    psi = synth.random_tensor((m, m, m), True, g)
+    const = lambda mu, t: (-0.3j if mu == 2 else 0.0)
+    one = sc.magnus_midpoint(psi, B, d, const, tau, 1)
+    five = sc.magnus_midpoint(psi, B, d, const, tau / 5, 5)
+    assert _rel(five, one) < 1e-12
+
+
+def test_magnus_second_order_against_ode_solution():
+    # 1-D mode-3 problem u' = (B + g(t) diag(x)) u, solved to high accuracy
+    # by an adaptive Runge-Kutta method, against the exponential midpoint rule
+    from scipy.integrate import solve_ivp
+    m, T = 10, 1.0
+    B, d, gf = op.hkmp_problem(m)
+    A0, X = B[2], d[2]
+    g = synth.rng(213, 0)
+    u0 = g.standard_normal(m) + 1j * g.standard_normal(m)
+    sol = solve_ivp(lambda t, u: (A0 + gf(2, t) * np.diag(X)) @ u, (0.0, T), u0, method="DOP853",
+                    rtol=1e-13, atol=1e-13)
+    exact = sol.y[:, -1]
+
+    def run(k):
+        u = u0.reshape(m, 1, 1)
+        out = sc.magnus_midpoint(u, [A0, None, None], [X, None, None],
+                                 lambda mu, t: gf(2, t) if mu == 0 else 0.0, T / k, k)
+        return out.reshape(m)
+
+    e1 = np.linalg.norm(run(16) - exact)
+    e2 = np.linalg.norm(run(32) - exact)
+    assert e2 < 1e-3 * np.linalg.norm(exact)
+    assert 3.5 < e1 / e2 < 4.5
+
+
+def test_magnus_product_state_is_product_of_mode_steps():
+    m, tau = 7, 0.2
+    B, d, gf = op.hkmp_problem(m)
+    g = synth.rng(214, 0)
+    v = [g.standard_normal(m) + 1j * g.standard_normal(m) for _ in range(3)]
+    psi = np.einsum("i,j,k->ijk", *v)
+    got = sc.magnus_midpoint(psi, B, d, gf, tau, 3, t0=0.1)
+    w = []
+    for mu in range(3):
+        u = v[mu].reshape(m, 1, 1)
+        Bs = [B[mu], None, None]
+        ds = [d[mu], None, None]
+        w.append(sc.magnus_midpoint(u, Bs, ds, lambda nu, t, mu=mu: gf(mu, t) if nu == 0 else 0.0,
+                                    tau, 3, t0=0.1).reshape(m))
+    assert _rel(got, np.einsum("i,j,k->ijk", *w)) < 1e-12
