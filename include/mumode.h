@@ -188,6 +188,39 @@ mm_status ho_strang_step(mm_ctx ctx, mm_tensor* psi, const mm_op* Lh, const doub
 mm_status mumode_expstep_batched(mm_ctx ctx, int count, mm_tensor* const* T, const mm_op* const* E, int nsteps,
                                  mm_stream stream);
 
+/* Exponential midpoint rule (the second-order Magnus integrator of Section
+ * 4.3, equation mag2) for u' = A(t) u with A(t) in Kronecker-sum form whose
+ * mode parts depend on time as A_mu(t) = B_mu + g_mu(t) diag(d_mu):
+ * each step u <- exp(tau A(t_n + tau/2)) u is the mu-mode integrator with
+ * E_mu = exp(tau A_mu(t_n + tau/2)) (the exponential of a Kronecker sum is
+ * the Kronecker product of the mode exponentials, Section 2).  The
+ * exponentials of the time-dependent modes are formed on the device every
+ * step in FP64 (scaling and squaring of the Taylor polynomial, products on
+ * FP64 MFMA, as mm_expm_device), prepared in `prec` and applied; modes
+ * without a time-dependent part are exponentiated once per call.
+ *   B[k]   : n_k x n_k FP64 master (MM_C128 or MM_R64, host or device);
+ *            B[k].data == NULL leaves mode k+1 unchanged.
+ *   d      : NULL, or d[k] a host array of n_k reals (NULL: no
+ *            time-dependent part on mode k+1).
+ *   g      : host array of nsteps * T->d complex coefficients (re, im),
+ *            g[2*(n*d + k)] = Re g_{k+1}(t_n + tau/2); may be NULL when no
+ *            mode has a time-dependent part.  The caller evaluates them.
+ * T is complex (MM_C128 with MM_PREC_FP64, MM_C64 otherwise), in place.
+ * Allocates per-call device buffers (freed before returning, which
+ * synchronises the device). */
+mm_status mumode_magnus_step(mm_ctx ctx, mm_tensor* T, const mm_matrix* B, const double* const* d, const double* g,
+                             double tau, int nsteps, mm_prec prec, mm_stream stream);
+
+/* exp(c A) of a complex n x n FP64 matrix on the device (A, out: device
+ * pointers, column-major interleaved, leading dimension n, not
+ * overlapping): scaling to ||c A / 2^q||_1 <= 1, the degree-18 Taylor
+ * polynomial by Horner's rule (truncation below 2.2e-17), q squarings; each
+ * matrix product runs on the FP64 MFMA mode-product kernel (the Taylor
+ * approach Section 5.3 uses on the GPU).  Computes ||A||_1 on the device and
+ * synchronises `stream`. */
+mm_status mm_expm_device(mm_ctx ctx, int n, const double* A, double c_re, double c_im, double* out,
+                         mm_stream stream);
+
 /* Discrete GPE energy cell * [Re sum conj(psi) (sum_mu psi x_mu H[mu-1])
  * + (beta/2) sum |psi|^4], FP64 accumulation on the device; H[k] are the 1-D
  * Hamiltonians prepared in psi's precision.  Synchronises `stream`. */

@@ -240,6 +240,50 @@ class Context:
                   "mm_norm2")
         return out.value
 
+    def mumode_magnus_step(self, T, B, d, g, tau: float, nsteps: int = 1, prec="fp64", stream=None):
+        """B: list of n_k x n_k numpy matrices (None: mode unchanged); d: list of
+        real node arrays or None; g: array (nsteps, T.d) of complex coefficients
+        at the step midpoints (or None)."""
+        prec = PRECISIONS[prec] if isinstance(prec, str) else int(prec)
+        t = as_mm_tensor(T)
+        k = len(B)
+        mats = (_lib.MMMatrix * k)()
+        keep = []
+        for i, Bm in enumerate(B):
+            if Bm is None:
+                mats[i].data = None
+                continue
+            F = np.asfortranarray(np.asarray(Bm, dtype=np.complex128))
+            keep.append(F)
+            mats[i].rows, mats[i].cols = F.shape
+            mats[i].ld = F.shape[0]
+            mats[i].dtype = MM_C128
+            mats[i].data = F.ctypes.data
+            mats[i].on_device = 0
+        darr = None
+        if d is not None:
+            dk = [np.ascontiguousarray(np.asarray(x, dtype=np.float64)) if x is not None else None for x in d]
+            keep.extend(x for x in dk if x is not None)
+            darr = (C.POINTER(C.c_double) * k)(*[x.ctypes.data_as(C.POINTER(C.c_double)) if x is not None else None
+                                                 for x in dk])
+        garr = None
+        if g is not None:
+            G = np.ascontiguousarray(np.asarray(g, dtype=np.complex128).reshape(nsteps, k))
+            keep.append(G)
+            garr = G.ctypes.data_as(C.POINTER(C.c_double))
+        self._chk(_lib.lib.mumode_magnus_step(self.handle, C.byref(t), mats, darr, garr, float(tau), nsteps, prec,
+                                              _stream(stream)), "mumode_magnus_step")
+        return T
+
+    def mm_expm_device(self, A, c: complex, out, stream=None):
+        """A, out: torch complex128 CUDA tensors holding column-major n x n
+        matrices (e.g. the transpose view .T of a row-major matrix's storage)."""
+        n = A.shape[0]
+        c = complex(c)
+        self._chk(_lib.lib.mm_expm_device(self.handle, n, C.c_void_p(A.data_ptr()), c.real, c.imag,
+                                          C.c_void_p(out.data_ptr()), _stream(stream)), "mm_expm_device")
+        return out
+
     # ------------------------------------------------- tuning, memory ----
     def mm_autotune(self, T, E, budget_ms: int = 1000, stream=None):
         t = as_mm_tensor(T)

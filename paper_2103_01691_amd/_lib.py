@@ -27,7 +27,7 @@ EXPORTS = [
     "mumode_expstep_batched",
     "mm_fd2_matrix", "mm_expm", "mm_hermite_nodes", "mm_hermite_matrices",
     "mm_autotune", "mm_tune_count", "mm_tune_get", "mm_tune_clear", "mm_tune_save", "mm_tune_load",
-    "mm_set_workspace",
+    "mm_set_workspace", "mumode_magnus_step", "mm_expm_device",
 ]
 
 
@@ -83,6 +83,9 @@ def _load():
         "mm_tune_save": (st, [P, C.c_char_p]),
         "mm_tune_load": (st, [P, C.c_char_p]),
         "mm_set_workspace": (st, [P, P, C.c_size_t]),
+        "mumode_magnus_step": (st, [P, C.POINTER(MMTensor), C.POINTER(MMMatrix), C.POINTER(C.POINTER(d)),
+                                    C.POINTER(d), d, C.c_int, C.c_int, P]),
+        "mm_expm_device": (st, [P, C.c_int, P, d, d, P, P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)

@@ -170,6 +170,53 @@ __global__ __launch_bounds__(NORM_THREADS) void maxabs_final_kernel(const uint32
   if (threadIdx.x < 3) slots[threadIdx.x] = threadIdx.x == 0 ? red[0] : 0u;
 }
 
+// ------------------------------------------------------ device expm ------
+// Helpers of the device matrix exponential (complex FP64, column-major,
+// interleaved (re, im), n x n, leading dimension n).
+
+// X = f (A + g diag(d)) with complex f, g; d real (nullable)
+__global__ void expm_generator_kernel(const double* __restrict__ A, int n, const double* __restrict__ d,
+                                      double gr, double gi, double fr, double fi, double* __restrict__ X) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (int64_t)n * n) return;
+  const int i = (int)(e % n), j = (int)(e / n);
+  double re = A[2 * e], im = A[2 * e + 1];
+  if (d && i == j) {
+    re += gr * d[i];
+    im += gi * d[i];
+  }
+  X[2 * e] = fr * re - fi * im;
+  X[2 * e + 1] = fr * im + fi * re;
+}
+
+// T = I + f W (f real); W == nullptr: T = I
+__global__ void expm_horner_kernel(double* __restrict__ T, const double* __restrict__ W, int n, double f) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (int64_t)n * n) return;
+  const int i = (int)(e % n), j = (int)(e / n);
+  const double one = i == j ? 1.0 : 0.0;
+  T[2 * e] = one + (W ? f * W[2 * e] : 0.0);
+  T[2 * e + 1] = W ? f * W[2 * e + 1] : 0.0;
+}
+
+// per-column sum of |A_ij| (1-norm = max over columns)
+__global__ void expm_colsum_kernel(const double* __restrict__ A, int n, const double* __restrict__ d, double gr,
+                                   double gi, double* __restrict__ out) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  double s = 0.0;
+  for (int i = 0; i < n; ++i) {
+    const int64_t e = (int64_t)j * n + i;
+    double re = A[2 * e], im = A[2 * e + 1];
+    if (d && i == j) {
+      re += gr * d[i];
+      im += gi * d[i];
+    }
+    s += sqrt(re * re + im * im);
+  }
+  out[j] = s;
+}
+
 // ---------------------------------------------------------- host side -----
 
 std::atomic<int> g_split_cls{-2};   // -2: not read yet, -1: automatic
@@ -346,6 +393,26 @@ hipError_t launch_prepare(int prec, int cplx, const double* master, int64_t rows
 }
 
 int norm_partials() { return NORM_BLOCKS; }
+
+hipError_t launch_expm_generator(const double* A, int n, const double* d, double gr, double gi, double fr, double fi,
+                                 double* X, hipStream_t s) {
+  const int64_t nn = (int64_t)n * n;
+  hipLaunchKernelGGL(expm_generator_kernel, dim3((unsigned)((nn + 255) / 256)), dim3(256), 0, s, A, n, d, gr, gi, fr,
+                     fi, X);
+  return hipGetLastError();
+}
+
+hipError_t launch_expm_horner(double* T, const double* W, int n, double f, hipStream_t s) {
+  const int64_t nn = (int64_t)n * n;
+  hipLaunchKernelGGL(expm_horner_kernel, dim3((unsigned)((nn + 255) / 256)), dim3(256), 0, s, T, W, n, f);
+  return hipGetLastError();
+}
+
+hipError_t launch_expm_colsum(const double* A, int n, const double* d, double gr, double gi, double* out,
+                              hipStream_t s) {
+  hipLaunchKernelGGL(expm_colsum_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, A, n, d, gr, gi, out);
+  return hipGetLastError();
+}
 
 int fp16x2_op_exp(double amax) {
   if (!(amax > 0.0) || !std::isfinite(amax)) return 0;

@@ -129,6 +129,14 @@ hipError_t launch_prepare(int prec, int cplx, const double* master, int64_t rows
 // Scale exponent of an operator whose largest |real component| is amax:
 // the scaled entries stay below 16 (so hi * 2^11 stays below 2^15).
 int fp16x2_op_exp(double amax);
+// Device matrix exponential helpers (complex FP64, column-major interleaved,
+// n x n): X = f (A + g diag(d)) (d real, nullable); T = I + f W (W null:
+// T = I); out[j] = sum_i |(A + g diag(d))_ij|.
+hipError_t launch_expm_generator(const double* A, int n, const double* d, double gr, double gi, double fr, double fi,
+                                 double* X, hipStream_t s);
+hipError_t launch_expm_horner(double* T, const double* W, int n, double f, hipStream_t s);
+hipError_t launch_expm_colsum(const double* A, int n, const double* d, double gr, double gi, double* out,
+                              hipStream_t s);
 // FP16X2 chain start: slots[0] = float bits of max |x_k| over `count` floats,
 // slots[1] = slots[2] = 0.  partial: >= norm_partials() words.
 hipError_t launch_maxabs(const float* x, int64_t count, uint32_t* partial, uint32_t* slots, hipStream_t s);

@@ -51,6 +51,12 @@ struct mm_ctx_s {
   uint32_t* smax = nullptr;
   const void* chain_end = nullptr;
   int sidx = 0;
+  // device matrix exponential scratch: X, T, W (complex FP64 n x n each),
+  // the prepared X / T, column sums
+  double* ex_buf = nullptr;
+  size_t ex_bytes = 0;
+  void* ex_prep = nullptr;
+  size_t ex_prep_bytes = 0;
   // per-mode scratch for operators re-prepared every step (ho_strang_step)
   void* step_prep[MM_MAXD] = {nullptr};
   size_t step_prep_bytes[MM_MAXD] = {0};
@@ -309,6 +315,84 @@ mm_status sweep(mm_ctx ctx, mm_tensor* T, const mm_op* E, double first_pre, doub
   return MM_OK;
 }
 
+// Grow a device buffer owned by the context.
+mm_status grow(mm_ctx ctx, void** p, size_t* have, size_t need) {
+  if (*have >= need) return MM_OK;
+  if (*p) {
+    HIPCHK(ctx, hipDeviceSynchronize());
+    HIPCHK(ctx, hipFree(*p));
+    *p = nullptr;
+    *have = 0;
+  }
+  if (hipMalloc(p, need) != hipSuccess) return fail(ctx, MM_ERR_NOMEM, "scratch of %zu bytes", need);
+  *have = need;
+  return MM_OK;
+}
+
+// A throw-away operator record for products with a device-resident FP64
+// master that is prepared by the caller (prep_override of run_mode).
+mm_op_s scratch_op(int n, mm_prec prec, int a_exp) {
+  mm_op_s o;
+  o.rows = o.cols = n;
+  o.cplx = 1;
+  o.prec = prec;
+  o.a_exp = a_exp;
+  mm::op_blocks(kprec(prec), 2 * (int64_t)n, 2 * (int64_t)n, &o.KBT, &o.MFT);
+  return o;
+}
+
+// out = exp(f (A + g diag(d))) for a complex n x n FP64 matrix A on the
+// device (d real, nullable), by scaling and squaring of the Taylor
+// polynomial: X = f (A + g diag d) / 2^q with ||X||_1 <= 1, T = sum_k X^k/k!
+// to degree 18 by Horner's rule (truncation <= e/19! < 2.2e-17), then q
+// squarings.  Every matrix product is a mode-1 product of the FP64 MFMA
+// kernel.  bound: an upper bound of ||A + g diag d||_1 known to the caller,
+// or < 0 to compute it here (synchronises s).
+mm_status expm_device(mm_ctx ctx, int n, const double* A, const double* d, double gr, double gi, double fr,
+                      double fi, double bound, double* out, hipStream_t s) {
+  const size_t mat = (size_t)n * n * 2;
+  mm_status st = grow(ctx, (void**)&ctx->ex_buf, &ctx->ex_bytes, sizeof(double) * (3 * mat + n));
+  if (st != MM_OK) return st;
+  mm_op_s op = scratch_op(n, MM_PREC_FP64, 0);
+  st = grow(ctx, &ctx->ex_prep, &ctx->ex_prep_bytes, mm::prepared_bytes(mm::KP_F64, op.KBT, op.MFT));
+  if (st != MM_OK) return st;
+  double* X = ctx->ex_buf;
+  double* T = X + mat;
+  double* W = T + mat;
+  double* cs = W + mat;
+  if (bound < 0) {
+    HIPCHK(ctx, mm::launch_expm_colsum(A, n, d, gr, gi, cs, s));
+    std::vector<double> h(n);
+    HIPCHK(ctx, hipMemcpyAsync(h.data(), cs, sizeof(double) * n, hipMemcpyDeviceToHost, s));
+    HIPCHK(ctx, hipStreamSynchronize(s));
+    bound = 0.0;
+    for (double v : h) bound = std::max(bound, v);
+  }
+  if (!std::isfinite(bound)) return fail(ctx, MM_ERR_NONFINITE, "matrix holds NaN / Inf");
+  const double fa = std::hypot(fr, fi) * bound;
+  int q = 0;
+  if (fa > 1.0) q = (int)std::ceil(std::log2(fa));
+  if (q > 1000) return fail(ctx, MM_ERR_ARG, "exponent argument too large (norm %g)", fa);
+  const double sc = std::ldexp(1.0, -q);
+  HIPCHK(ctx, mm::launch_expm_generator(A, n, d, gr, gi, fr * sc, fi * sc, X, s));
+  HIPCHK(ctx, mm::launch_prepare(mm::KP_F64, 1, X, n, n, n, mm::PhaseScale(), ctx->ex_prep, op.KBT, op.MFT, s));
+  HIPCHK(ctx, mm::launch_expm_horner(T, nullptr, n, 0.0, s));
+  const int64_t dims[2] = {n, n};
+  for (int k = 18; k >= 1; --k) {
+    st = run_mode(ctx, T, W, dims, 2, MM_C128, &op, 1, 0, 0, s, nullptr, false, ctx->ex_prep);
+    if (st != MM_OK) return st;
+    HIPCHK(ctx, mm::launch_expm_horner(T, W, n, 1.0 / k, s));
+  }
+  for (int r = 0; r < q; ++r) {
+    HIPCHK(ctx, mm::launch_prepare(mm::KP_F64, 1, T, n, n, n, mm::PhaseScale(), ctx->ex_prep, op.KBT, op.MFT, s));
+    st = run_mode(ctx, T, W, dims, 2, MM_C128, &op, 1, 0, 0, s, nullptr, false, ctx->ex_prep);
+    if (st != MM_OK) return st;
+    std::swap(T, W);
+  }
+  HIPCHK(ctx, hipMemcpyAsync(out, T, sizeof(double) * mat, hipMemcpyDeviceToDevice, s));
+  return MM_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -393,6 +477,8 @@ mm_status mm_destroy(mm_ctx ctx) {
   if (ctx->red_partial) hipFree(ctx->red_partial);
   if (ctx->red_result) hipFree(ctx->red_result);
   if (ctx->smax) hipFree(ctx->smax);
+  if (ctx->ex_buf) hipFree(ctx->ex_buf);
+  if (ctx->ex_prep) hipFree(ctx->ex_prep);
   if (ctx->host_result) hipHostFree(ctx->host_result);
   delete ctx;
   return MM_OK;
@@ -1100,6 +1186,155 @@ mm_status mm_tune_load(mm_ctx ctx, const char* path) {
   std::fclose(f);
   if (!eof) return fail(ctx, MM_ERR_ARG, "%s: malformed line", path);
   for (const auto& e : t) ctx->tune[e.first] = e.second;
+  return MM_OK;
+}
+
+mm_status mm_expm_device(mm_ctx ctx, int n, const double* A, double c_re, double c_im, double* out,
+                         mm_stream stream) {
+  if (!ctx) return MM_ERR_ARG;
+  if (!A || !out) return fail(ctx, MM_ERR_ARG, "A / out is NULL");
+  if (n < 1 || n > 4096) return fail(ctx, MM_ERR_SHAPE, "n = %d outside [1, 4096]", n);
+  if (((uintptr_t)A & 15) || ((uintptr_t)out & 15)) return fail(ctx, MM_ERR_ALIGN, "A / out not 16-byte aligned");
+  if (!std::isfinite(c_re) || !std::isfinite(c_im)) return fail(ctx, MM_ERR_ARG, "c not finite");
+  const char* a0 = (const char*)A;
+  const char* o0 = (const char*)out;
+  const size_t bytes = sizeof(double) * 2 * (size_t)n * n;
+  if (a0 < o0 + bytes && o0 < a0 + bytes) return fail(ctx, MM_ERR_ARG, "out overlaps A");
+  HIPCHK(ctx, hipSetDevice(ctx->device));
+  ctx->chain_end = nullptr;
+  return expm_device(ctx, n, A, nullptr, 0.0, 0.0, c_re, c_im, -1.0, out, (hipStream_t)stream);
+}
+
+mm_status mumode_magnus_step(mm_ctx ctx, mm_tensor* T, const mm_matrix* B, const double* const* dg, const double* g,
+                             double tau, int nsteps, mm_prec prec, mm_stream stream) {
+  if (!ctx) return MM_ERR_ARG;
+  mm_status st = check_tensor(ctx, T, "T");
+  if (st != MM_OK) return st;
+  if (!is_complex(T->dtype)) return fail(ctx, MM_ERR_DTYPE, "T must be complex");
+  if (!B) return fail(ctx, MM_ERR_ARG, "B is NULL");
+  if (nsteps < 0) return fail(ctx, MM_ERR_ARG, "nsteps < 0");
+  if (!std::isfinite(tau)) return fail(ctx, MM_ERR_ARG, "tau not finite");
+  if (prec < MM_PREC_FP64 || prec > MM_PREC_BF16) return fail(ctx, MM_ERR_ARG, "bad precision");
+  if ((prec == MM_PREC_FP64) != is_f64(T->dtype))
+    return fail(ctx, MM_ERR_DTYPE, "precision %d does not match tensor dtype %d", (int)prec, (int)T->dtype);
+  const int d = T->d;
+  bool any_t = false;
+  for (int k = 0; k < d; ++k) {
+    if (!B[k].data) continue;
+    if (B[k].rows != T->dims[k] || B[k].cols != T->dims[k])
+      return fail(ctx, MM_ERR_SHAPE, "B[%d] must be %lld x %lld", k, (long long)T->dims[k], (long long)T->dims[k]);
+    if (B[k].dtype != MM_C128 && B[k].dtype != MM_R64) return fail(ctx, MM_ERR_DTYPE, "B[%d] must be MM_C128 or MM_R64", k);
+    if (B[k].ld < B[k].rows) return fail(ctx, MM_ERR_SHAPE, "B[%d]: ld < rows", k);
+    if (dg && dg[k]) any_t = true;
+  }
+  if (any_t && !g) return fail(ctx, MM_ERR_ARG, "g is NULL but a mode has a time-dependent part");
+  if (nsteps == 0) return MM_OK;
+  HIPCHK(ctx, hipSetDevice(ctx->device));
+  ctx->chain_end = nullptr;
+  hipStream_t s = (hipStream_t)stream;
+  const int kp = kprec(prec);
+  // per-mode device state: FP64 complex master, diagonal, exponential,
+  // prepared exponential
+  struct Mode {
+    int n = 0;
+    double* Bd = nullptr;
+    double* dd = nullptr;
+    double* E = nullptr;
+    void* P = nullptr;
+    double bnorm = 0.0, dmax = 0.0;
+    mm_op_s op;
+  };
+  std::vector<Mode> modes(d);
+  struct Guard {
+    std::vector<Mode>* m;
+    ~Guard() {
+      hipDeviceSynchronize();
+      for (auto& x : *m) {
+        if (x.Bd) hipFree(x.Bd);
+        if (x.dd) hipFree(x.dd);
+        if (x.E) hipFree(x.E);
+        if (x.P) hipFree(x.P);
+      }
+    }
+  } guard{&modes};
+  for (int k = 0; k < d; ++k) {
+    if (!B[k].data) continue;
+    Mode& M = modes[k];
+    const int n = (int)T->dims[k];
+    M.n = n;
+    const int comps = B[k].dtype == MM_C128 ? 2 : 1;
+    std::vector<double> full((size_t)B[k].ld * n * comps), host((size_t)n * n * 2, 0.0);
+    if (B[k].on_device)
+      HIPCHK(ctx, hipMemcpy(full.data(), B[k].data, full.size() * sizeof(double), hipMemcpyDeviceToHost));
+    else
+      std::memcpy(full.data(), B[k].data, full.size() * sizeof(double));
+    std::vector<double> colsum(n, 0.0);
+    for (int j = 0; j < n; ++j)
+      for (int i = 0; i < n; ++i) {
+        const double re = full[((size_t)j * B[k].ld + i) * comps];
+        const double im = comps == 2 ? full[((size_t)j * B[k].ld + i) * 2 + 1] : 0.0;
+        if (!std::isfinite(re) || !std::isfinite(im)) return fail(ctx, MM_ERR_NONFINITE, "B[%d] holds NaN / Inf", k);
+        host[2 * ((size_t)j * n + i)] = re;
+        host[2 * ((size_t)j * n + i) + 1] = im;
+        colsum[j] += std::hypot(re, im);
+      }
+    for (double v : colsum) M.bnorm = std::max(M.bnorm, v);
+    if (hipMalloc((void**)&M.Bd, host.size() * sizeof(double)) != hipSuccess ||
+        hipMalloc((void**)&M.E, host.size() * sizeof(double)) != hipSuccess)
+      return fail(ctx, MM_ERR_NOMEM, "mode buffers");
+    HIPCHK(ctx, hipMemcpy(M.Bd, host.data(), host.size() * sizeof(double), hipMemcpyHostToDevice));
+    if (dg && dg[k]) {
+      for (int i = 0; i < n; ++i) {
+        if (!std::isfinite(dg[k][i])) return fail(ctx, MM_ERR_NONFINITE, "d[%d] holds NaN / Inf", k);
+        M.dmax = std::max(M.dmax, std::fabs(dg[k][i]));
+      }
+      if (hipMalloc((void**)&M.dd, sizeof(double) * n) != hipSuccess) return fail(ctx, MM_ERR_NOMEM, "diagonal");
+      HIPCHK(ctx, hipMemcpy(M.dd, dg[k], sizeof(double) * n, hipMemcpyHostToDevice));
+    }
+    M.op = scratch_op(n, prec, 0);
+    if (hipMalloc(&M.P, mm::prepared_bytes(kp, M.op.KBT, M.op.MFT)) != hipSuccess)
+      return fail(ctx, MM_ERR_NOMEM, "prepared operator");
+  }
+  const size_t bytes = (size_t)numel(T) * dsize(T->dtype);
+  for (int it = 0; it < nsteps; ++it) {
+    void* cur = T->data;
+    for (int k = 0; k < d; ++k) {
+      Mode& M = modes[k];
+      if (!M.Bd) continue;
+      if (it == 0 || M.dd) {
+        // E_k = exp(tau (B_k + g diag d_k)) at the midpoint of the step
+        double gr = 0.0, gi = 0.0;
+        if (M.dd) {
+          gr = g[2 * ((size_t)it * d + k)];
+          gi = g[2 * ((size_t)it * d + k) + 1];
+          if (!std::isfinite(gr) || !std::isfinite(gi)) return fail(ctx, MM_ERR_NONFINITE, "g not finite");
+        }
+        const double bound = M.bnorm + std::hypot(gr, gi) * M.dmax;
+        st = expm_device(ctx, M.n, M.Bd, M.dd, gr, gi, tau, 0.0, bound, M.E, s);
+        if (st != MM_OK) return st;
+        // FP16X2: |E_ij| <= ||E||_1 <= exp(|tau| bound)
+        M.op.a_exp = prec == MM_PREC_SPLIT_FP16X2 ? mm::fp16x2_op_exp(std::exp(std::min(700.0, std::fabs(tau) * bound))) : 0;
+        HIPCHK(ctx, mm::launch_prepare(kp, 1, M.E, M.n, M.n, M.n, mm::PhaseScale(), M.P, M.op.KBT, M.op.MFT, s,
+                                       M.op.a_exp));
+      }
+      mm::ModePlan plan;
+      st = run_mode(ctx, cur, cur, T->dims, d, T->dtype, &M.op, k + 1, 0, 0, s, &plan, true, M.P);
+      if (st != MM_OK) return st;
+      void* dst = cur;
+      if (!plan.covers_all_rows) {
+        st = ensure_ws(ctx, bytes);
+        if (st != MM_OK) return st;
+        dst = (cur == T->data) ? ctx->ws : T->data;
+      }
+      st = run_mode(ctx, cur, dst, T->dims, d, T->dtype, &M.op, k + 1, 0, 0, s, nullptr, false, M.P);
+      if (st != MM_OK) return st;
+      cur = dst;
+    }
+    if (cur != T->data) {
+      HIPCHK(ctx, hipMemcpyAsync(T->data, cur, bytes, hipMemcpyDeviceToDevice, s));
+      if (ctx->chain_end == cur) ctx->chain_end = T->data;
+    }
+  }
   return MM_OK;
 }
 
