@@ -193,6 +193,32 @@ def other_workloads(ctx, mm, torch):
                                 "tflops_effective": 3 * 8.0 * m * m ** 3 / (t / K) / 1e12}
         Lh.destroy()
         del psi
+    # time-dependent Schroedinger problem of Section 4.3 in nodal Hermite
+    # space, exponential midpoint rule: the mode-3 exponential is formed on
+    # the device every step ("exp (int)"), then the three mode products
+    for m in (128, 256):
+        Phi, Psi = mm.hermite_matrices(m)
+        X, _ = mm.hermite_nodes(m)
+        Bm = Psi @ np.diag(-1j * (np.arange(m) + 0.5)) @ Phi
+        K = 20
+        g = np.zeros((K, 3), dtype=np.complex128)
+        g[:, 2] = -1j * np.sin((np.arange(K) + 0.5) * 0.02) ** 2
+        for prec, sdt in (("fp64", torch.complex128), ("fp32", torch.complex64)):
+            psi = torch.randn((m, m, m), dtype=sdt, device="cuda", generator=gen)
+            ctx.mumode_magnus_step(psi, [Bm] * 3, [None, None, X], g[:2], 0.02, 2, prec)
+            t = timed(torch, lambda k: ctx.mumode_magnus_step(psi, [Bm] * 3, [None, None, X], g[:k], 0.02, k, prec), K)
+            A = torch.from_numpy(np.ascontiguousarray((0.02 * (Bm - 1j * 0.5 * np.diag(X))).T)).cuda()
+            Eo = torch.empty_like(A)
+            t_exp = timed(torch, lambda k: [ctx.mm_expm_device(A, 1.0, Eo) for _ in range(k)], K)
+            out[f"hkmp{m}_{prec}"] = {"ms_per_step": 1e3 * t / K, "ms_exp_int": 1e3 * t_exp / K,
+                                      "note": "step = one device expm (mode 3) + three mode products; "
+                                              "exp timed alone includes a host sync for its norm"}
+            del psi, A, Eo
+    out["hkmp_paper_v100_ms"] = {"n127_double": {"exp_int": 0.37, "mu_mode": 1.05},
+                                 "n255_double": {"exp_int": 0.66, "mu_mode": 13.79},
+                                 "n127_single": {"exp_int": 0.25, "mu_mode": 0.54},
+                                 "n255_single": {"exp_int": 0.34, "mu_mode": 7.01},
+                                 "source": "the paper's table for this problem (V100), context only"}
     # heat, d = 2, n = 64, FP64, 20 steps per call (launch-latency bound)
     E = mm.expm(mm.fd2_matrix(64, 0.0, 1.0), 1e-3).real.copy()
     Eop = ctx.mm_op_prepare(E, "fp64")
