@@ -214,7 +214,8 @@ mm_status mumode_magnus_step(mm_ctx ctx, mm_tensor* T, const mm_matrix* B, const
 /* exp(c A) of a complex n x n FP64 matrix on the device (A, out: device
  * pointers, column-major interleaved, leading dimension n, not
  * overlapping): scaling to ||c A / 2^q||_1 <= 1, the degree-18 Taylor
- * polynomial by Horner's rule (truncation below 2.2e-17), q squarings; each
+ * polynomial (truncation below 2.2e-17) by the Paterson-Stockmeyer scheme
+ * (7 matrix products), q squarings; each
  * matrix product runs on the FP64 MFMA mode-product kernel (the Taylor
  * approach Section 5.3 uses on the GPU).  Computes ||A||_1 on the device and
  * synchronises `stream`. */

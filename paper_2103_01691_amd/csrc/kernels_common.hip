@@ -199,6 +199,23 @@ __global__ void expm_horner_kernel(double* __restrict__ T, const double* __restr
   T[2 * e + 1] = W ? f * W[2 * e + 1] : 0.0;
 }
 
+// P = W + c0 I + c1 X + c2 X2 + c3 X3 (W nullable): one Paterson-Stockmeyer
+// block of the Taylor polynomial
+__global__ void expm_ps_kernel(double* __restrict__ P, const double* __restrict__ W, const double* __restrict__ X,
+                               const double* __restrict__ X2, const double* __restrict__ X3, int n, double c0,
+                               double c1, double c2, double c3) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (int64_t)n * n) return;
+  const int i = (int)(e % n), j = (int)(e / n);
+#pragma unroll
+  for (int c = 0; c < 2; ++c) {
+    const int64_t k = 2 * e + c;
+    double v = (W ? W[k] : 0.0) + c1 * X[k] + c2 * X2[k] + c3 * X3[k];
+    if (c == 0 && i == j) v += c0;
+    P[k] = v;
+  }
+}
+
 // per-column sum of |A_ij| (1-norm = max over columns)
 __global__ void expm_colsum_kernel(const double* __restrict__ A, int n, const double* __restrict__ d, double gr,
                                    double gi, double* __restrict__ out) {
@@ -405,6 +422,14 @@ hipError_t launch_expm_generator(const double* A, int n, const double* d, double
 hipError_t launch_expm_horner(double* T, const double* W, int n, double f, hipStream_t s) {
   const int64_t nn = (int64_t)n * n;
   hipLaunchKernelGGL(expm_horner_kernel, dim3((unsigned)((nn + 255) / 256)), dim3(256), 0, s, T, W, n, f);
+  return hipGetLastError();
+}
+
+hipError_t launch_expm_ps(double* P, const double* W, const double* X, const double* X2, const double* X3, int n,
+                          const double* c, hipStream_t s) {
+  const int64_t nn = (int64_t)n * n;
+  hipLaunchKernelGGL(expm_ps_kernel, dim3((unsigned)((nn + 255) / 256)), dim3(256), 0, s, P, W, X, X2, X3, n, c[0],
+                     c[1], c[2], c[3]);
   return hipGetLastError();
 }
 

@@ -137,6 +137,9 @@ hipError_t launch_expm_generator(const double* A, int n, const double* d, double
 hipError_t launch_expm_horner(double* T, const double* W, int n, double f, hipStream_t s);
 hipError_t launch_expm_colsum(const double* A, int n, const double* d, double gr, double gi, double* out,
                               hipStream_t s);
+// P = W + c[0] I + c[1] X + c[2] X2 + c[3] X3 (W nullable)
+hipError_t launch_expm_ps(double* P, const double* W, const double* X, const double* X2, const double* X3, int n,
+                          const double* c, hipStream_t s);
 // FP16X2 chain start: slots[0] = float bits of max |x_k| over `count` floats,
 // slots[1] = slots[2] = 0.  partial: >= norm_partials() words.
 hipError_t launch_maxabs(const float* x, int64_t count, uint32_t* partial, uint32_t* slots, hipStream_t s);

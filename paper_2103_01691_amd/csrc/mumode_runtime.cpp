@@ -343,23 +343,31 @@ mm_op_s scratch_op(int n, mm_prec prec, int a_exp) {
 
 // out = exp(f (A + g diag(d))) for a complex n x n FP64 matrix A on the
 // device (d real, nullable), by scaling and squaring of the Taylor
-// polynomial: X = f (A + g diag d) / 2^q with ||X||_1 <= 1, T = sum_k X^k/k!
-// to degree 18 by Horner's rule (truncation <= e/19! < 2.2e-17), then q
-// squarings.  Every matrix product is a mode-1 product of the FP64 MFMA
-// kernel.  bound: an upper bound of ||A + g diag d||_1 known to the caller,
-// or < 0 to compute it here (synchronises s).
+// polynomial: X = f (A + g diag d) / 2^q with ||X||_1 <= 1, the degree-18
+// Taylor polynomial (truncation <= e/19! < 2.2e-17) evaluated by the
+// Paterson-Stockmeyer scheme with blocks of four terms (X^2, X^3, X^4, then
+// Horner in X^4: 7 matrix products instead of 18), then q squarings.  Every
+// matrix product is a mode-1 product of the FP64 MFMA kernel.  bound: an
+// upper bound of ||A + g diag d||_1 known to the caller, or < 0 to compute
+// it here (synchronises s).
 mm_status expm_device(mm_ctx ctx, int n, const double* A, const double* d, double gr, double gi, double fr,
                       double fi, double bound, double* out, hipStream_t s) {
   const size_t mat = (size_t)n * n * 2;
-  mm_status st = grow(ctx, (void**)&ctx->ex_buf, &ctx->ex_bytes, sizeof(double) * (3 * mat + n));
+  mm_status st = grow(ctx, (void**)&ctx->ex_buf, &ctx->ex_bytes, sizeof(double) * (6 * mat + n));
   if (st != MM_OK) return st;
   mm_op_s op = scratch_op(n, MM_PREC_FP64, 0);
-  st = grow(ctx, &ctx->ex_prep, &ctx->ex_prep_bytes, mm::prepared_bytes(mm::KP_F64, op.KBT, op.MFT));
+  const size_t pb = mm::prepared_bytes(mm::KP_F64, op.KBT, op.MFT);
+  st = grow(ctx, &ctx->ex_prep, &ctx->ex_prep_bytes, 2 * pb);
   if (st != MM_OK) return st;
   double* X = ctx->ex_buf;
-  double* T = X + mat;
-  double* W = T + mat;
+  double* X2 = X + mat;
+  double* X3 = X2 + mat;
+  double* Y = X3 + mat;     // X^4
+  double* P = Y + mat;
+  double* W = P + mat;
   double* cs = W + mat;
+  void* prepX = ctx->ex_prep;
+  void* prepY = (char*)ctx->ex_prep + pb;
   if (bound < 0) {
     HIPCHK(ctx, mm::launch_expm_colsum(A, n, d, gr, gi, cs, s));
     std::vector<double> h(n);
@@ -374,19 +382,29 @@ mm_status expm_device(mm_ctx ctx, int n, const double* A, const double* d, doubl
   if (fa > 1.0) q = (int)std::ceil(std::log2(fa));
   if (q > 1000) return fail(ctx, MM_ERR_ARG, "exponent argument too large (norm %g)", fa);
   const double sc = std::ldexp(1.0, -q);
-  HIPCHK(ctx, mm::launch_expm_generator(A, n, d, gr, gi, fr * sc, fi * sc, X, s));
-  HIPCHK(ctx, mm::launch_prepare(mm::KP_F64, 1, X, n, n, n, mm::PhaseScale(), ctx->ex_prep, op.KBT, op.MFT, s));
-  HIPCHK(ctx, mm::launch_expm_horner(T, nullptr, n, 0.0, s));
   const int64_t dims[2] = {n, n};
-  for (int k = 18; k >= 1; --k) {
-    st = run_mode(ctx, T, W, dims, 2, MM_C128, &op, 1, 0, 0, s, nullptr, false, ctx->ex_prep);
-    if (st != MM_OK) return st;
-    HIPCHK(ctx, mm::launch_expm_horner(T, W, n, 1.0 / k, s));
+  auto mul = [&](const void* prep, const double* in, double* o) {
+    return run_mode(ctx, in, o, dims, 2, MM_C128, &op, 1, 0, 0, s, nullptr, false, prep);
+  };
+  HIPCHK(ctx, mm::launch_expm_generator(A, n, d, gr, gi, fr * sc, fi * sc, X, s));
+  HIPCHK(ctx, mm::launch_prepare(mm::KP_F64, 1, X, n, n, n, mm::PhaseScale(), prepX, op.KBT, op.MFT, s));
+  if ((st = mul(prepX, X, X2)) != MM_OK) return st;
+  if ((st = mul(prepX, X2, X3)) != MM_OK) return st;
+  if ((st = mul(prepX, X3, Y)) != MM_OK) return st;
+  HIPCHK(ctx, mm::launch_prepare(mm::KP_F64, 1, Y, n, n, n, mm::PhaseScale(), prepY, op.KBT, op.MFT, s));
+  // coefficients 1/k!, k = 0..18, in blocks B_j = sum_i c_{4j+i} X^i
+  double c[20] = {0};
+  c[0] = 1.0;
+  for (int k = 1; k <= 18; ++k) c[k] = c[k - 1] / k;
+  HIPCHK(ctx, mm::launch_expm_ps(P, nullptr, X, X2, X3, n, c + 16, s));
+  for (int j = 3; j >= 0; --j) {
+    if ((st = mul(prepY, P, W)) != MM_OK) return st;   // P X^4 (polynomials in X commute)
+    HIPCHK(ctx, mm::launch_expm_ps(P, W, X, X2, X3, n, c + 4 * j, s));
   }
+  double* T = P;
   for (int r = 0; r < q; ++r) {
-    HIPCHK(ctx, mm::launch_prepare(mm::KP_F64, 1, T, n, n, n, mm::PhaseScale(), ctx->ex_prep, op.KBT, op.MFT, s));
-    st = run_mode(ctx, T, W, dims, 2, MM_C128, &op, 1, 0, 0, s, nullptr, false, ctx->ex_prep);
-    if (st != MM_OK) return st;
+    HIPCHK(ctx, mm::launch_prepare(mm::KP_F64, 1, T, n, n, n, mm::PhaseScale(), prepX, op.KBT, op.MFT, s));
+    if ((st = mul(prepX, T, W)) != MM_OK) return st;
     std::swap(T, W);
   }
   HIPCHK(ctx, hipMemcpyAsync(out, T, sizeof(double) * mat, hipMemcpyDeviceToDevice, s));
