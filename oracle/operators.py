@@ -14,6 +14,15 @@ Pins (tests/test_oracle_operators.py):
                          formulas agree; Hermite eigen-relation
                          (-1/2 sum (d^2 - x^2)) H_i = lambda_i H_i checked on
                          the continuum by finite differences of the functions.
+  central_d2_weights /  -- the textbook orders 2 and 4; convergence at the
+  fd2_periodic_order       stencil's order on a smooth periodic function
+                           (error ratio 2^p when n doubles); order 2 = fd2.
+  fourier_d2            -- exact (to rounding) on every trigonometric mode
+                           the grid carries, symmetric.
+  pipe_flow_operators   -- second-order consistency, boundary rows included,
+                           on functions that satisfy the boundary conditions
+                           (Neumann / Dirichlet-Neumann), against the
+                           analytic operator including the 1/r and s(z) terms.
 """
 from __future__ import annotations
 
@@ -153,3 +162,87 @@ def hkmp_problem(m: int):
     B = [Bm, Bm, Bm]
     d = [None, None, X]
     return B, d, (lambda mu, t: -1j * np.sin(t) ** 2 if mu == 2 else 0.0)
+
+
+# ------------------------------------------------ operator front-ends ----
+
+def central_d2_weights(order: int) -> np.ndarray:
+    """Weights w_0..w_m (m = order/2) of the centred second difference of the
+    given even order, from the Taylor conditions: sum_k w_|k| k^(2q) = 2 [q == 1]
+    for q = 0..m (symmetric stencil, h = 1)."""
+    m = order // 2
+    ks = np.arange(0, m + 1)
+    # unknowns w_0..w_m; row q: w_0 [q==0] + 2 sum_{k>=1} w_k k^(2q)
+    M = np.zeros((m + 1, m + 1))
+    rhs = np.zeros(m + 1)
+    for q in range(m + 1):
+        M[q, 0] = 1.0 if q == 0 else 0.0
+        M[q, 1:] = 2.0 * ks[1:].astype(float) ** (2 * q)
+    rhs[1] = 2.0
+    return np.linalg.solve(M, rhs)
+
+
+def fd2_periodic_order(n: int, a: float, b: float, order: int) -> np.ndarray:
+    """Centred second difference of even `order` on n periodic nodes of
+    [a, b) (h = (b - a)/n): a symmetric circulant (Section 4.1, Test 2)."""
+    h = (b - a) / n
+    w = central_d2_weights(order)
+    D = np.zeros((n, n))
+    for i in range(n):
+        D[i, i] += w[0]
+        for k in range(1, len(w)):
+            D[i, (i + k) % n] += w[k]
+            D[i, (i - k) % n] += w[k]
+    return D / h ** 2
+
+
+def fourier_d2(n: int, a: float, b: float) -> np.ndarray:
+    """Fourier spectral second derivative on n periodic nodes of [a, b): the
+    matrix of u -> ifft(-(2 pi k / L)^2 fft(u)), k the FFT wavenumbers (the
+    Nyquist mode of even n multiplied by -(pi n / L)^2), applied to the unit
+    vectors."""
+    L = b - a
+    k = np.fft.fftfreq(n, d=1.0 / n)
+    if n % 2 == 0:
+        k[n // 2] = n // 2
+    sym = -(2.0 * np.pi * k / L) ** 2
+    return np.real(np.fft.ifft(sym[:, None] * np.fft.fft(np.eye(n), axis=0), axis=0))
+
+
+def pipe_flow_operators(n_rho: int, n_z: int, rho_min: float, rho_max: float, z_max: float, alpha: float):
+    """1-D operators of the pipe-flow problem of Section 4.2,
+    c_t = alpha (c_rr + c_r / r + c_zz) - s(z) c_z, s(z) = 2 + tanh(4(z - 5/2))
+    - tanh(4(z - 5)), by second-order centred differences:
+      r: n_rho nodes r_i = r_min + i h, i = 0..n-1, h = (r_max - r_min)/(n - 1),
+         homogeneous Neumann at both ends by mirrored ghost values;
+      z: n_z nodes z_j = j h, j = 1..n, h = z_max / n, c = 0 at z = 0
+         (Dirichlet, eliminated), homogeneous Neumann at z_max by a mirrored
+         ghost value.
+    Returns (A_r, A_z, r, z)."""
+    def d1_d2(n, h, left, right):
+        D1 = np.zeros((n, n))
+        D2 = np.zeros((n, n))
+        for i in range(n):
+            for j, c1, c2 in ((i - 1, -0.5 / h, 1.0 / h ** 2), (i, 0.0, -2.0 / h ** 2), (i + 1, 0.5 / h, 1.0 / h ** 2)):
+                if j < 0:
+                    if left == "dirichlet":
+                        continue
+                    j = 1            # mirrored ghost value c_{-1} = c_1
+                if j >= n:
+                    if right == "dirichlet":
+                        continue
+                    j = n - 2        # mirrored ghost value c_n = c_{n-2}
+                D1[i, j] += c1
+                D2[i, j] += c2
+        return D1, D2
+
+    hr = (rho_max - rho_min) / (n_rho - 1)
+    r = rho_min + hr * np.arange(n_rho)
+    D1r, D2r = d1_d2(n_rho, hr, "neumann", "neumann")
+    A_r = alpha * (D2r + np.diag(1.0 / r) @ D1r)
+    hz = z_max / n_z
+    z = hz * np.arange(1, n_z + 1)
+    D1z, D2z = d1_d2(n_z, hz, "dirichlet", "neumann")
+    s = 2.0 + np.tanh(4.0 * (z - 2.5)) - np.tanh(4.0 * (z - 5.0))
+    A_z = alpha * D2z - np.diag(s) @ D1z
+    return A_r, A_z, r, z

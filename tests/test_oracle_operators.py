@@ -165,3 +165,57 @@ def test_exp_symmetric_complex_hermitian_matches_scipy_expm():
     Hm = 0.5 * (B + B.conj().T)
     E = op.exp_symmetric(Hm, -0.8j)
     assert _rel(E, scipy.linalg.expm(-0.8j * Hm)) < 1e-13
+
+
+# ------------------------------------------------ operator front-ends ----
+
+def test_central_weights_known_orders():
+    # order 2: (1, -2, 1); order 4: (-1/12, 4/3, -5/2, 4/3, -1/12)
+    assert np.allclose(op.central_d2_weights(2), [-2.0, 1.0], atol=1e-14)
+    assert np.allclose(op.central_d2_weights(4), [-2.5, 4.0 / 3, -1.0 / 12], atol=1e-13)
+
+
+@pytest.mark.parametrize("order", [2, 4, 6, 8])
+def test_fd2_periodic_order_converges_at_its_order(order):
+    errs = []
+    for n in (32, 64):
+        D = op.fd2_periodic_order(n, 0.0, 2 * np.pi, order)
+        x = 2 * np.pi * np.arange(n) / n
+        u = np.exp(np.sin(x))
+        exact = (np.cos(x) ** 2 - np.sin(x)) * u
+        errs.append(np.abs(D @ u - exact).max())
+    assert order - 0.5 < np.log2(errs[0] / errs[1]) < order + 0.7
+
+
+def test_fd2_periodic_order2_is_fd2():
+    assert np.allclose(op.fd2_periodic_order(17, 0.0, 3.0, 2), op.fd2(17, 0.0, 3.0, "periodic"), atol=1e-12)
+
+
+def test_fourier_d2_exact_on_trigonometric_polynomials():
+    n, a, b = 24, -1.0, 3.0
+    L = b - a
+    D = op.fourier_d2(n, a, b)
+    x = a + L * np.arange(n) / n
+    for k in range(0, n // 2 + 1):
+        w = 2 * np.pi * k / L
+        u = np.cos(w * (x - a))
+        assert np.abs(D @ u + w ** 2 * u).max() < 1e-9 * max(1.0, w ** 2)
+    assert np.allclose(D, D.T, atol=1e-10)
+
+
+def test_pipe_flow_operators_second_order_and_boundary_conditions():
+    rmin, rmax, zmax, alpha = 0.1, 5.0, 8.0, 1.0 / 90
+    er, ez = [], []
+    for n in (100, 200):
+        A_r, A_z, r, z = op.pipe_flow_operators(n, n, rmin, rmax, zmax, alpha)
+        k = np.pi / (rmax - rmin)
+        c = np.cos(k * (r - rmin))                       # Neumann at both ends
+        exact = alpha * (-k ** 2 * c - k * np.sin(k * (r - rmin)) / r)
+        er.append(np.abs(A_r @ c - exact).max())
+        q = np.pi / (2 * zmax)
+        cz = np.sin(q * z)                               # c(0) = 0, c'(z_max) = 0
+        s = 2 + np.tanh(4 * (z - 2.5)) - np.tanh(4 * (z - 5))
+        exact_z = -alpha * q ** 2 * cz - s * q * np.cos(q * z)
+        ez.append(np.abs(A_z @ cz - exact_z).max())
+    assert 3.5 < er[0] / er[1] < 4.5
+    assert 3.5 < ez[0] / ez[1] < 4.5
