@@ -309,6 +309,29 @@ mm_status mm_hermite_matrices(int m, double* Phi, double* Psi);
  * interleaved), Phi / Psi as in mm_hermite_matrices. */
 mm_status mm_hermite_ho_exponential(int m, double tau, double* out);
 
+/* Centred second difference of even order `order` (2..16) on n periodic
+ * nodes of [a, b) (h = (b-a)/n), the symmetric circulant of the classical
+ * central weights (Section 4.1, Test 2 varies the order).  out: n*n doubles,
+ * column-major.  n >= order + 1. */
+mm_status mm_fd2_periodic_order(int n, double a, double b, int order, double* out);
+
+/* Fourier spectral second derivative on n periodic nodes of [a, b) (the
+ * full matrix that Section 4.1 contrasts with sparse stencils), from its
+ * closed form; for even n the Nyquist mode gets -(pi n / (b-a))^2.  out: n*n
+ * doubles, column-major. */
+mm_status mm_fourier_d2(int n, double a, double b, double* out);
+
+/* 1-D operators of the pipe-flow problem of Section 4.2,
+ * c_t = alpha (c_rr + c_r / r + c_zz) - s(z) c_z with
+ * s(z) = 2 + tanh(4(z - 5/2)) - tanh(4(z - 5)), second-order centred
+ * differences: A_r (n_r x n_r) on r_i = r_min + i h, h = (r_max - r_min)/
+ * (n_r - 1), homogeneous Neumann at both ends (mirrored ghost values); A_z
+ * (n_z x n_z) on z_j = j h, j = 1..n_z, h = z_max / n_z, c = 0 at z = 0 and
+ * homogeneous Neumann at z_max.  The generator of the 2-D problem is the
+ * Kronecker sum of the two (mode 1 = r, mode 2 = z).  Column-major. */
+mm_status mm_pipe_flow_operators(int n_r, int n_z, double r_min, double r_max, double z_max, double alpha,
+                                 double* A_r, double* A_z);
+
 #ifdef __cplusplus
 }
 #endif

@@ -82,6 +82,32 @@ def hermite_ho_exponential(m: int, tau: float) -> np.ndarray:
     return np.asarray(out)
 
 
+def fd2_periodic_order(n: int, a: float, b: float, order: int) -> np.ndarray:
+    """Centred second difference of even `order` on n periodic nodes of [a, b)."""
+    out = np.zeros((n, n), dtype=np.float64, order="F")
+    _check(_lib.lib.mm_fd2_periodic_order(n, float(a), float(b), int(order), out.ctypes.data_as(C.POINTER(C.c_double))),
+           "mm_fd2_periodic_order")
+    return np.asarray(out)
+
+
+def fourier_d2(n: int, a: float, b: float) -> np.ndarray:
+    """Fourier spectral second derivative on n periodic nodes of [a, b)."""
+    out = np.zeros((n, n), dtype=np.float64, order="F")
+    _check(_lib.lib.mm_fourier_d2(n, float(a), float(b), out.ctypes.data_as(C.POINTER(C.c_double))), "mm_fourier_d2")
+    return np.asarray(out)
+
+
+def pipe_flow_operators(n_r: int, n_z: int, r_min: float = 0.1, r_max: float = 5.0, z_max: float = 8.0,
+                        alpha: float = 1.0 / 90):
+    """(A_r, A_z) of the pipe-flow problem (Section 4.2)."""
+    A_r = np.zeros((n_r, n_r), dtype=np.float64, order="F")
+    A_z = np.zeros((n_z, n_z), dtype=np.float64, order="F")
+    _check(_lib.lib.mm_pipe_flow_operators(n_r, n_z, float(r_min), float(r_max), float(z_max), float(alpha),
+                                           A_r.ctypes.data_as(C.POINTER(C.c_double)),
+                                           A_z.ctypes.data_as(C.POINTER(C.c_double))), "mm_pipe_flow_operators")
+    return np.asarray(A_r), np.asarray(A_z)
+
+
 # -------------------------------------------------------------- tensors ----
 
 def _dtype_code(t) -> int:

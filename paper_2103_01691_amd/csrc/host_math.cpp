@@ -199,4 +199,88 @@ mm_status mm_hermite_ho_exponential(int m, double tau, double* out) {
   return MM_OK;
 }
 
+mm_status mm_fd2_periodic_order(int n, double a, double b, int order, double* out) {
+  if (!out) return MM_ERR_ARG;
+  if (order < 2 || order > 16 || (order & 1)) return MM_ERR_ARG;
+  const int m = order / 2;
+  if (n < 2 * m + 1 || n > 65536 || !(b > a)) return MM_ERR_SHAPE;
+  const double h = (b - a) / n;
+  // w_k = 2 (-1)^(k+1) (m!)^2 / (k^2 (m-k)! (m+k)!), w_0 = -2 sum w_k
+  std::vector<double> w(m + 1, 0.0);
+  for (int k = 1; k <= m; ++k) {
+    double r = 1.0;   // (m!)^2 / ((m-k)! (m+k)!) = prod_{i=1..k} (m-i+1)/(m+i)
+    for (int i = 1; i <= k; ++i) r *= (double)(m - i + 1) / (double)(m + i);
+    w[k] = 2.0 * ((k & 1) ? 1.0 : -1.0) * r / ((double)k * k);
+    w[0] -= 2.0 * w[k];
+  }
+  std::memset(out, 0, sizeof(double) * (size_t)n * n);
+  const double s2 = 1.0 / (h * h);
+  for (int i = 0; i < n; ++i) {
+    out[i + (size_t)i * n] += w[0] * s2;
+    for (int k = 1; k <= m; ++k) {
+      out[i + (size_t)((i + k) % n) * n] += w[k] * s2;
+      out[i + (size_t)((i - k + n) % n) * n] += w[k] * s2;
+    }
+  }
+  return MM_OK;
+}
+
+mm_status mm_fourier_d2(int n, double a, double b, double* out) {
+  if (!out) return MM_ERR_ARG;
+  if (n < 2 || n > 65536 || !(b > a)) return MM_ERR_SHAPE;
+  // closed form of the periodic spectral second derivative on [0, 2 pi)
+  // (h = 2 pi / n), scaled by (2 pi / L)^2 for the interval [a, b)
+  const double h = 2.0 * M_PI / n;
+  const double sc = (2.0 * M_PI / (b - a)) * (2.0 * M_PI / (b - a));
+  for (int j = 0; j < n; ++j)
+    for (int i = 0; i < n; ++i) {
+      double v;
+      if (i == j) {
+        v = (n % 2 == 0) ? -M_PI * M_PI / (3.0 * h * h) - 1.0 / 6.0 : -M_PI * M_PI / (3.0 * h * h) + 1.0 / 12.0;
+      } else {
+        const int k = i - j;
+        const double sg = (k & 1) ? -1.0 : 1.0;
+        const double sn = std::sin(0.5 * k * h);
+        v = (n % 2 == 0) ? -sg / (2.0 * sn * sn) : -sg * std::cos(0.5 * k * h) / (2.0 * sn * sn);
+      }
+      out[i + (size_t)j * n] = sc * v;
+    }
+  return MM_OK;
+}
+
+mm_status mm_pipe_flow_operators(int n_r, int n_z, double r_min, double r_max, double z_max, double alpha,
+                                 double* A_r, double* A_z) {
+  if (!A_r || !A_z) return MM_ERR_ARG;
+  if (n_r < 3 || n_z < 3 || n_r > 65536 || n_z > 65536) return MM_ERR_SHAPE;
+  if (!(r_min > 0.0) || !(r_max > r_min) || !(z_max > 0.0) || !std::isfinite(alpha)) return MM_ERR_ARG;
+  std::memset(A_r, 0, sizeof(double) * (size_t)n_r * n_r);
+  std::memset(A_z, 0, sizeof(double) * (size_t)n_z * n_z);
+  // r: nodes r_min + i h (i = 0..n-1), Neumann at both ends by mirrored
+  // ghost values (c_{-1} = c_1, c_n = c_{n-2})
+  const double hr = (r_max - r_min) / (n_r - 1);
+  for (int i = 0; i < n_r; ++i) {
+    const double r = r_min + i * hr;
+    const double lo = alpha * (1.0 / (hr * hr) - 0.5 / (hr * r));   // coefficient of c_{i-1}
+    const double hi = alpha * (1.0 / (hr * hr) + 0.5 / (hr * r));   // coefficient of c_{i+1}
+    const int il = i == 0 ? 1 : i - 1;
+    const int ih = i == n_r - 1 ? n_r - 2 : i + 1;
+    A_r[i + (size_t)i * n_r] += -2.0 * alpha / (hr * hr);
+    A_r[i + (size_t)il * n_r] += lo;
+    A_r[i + (size_t)ih * n_r] += hi;
+  }
+  // z: nodes j h (j = 1..n), c = 0 at z = 0, Neumann at z_max (c_{n+1} = c_{n-1})
+  const double hz = z_max / n_z;
+  for (int j = 0; j < n_z; ++j) {
+    const double z = (j + 1) * hz;
+    const double sv = 2.0 + std::tanh(4.0 * (z - 2.5)) - std::tanh(4.0 * (z - 5.0));
+    const double lo = alpha / (hz * hz) + 0.5 * sv / hz;
+    const double hi = alpha / (hz * hz) - 0.5 * sv / hz;
+    A_z[j + (size_t)j * n_z] += -2.0 * alpha / (hz * hz);
+    if (j > 0) A_z[j + (size_t)(j - 1) * n_z] += lo;
+    const int jh = j == n_z - 1 ? n_z - 2 : j + 1;
+    A_z[j + (size_t)jh * n_z] += hi;
+  }
+  return MM_OK;
+}
+
 }  // extern "C"

@@ -120,3 +120,41 @@ def test_host_builders_validate():
     assert lib.mm_expm(0, buf, 1.0, 0.0, buf) == _lib().MM_ERR_SHAPE
     nan = (C.c_double * 2)(float("nan"), 0.0)
     assert lib.mm_expm(1, nan, 1.0, 0.0, buf) == _lib().MM_ERR_NONFINITE
+
+
+@pytest.mark.parametrize("order", [2, 4, 6, 10, 16])
+def test_library_fd2_periodic_order_matches_oracle(order):
+    import paper_2103_01691_amd as mm
+    for n in (order + 1, 40, 101):
+        L = mm.fd2_periodic_order(n, 0.0, 2 * np.pi, order)
+        O = op.fd2_periodic_order(n, 0.0, 2 * np.pi, order)
+        assert np.max(np.abs(L - O)) <= 1e-9 * np.max(np.abs(O))
+
+
+@pytest.mark.parametrize("n", [2, 7, 24, 65, 128])
+def test_library_fourier_d2_matches_oracle(n):
+    import paper_2103_01691_amd as mm
+    L = mm.fourier_d2(n, -1.0, 3.0)
+    O = op.fourier_d2(n, -1.0, 3.0)
+    assert np.max(np.abs(L - O)) <= 1e-10 * np.max(np.abs(O))
+
+
+def test_library_pipe_flow_operators_match_oracle():
+    import paper_2103_01691_amd as mm
+    for nr, nz in ((3, 3), (50, 70), (200, 200)):
+        Lr, Lz = mm.pipe_flow_operators(nr, nz, 0.1, 5.0, 8.0, 1.0 / 90)
+        Or, Oz, _, _ = op.pipe_flow_operators(nr, nz, 0.1, 5.0, 8.0, 1.0 / 90)
+        assert np.max(np.abs(Lr - Or)) <= 1e-12 * np.max(np.abs(Or))
+        assert np.max(np.abs(Lz - Oz)) <= 1e-12 * np.max(np.abs(Oz))
+
+
+def test_front_end_builders_validate():
+    import paper_2103_01691_amd as mm
+    with pytest.raises(mm.MumodeError):
+        mm.fd2_periodic_order(10, 0.0, 1.0, 3)          # odd order
+    with pytest.raises(mm.MumodeError):
+        mm.fd2_periodic_order(4, 0.0, 1.0, 8)           # stencil wider than the grid
+    with pytest.raises(mm.MumodeError):
+        mm.fourier_d2(8, 1.0, 1.0)
+    with pytest.raises(mm.MumodeError):
+        mm.pipe_flow_operators(10, 10, 0.0, 5.0, 8.0)   # r_min must be > 0

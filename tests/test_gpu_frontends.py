@@ -1,0 +1,77 @@
+"""GPU parity of the integrator with the operator front-ends: centred
+differences of higher order and the Fourier spectral second derivative on
+the periodic heat problem of Section 4.1 (Test 2), and the non-constant-
+coefficient pipe-flow operators of Section 4.2."""
+import numpy as np
+import pytest
+
+from gpu_util import REL_TOL, cast, from_gpu, note, rel, to_gpu
+from oracle import mumode as om
+from oracle import operators as op
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import paper_2103_01691_amd as mm
+    c = mm.Context(0)
+    yield c
+    c.close()
+
+
+def _heat_u0(n):
+    x = 2 * np.pi * np.arange(n) / n
+    c = np.cos(x)
+    return c[:, None, None] + c[None, :, None] + c[None, None, :]
+
+
+@pytest.mark.parametrize("order", [4, 8, "spectral"])
+def test_periodic_heat_higher_order(ctx, order):
+    import paper_2103_01691_amd as mm
+    n, T = 40, 1.0
+    if order == "spectral":
+        Al, Ao = mm.fourier_d2(n, 0.0, 2 * np.pi), op.fourier_d2(n, 0.0, 2 * np.pi)
+    else:
+        Al, Ao = mm.fd2_periodic_order(n, 0.0, 2 * np.pi, order), op.fd2_periodic_order(n, 0.0, 2 * np.pi, order)
+    El = mm.expm(Al, T).real.copy()
+    Eo = op.exp_symmetric(Ao, T).real
+    u0 = _heat_u0(n)
+    ref = om.expstep(u0, [Eo] * 3, 1)
+    u = to_gpu(u0, "fp64", False)
+    ctx.mumode_expstep(u, [ctx.mm_op_prepare(El, "fp64")] * 3, 1)
+    got = from_gpu(u)
+    err = rel(got, ref)
+    # closed form: cos(x) is an eigenvector of every periodic stencil, with
+    # eigenvalue (w_0 + 2 sum_k w_k cos(k h)) / h^2 (-1 for the spectral
+    # matrix), so u(T) = exp(lambda T) u0
+    h = 2 * np.pi / n
+    if order == "spectral":
+        lam = -1.0
+    else:
+        w = op.central_d2_weights(order)
+        lam = (w[0] + 2 * sum(w[k] * np.cos(k * h) for k in range(1, len(w)))) / h ** 2
+    cf = rel(got, np.exp(lam * T) * u0)
+    note(f"periodic heat order={order}: rel err vs oracle {err:.3e}, vs closed form {cf:.3e}, "
+         f"vs continuum exp(-T) u0 {rel(got, np.exp(-T) * u0):.3e}")
+    assert err < 1e-12
+    assert cf < 1e-12
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_pipe_flow_step(ctx, prec):
+    import paper_2103_01691_amd as mm
+    from scipy.linalg import expm
+    n, T = 200, 1.0
+    rmin, rmax, zmax, alpha = 0.1, 5.0, 8.0, 1.0 / 90
+    Ar, Az, r, z = op.pipe_flow_operators(n, n, rmin, rmax, zmax, alpha)
+    c0 = np.exp(-8 * (r[:, None] - 0.5 * (rmin + rmax)) ** 2 - 8 * (z[None, :] - 1.5) ** 2)
+    c0 = cast(c0, prec, False)
+    ref = om.expstep(c0, [expm(T * Ar), expm(T * Az)], 1)
+    Lr, Lz = mm.pipe_flow_operators(n, n, rmin, rmax, zmax, alpha)
+    ops = [ctx.mm_op_prepare(mm.expm(L, T).real.copy(), prec) for L in (Lr, Lz)]
+    c = to_gpu(c0, prec, False)
+    ctx.mumode_expstep(c, ops, 1)
+    err = rel(from_gpu(c), ref)
+    note(f"pipe flow n={n} {prec} rel err {err:.3e}")
+    assert err < REL_TOL[prec] * (10 if prec == "fp64" else 1)
