@@ -261,6 +261,16 @@ mm_status mm_tune_clear(mm_ctx ctx);
 mm_status mm_tune_save(mm_ctx ctx, const char* path);
 mm_status mm_tune_load(mm_ctx ctx, const char* path);
 
+/* Context options.
+ *   MM_OPT_SMALL_RUN (default 1): mumode_expstep with nsteps >= 2, plain
+ *     FP64 or FP32 operators, a state of at most 2 MiB and modes of at most
+ *     128 real rows runs all steps in one single-workgroup launch (the
+ *     launch latency otherwise dominates such problems); 0 uses one launch
+ *     per product.
+ * MM_ERR_ARG for an unknown option. */
+enum { MM_OPT_SMALL_RUN = 1 };
+mm_status mm_set_option(mm_ctx ctx, int option, int64_t value);
+
 /* Hand the context a caller-owned device workspace (256-byte aligned) for
  * products that cannot run in place and for the transform chain; the
  * context then never allocates one and returns MM_ERR_NOMEM when a call

@@ -18,6 +18,8 @@ from . import _lib
 from ._lib import (MM_C64, MM_C128, MM_PREC_BF16, MM_PREC_FP32, MM_PREC_FP64,  # noqa: F401
                    MM_PREC_SPLIT_BF16X3, MM_PREC_SPLIT_FP16X2, MM_R32, MM_R64)
 
+MM_OPT_SMALL_RUN = 1
+
 PRECISIONS = {"fp64": MM_PREC_FP64, "fp32": MM_PREC_FP32, "bf16x3": MM_PREC_SPLIT_BF16X3,
               "fp16x2": MM_PREC_SPLIT_FP16X2, "bf16": MM_PREC_BF16}
 
@@ -311,6 +313,9 @@ class Context:
         return out
 
     # ------------------------------------------------- tuning, memory ----
+    def mm_set_option(self, option: int, value: int):
+        self._chk(_lib.lib.mm_set_option(self.handle, int(option), int(value)), "mm_set_option")
+
     def mm_autotune(self, T, E, budget_ms: int = 1000, stream=None):
         t = as_mm_tensor(T)
         self._chk(_lib.lib.mm_autotune(self.handle, C.byref(t), _op_array(E), int(budget_ms), _stream(stream)),

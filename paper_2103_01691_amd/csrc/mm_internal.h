@@ -107,6 +107,19 @@ hipError_t launch_mode(const ModePlan& plan, const ModeArgs& a, hipStream_t s);
 // Batched launch: `count` work items (device array) that all use `plan`'s
 // kernel (same precision, complexity, load path and tile class).
 hipError_t launch_mode_batch(const ModePlan& plan, const BatchItem* items, int count, hipStream_t s);
+// Whole-run kernel for small states (kern_small.hip): one workgroup, every
+// step and mode of an expstep.  m[k].A == nullptr skips mode k; every mode
+// must be planned with tile class SMALL_RUN_CLASS covering all its rows, with
+// in == out == the state.
+#define SMALL_RUN_CLASS 2
+struct SmallRun {
+  ModeArgs m[6];
+  int load[6];
+  int tiles[6];   // fibre tiles of mode k (its plan's grid_x)
+  int d, nsteps;
+};
+hipError_t launch_small_run(int prec, int cplx, const SmallRun& r, int* threads_out, hipStream_t s);
+
 // Force the tile class of split complex kernels (-1: automatic).  Also read
 // from MUMODE_SPLIT_TILE at first use.
 void set_split_class(int cls);

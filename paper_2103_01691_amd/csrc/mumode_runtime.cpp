@@ -39,6 +39,7 @@ struct mm_ctx_s {
   // path, real rows Mr, real columns Kr, fibres F) -> (class, microseconds)
   std::map<std::array<int64_t, 6>, std::pair<int, double>> tune;
   int force_cls = -1;            // set while the autotuner times a class
+  bool small_run = true;         // whole-run single-workgroup kernel for small expsteps
   double* red_partial = nullptr;
   double* red_result = nullptr;
   double* host_result = nullptr; // pinned
@@ -185,7 +186,8 @@ mm_status ensure_prepared(mm_ctx ctx, mm_op L, bool cplx, hipStream_t s, void** 
 // all rows in one workgroup (checked by the caller through *in_place_ok).
 mm_status run_mode(mm_ctx ctx, const void* in, void* out, const int64_t* dims, int d, mm_dtype dt,
                    mm_op L, int mu, double s_pre, double s_post, hipStream_t s, mm::ModePlan* plan_out,
-                   bool dry, const void* prep_override = nullptr, bool batch = false) {
+                   bool dry, const void* prep_override = nullptr, bool batch = false,
+                   mm::ModeArgs* args_out = nullptr) {
   const bool cplx = is_complex(dt);
   void* prep = nullptr;
   int KBT = 0, MFT = 0;
@@ -235,6 +237,7 @@ mm_status run_mode(mm_ctx ctx, const void* in, void* out, const int64_t* dims, i
                      force))
     return fail(ctx, MM_ERR_UNSUPPORTED, "no kernel plan for this shape");
   if (plan_out) *plan_out = plan;
+  if (args_out) *args_out = a;
   if (dry) return MM_OK;
   if (plan.prec == mm::KP_FP16X2) {
     if (in != ctx->chain_end) {
@@ -408,6 +411,66 @@ mm_status expm_device(mm_ctx ctx, int n, const double* A, const double* d, doubl
     std::swap(T, W);
   }
   HIPCHK(ctx, hipMemcpyAsync(out, T, sizeof(double) * mat, hipMemcpyDeviceToDevice, s));
+  return MM_OK;
+}
+
+// Whole run of a small expstep in one single-workgroup launch, when every
+// operator is plain FP64 / FP32, the state is small enough to stay in one
+// XCD's L2 (<= 2 MiB) and every mode fits one tile of the small-run class.
+// *used = false (and nothing launched) when the problem does not qualify.
+mm_status small_expstep(mm_ctx ctx, mm_tensor* T, const mm_op* E, int nsteps, hipStream_t s, bool* used) {
+  *used = false;
+  const size_t bytes = (size_t)numel(T) * dsize(T->dtype);
+  if (bytes > ((size_t)2 << 20) || T->d > 6) return MM_OK;
+  const bool cplx = is_complex(T->dtype);
+  mm::SmallRun r;
+  std::memset(&r, 0, sizeof r);
+  r.d = T->d;
+  r.nsteps = nsteps;
+  int kp = -1;
+  for (int k = 0; k < T->d; ++k) {
+    if (!E[k]) continue;
+    const int p = kprec(E[k]->prec);
+    if ((p != mm::KP_F64 && p != mm::KP_F32) || (kp >= 0 && p != kp)) return MM_OK;
+    kp = p;
+    mm::ModePlan plan;
+    mm::ModeArgs a;
+    mm_status st = run_mode(ctx, T->data, T->data, T->dims, T->d, T->dtype, E[k], k + 1, 0, 0, s, &plan, true,
+                            nullptr, false, &a);
+    if (st != MM_OK) {
+      ctx->err.clear();
+      return MM_OK;
+    }
+    // one row tile of the small-run class must hold all rows of the mode
+    mm::TileShape t;
+    if (!mm::tile_shape(p, SMALL_RUN_CLASS, &t)) return MM_OK;
+    const mm::FragGeom fgm = mm::frag_geom(p);
+    const int rows = t.WM * t.WMF * fgm.MB;
+    const int64_t nt = (int64_t)t.WN * t.WNF * fgm.NB;
+    if (a.Mr > rows) return MM_OK;
+    plan.grid_x = (int)((a.F + nt - 1) / nt);
+    void* prep = nullptr;
+    int KBT = 0, MFT = 0;
+    st = ensure_prepared(ctx, E[k], cplx, s, &prep, &KBT, &MFT);
+    if (st != MM_OK) return st;
+    a.A = prep;
+    r.m[k] = a;
+    r.load[k] = plan.load;
+    r.tiles[k] = plan.grid_x;
+  }
+  if (kp < 0) return MM_OK;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (ctx->profiling) {
+    HIPCHK(ctx, hipEventCreate(&e0));
+    HIPCHK(ctx, hipEventCreate(&e1));
+    HIPCHK(ctx, hipEventRecord(e0, s));
+  }
+  HIPCHK(ctx, mm::launch_small_run(kp, cplx ? 1 : 0, r, nullptr, s));
+  if (ctx->profiling) {
+    HIPCHK(ctx, hipEventRecord(e1, s));
+    ctx->recs.push_back({kp * 1000 + (cplx ? 100 : 0) + 90, e0, e1});
+  }
+  *used = true;
   return MM_OK;
 }
 
@@ -602,6 +665,11 @@ mm_status mumode_expstep(mm_ctx ctx, mm_tensor* T, const mm_op* E, int nsteps, m
   }
   HIPCHK(ctx, hipSetDevice(ctx->device));
   ctx->chain_end = nullptr;
+  if (ctx->small_run && nsteps >= 2) {
+    bool used = false;
+    st = small_expstep(ctx, T, E, nsteps, (hipStream_t)stream, &used);
+    if (st != MM_OK || used) return st;
+  }
   for (int it = 0; it < nsteps; ++it) {
     st = sweep(ctx, T, E, 0.0, 0.0, (hipStream_t)stream);
     if (st != MM_OK) return st;
@@ -1354,6 +1422,17 @@ mm_status mumode_magnus_step(mm_ctx ctx, mm_tensor* T, const mm_matrix* B, const
     }
   }
   return MM_OK;
+}
+
+mm_status mm_set_option(mm_ctx ctx, int option, int64_t value) {
+  if (!ctx) return MM_ERR_ARG;
+  switch (option) {
+    case MM_OPT_SMALL_RUN:
+      ctx->small_run = value != 0;
+      return MM_OK;
+    default:
+      return fail(ctx, MM_ERR_ARG, "unknown option %d", option);
+  }
 }
 
 }  // extern "C"
