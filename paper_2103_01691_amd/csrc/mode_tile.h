@@ -617,7 +617,55 @@ __device__ __forceinline__ void mode_tile(const ModeArgs& a, int64_t tile_x, int
   // FP16X2: the accumulators hold 2^11 * 2^-(s_exp + a_exp) * result
   const int o_exp = s_exp + a.a_exp - 11;
   float vmax = 0.0f;   // FP16X2: max |component| stored by this lane
-  if constexpr (FULL) {
+  // Contiguous fibres (mu = 1): each lane of an MFMA fragment holds one
+  // fibre, so direct stores would write 8 bytes per lane at fibre stride.
+  // When the tile is full and the LDS can hold a wave's fragments of one
+  // M-fragment row, stage them there (swizzled 16-byte blocks, [fibre][32
+  // real rows]) and write every fibre's 32 rows as one 128-byte run (eight
+  // lanes x 16 bytes).
+  constexpr bool T_EPI = FULL && LD == KL_KCONTIG && MB == 32 && sizeof(st) == 4 &&
+                         (size_t)2 * CHUNK * sizeof(pc) >= (size_t)WM * WN * WNF * 32 * 32 * 4;
+  if constexpr (T_EPI) {
+    typedef float f32x4v __attribute__((ext_vector_type(4)));
+    __syncthreads();   // every wave is done with the main loop's LDS
+    float* reg = (float*)lds + (size_t)wave * WNF * 32 * 32;
+    st* __restrict__ out = (st*)a.out;
+    const st s_post = (st)a.s_post;
+#pragma unroll
+    for (int i = 0; i < WMF; ++i) {
+      const int mf = mf0 + i;
+#pragma unroll
+      for (int j = 0; j < WNF; ++j)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int f = j * 32 + (lane % 32);
+          const int b = 2 * q + lane / 32;   // rows 8q + 4(lane/32) .. +3
+          f32x4v v;
+#pragma unroll
+          for (int r = 0; r < 4; ++r) v[r] = (float)acc[i][j][4 * q + r];
+          *(f32x4v*)(reg + f * 32 + ((b ^ (f & 7)) * 4)) = v;
+        }
+#pragma unroll
+      for (int sblk = 0; sblk < WNF * 32 / 8; ++sblk) {
+        const int f = 8 * sblk + lane / 8;
+        const int b = lane % 8;              // rows 4b .. 4b+3 of the fragment
+        f32x4v v = *(const f32x4v*)(reg + f * 32 + ((b ^ (f & 7)) * 4));
+        st w[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          w[r] = v[r];
+          if constexpr (F16) w[r] = ldexpf(w[r], o_exp);
+        }
+        if constexpr (CPLX && EPI) {
+          phase<st>(w[0], w[1], s_post);
+          phase<st>(w[2], w[3], s_post);
+        }
+        if constexpr (F16) vmax = fmaxf(vmax, fmaxf(fmaxf(fabsf(w[0]), fabsf(w[1])), fmaxf(fabsf(w[2]), fabsf(w[3]))));
+        const int64_t fg = f0 + (int64_t)nf0 * NB + f;
+        *(f32x4v*)(out + fg * a.Mr + mf * 32 + 4 * b) = f32x4v{w[0], w[1], w[2], w[3]};
+      }
+    }
+  } else if constexpr (FULL) {
     // Every row and fibre of the tile exists and every byte offset of the
     // output fits in 32 bits (checked by the planner): a store address is
     // a wave-uniform base (row) plus a per-fragment lane offset (fibre).
