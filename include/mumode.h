@@ -181,8 +181,9 @@ mm_status ho_strang_step(mm_ctx ctx, mm_tensor* psi, const mm_op* Lh, const doub
  * Instances may differ in d, dims, dtype (real / complex) and precision.  One
  * step of the whole batch is a single HIP graph (captured on the first call
  * with a given set of tensors and operators, replayed afterwards): for each
- * mode, one grouped launch per kernel kind covers every instance's fibre
- * tiles.  Requires every n_mu <= 256 (complex) / 512 (real) and P % 4 == 0
+ * mode, one launch per precision covers every instance's fibre tiles (each
+ * work item selects its tile code: real / complex, fibre load path, tile
+ * shape).  Requires every n_mu <= 256 (complex) / 512 (real) and P % 4 == 0
  * for the strided modes (MM_ERR_UNSUPPORTED otherwise).  E[i] is an array of
  * d_i operators (NULL entries leave the mode unchanged). */
 mm_status mumode_expstep_batched(mm_ctx ctx, int count, mm_tensor* const* T, const mm_op* const* E, int nsteps,

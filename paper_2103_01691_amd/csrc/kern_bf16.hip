@@ -7,4 +7,5 @@ KernFn pick_kernel_bf16(int cplx, int ld, int pro, int epi, int cls, int full) {
 }
 BatchFn pick_batch_bf16(int cplx, int ld, int cls) { return pick_batch<KP_BF16>(cplx, ld, cls); }
 bool tile_shape_bf16(int cls, TileShape* out) { return shape_table<KP_BF16>(cls, out); }
+BatchFn pick_batch_merged_bf16() { return pick_batch_merged<KP_BF16>(); }
 }  // namespace mm

@@ -7,4 +7,5 @@ KernFn pick_kernel_f32(int cplx, int ld, int pro, int epi, int cls, int full) {
 }
 BatchFn pick_batch_f32(int cplx, int ld, int cls) { return pick_batch<KP_F32>(cplx, ld, cls); }
 bool tile_shape_f32(int cls, TileShape* out) { return shape_table<KP_F32>(cls, out); }
+BatchFn pick_batch_merged_f32() { return pick_batch_merged<KP_F32>(); }
 }  // namespace mm

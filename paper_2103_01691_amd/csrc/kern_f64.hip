@@ -7,4 +7,5 @@ KernFn pick_kernel_f64(int cplx, int ld, int pro, int epi, int cls, int full) {
 }
 BatchFn pick_batch_f64(int cplx, int ld, int cls) { return pick_batch<KP_F64>(cplx, ld, cls); }
 bool tile_shape_f64(int cls, TileShape* out) { return shape_table<KP_F64>(cls, out); }
+BatchFn pick_batch_merged_f64() { return pick_batch_merged<KP_F64>(); }
 }  // namespace mm

@@ -378,6 +378,20 @@ hipError_t launch_mode_batch(const ModePlan& p, const BatchItem* items, int coun
   return hipGetLastError();
 }
 
+hipError_t launch_mode_batch_merged(int prec, const BatchItem* items, int count, hipStream_t s) {
+  BatchFn fn = nullptr;
+  switch (prec) {
+    case KP_F64: fn = pick_batch_merged_f64(); break;
+    case KP_F32: fn = pick_batch_merged_f32(); break;
+    case KP_BF16X3: fn = pick_batch_merged_bf16x3(); break;
+    case KP_BF16: fn = pick_batch_merged_bf16(); break;
+    default: return hipErrorInvalidDeviceFunction;
+  }
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(fn, dim3(count), dim3(256), 0, s, items);
+  return hipGetLastError();
+}
+
 hipError_t launch_prepare(int prec, int cplx, const double* master, int64_t rows, int64_t cols,
                           int64_t ld, PhaseScale ph, void* out, int KBT, int MFT, hipStream_t s,
                           int a_exp) {

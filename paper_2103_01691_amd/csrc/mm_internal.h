@@ -51,7 +51,7 @@ struct BatchItem {
   ModeArgs a;
   int64_t tile_x;
   int tile_y;
-  int pad_;
+  int kind;            // complex * 100 + load path * 10 + tile class (0..2)
 };
 
 typedef void (*KernFn)(ModeArgs);
@@ -83,6 +83,15 @@ bool tile_shape_fp16x2(int cls, TileShape* out);
 bool tile_shape_bf16(int cls, TileShape* out);
 
 bool tile_shape(int prec, int cls, TileShape* out);
+
+// Merged batched launch: one kernel per precision runs work items of every
+// kind (complex / real, contiguous / strided fibres, tile class 0..2; all
+// 256 threads), so every instance tile of one mode goes in a single launch.
+BatchFn pick_batch_merged_f64();
+BatchFn pick_batch_merged_f32();
+BatchFn pick_batch_merged_bf16x3();
+BatchFn pick_batch_merged_bf16();
+hipError_t launch_mode_batch_merged(int prec, const BatchItem* items, int count, hipStream_t s);
 
 // Per-launch plan chosen by the runtime.
 struct ModePlan {

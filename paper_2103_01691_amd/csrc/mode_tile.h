@@ -994,4 +994,55 @@ bool shape_table(int cls, TileShape* out) {
   return false;
 }
 
+// Merged batched kernel of one precision: a work item's kind selects the
+// tile code (complex, load path, tile class 0..2), so items of every kind
+// share one launch.  All classes 0..2 use 4 waves.
+template <int PR, int CLS>
+constexpr int lds_scalars() {
+  typedef Cfg<PR, CLS> C;
+  return 2 * C::KCH * C::WN * C::WNF * Tr<PR>::NPB * 64 * Tr<PR>::KPL;
+}
+
+template <int PR>
+constexpr int merged_lds_scalars() {
+  constexpr int a = lds_scalars<PR, 0>(), b = lds_scalars<PR, 1>(), c = lds_scalars<PR, 2>();
+  return a > b ? (a > c ? a : c) : (b > c ? b : c);
+}
+
+template <int PR>
+__global__ __launch_bounds__(256) void mode_batch_merged_kernel(const BatchItem* __restrict__ items) {
+  typedef typename Tr<PR>::pc pc;
+  __shared__ __attribute__((aligned(16))) pc lds[merged_lds_scalars<PR>()];
+  const BatchItem& it = items[blockIdx.x];
+  const ModeArgs a = it.a;
+#define MM_MK(C_, L_, K_)                                                                                  \
+  case (C_ ? 100 : 0) + L_ * 10 + K_: {                                                                    \
+    typedef Cfg<PR, K_> CF;                                                                                \
+    static_assert(CF::WM * CF::WN == 4, "merged batch classes use 4 waves");                               \
+    mode_tile<PR, C_, L_, CF::WMF, CF::WNF, CF::WM, CF::WN, CF::KCH, false, false, 1>(a, it.tile_x, it.tile_y, lds); \
+    break;                                                                                                 \
+  }
+  switch (it.kind) {
+    MM_MK(true, KL_KCONTIG, 0)
+    MM_MK(true, KL_KCONTIG, 1)
+    MM_MK(true, KL_KCONTIG, 2)
+    MM_MK(true, KL_FCONTIG, 0)
+    MM_MK(true, KL_FCONTIG, 1)
+    MM_MK(true, KL_FCONTIG, 2)
+    MM_MK(false, KL_KCONTIG, 0)
+    MM_MK(false, KL_KCONTIG, 1)
+    MM_MK(false, KL_KCONTIG, 2)
+    MM_MK(false, KL_FCONTIG, 0)
+    MM_MK(false, KL_FCONTIG, 1)
+    MM_MK(false, KL_FCONTIG, 2)
+    default: break;
+  }
+#undef MM_MK
+}
+
+template <int PR>
+BatchFn pick_batch_merged() {
+  return &mode_batch_merged_kernel<PR>;
+}
+
 }  // namespace mm

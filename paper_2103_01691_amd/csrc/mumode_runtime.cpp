@@ -941,14 +941,16 @@ mm_status mumode_expstep_batched(mm_ctx ctx, int count, mm_tensor* const* T, con
         a.smax_clr = nullptr;
         a.a_exp = 0;
         a.pad_ = 0;
-        const uint64_t key = (uint64_t)plan.prec * 1000 + plan.cplx * 100 + plan.load * 10 + plan.cls;
+        // one merged launch per (mode, precision); the item's kind selects its tile code
+        const uint64_t key = (uint64_t)plan.prec;
+        const int kind = plan.cplx * 100 + plan.load * 10 + plan.cls;
         size_t g = 0;
         while (g < byk.size() && byk[g].first != key) ++g;
         if (g == byk.size()) {
           byk.push_back({key, {}});
           plans.push_back(plan);
         }
-        for (int tx = 0; tx < plan.grid_x; ++tx) byk[g].second.push_back(mm::BatchItem{a, tx, 0, 0});
+        for (int tx = 0; tx < plan.grid_x; ++tx) byk[g].second.push_back(mm::BatchItem{a, tx, 0, kind});
       }
       for (size_t g = 0; g < byk.size(); ++g) {
         groups.push_back({plans[g], (int)items.size(), (int)byk[g].second.size()});
@@ -983,7 +985,7 @@ mm_status mumode_expstep_batched(mm_ctx ctx, int count, mm_tensor* const* T, con
     HIPCHK(ctx, hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal));
     hipError_t le = hipSuccess;
     for (const auto& g : ctx->bgroups) {
-      le = mm::launch_mode_batch(g.plan, ctx->bitems + g.offset, g.count, ctx->cap_stream);
+      le = mm::launch_mode_batch_merged(g.plan.prec, ctx->bitems + g.offset, g.count, ctx->cap_stream);
       if (le != hipSuccess) break;
     }
     hipGraph_t graph = nullptr;
