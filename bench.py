@@ -349,8 +349,7 @@ def main():
         "dtype": split,
         "data": "synthetic",
         "config": {"workload": f"gpe3d_strang_n256_split_{split}", "d": D, "n": N, "beta": BETA, "tau": TAU,
-                   "domain": [A, B], "state": "complex64", "precision": f"split_{split}_fp32acc",
-                   "parallelism": "single_gpu"},
+                   "domain": [A, B], "state": "complex64", "precision": f"split_{split}_fp32acc"},
         "tflops_effective": FLOPS_PER_STEP / (ms * 1e-3) / 1e12,
         "roofline": {
             "bound": "mfma", "achieved": achieved / 1e12 if achieved else None, "peak": PEAK["bf16"] / 1e12,
