@@ -574,8 +574,24 @@ __device__ __forceinline__ void mode_tile(const ModeArgs& a, int64_t tile_x, int
         if (kk == 0 && more) load_chunk(c + 1);
         if (kk + 1 < KCH) read_b(L, kk + 1, b_buf[nxt]);
         finish_a(a_buf[cur]);
-        __builtin_amdgcn_sched_barrier(0);
+        if constexpr (KPL != 8) __builtin_amdgcn_sched_barrier(0);
         mfma_kblock(a_buf[cur], b_buf[cur]);
+        if constexpr (KPL == 8) {
+          // split kernels (many MFMAs per K-block): issue the next K-block's
+          // operator loads and LDS reads one at a time between this
+          // K-block's MFMAs, so their issue cycles hide under MFMA execution
+#pragma unroll
+          for (int g = 0; g < WMF * NPS + (kk == 0 ? TPT * 4 : 0); ++g) {
+            __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+            __builtin_amdgcn_sched_group_barrier(0x020, 1, 0);
+          }
+#pragma unroll
+          for (int g = 0; g < WNF * NPB; ++g) {
+            __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+            __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+          }
+          if (kk + 1 < KCH) __builtin_amdgcn_sched_group_barrier(0x008, 64, 0);
+        }
         if (kk + 1 < KCH) {
           __builtin_amdgcn_sched_barrier(0);
         } else {
