@@ -102,3 +102,40 @@ def test_gpe_one_step_from_developed_state(ctx, trajectory, prec):
     err = rel(from_gpu(psi), ref)
     note(f"gpe n={N} one step from step {STEPS // 2} {prec}: rel L2 {err:.3e}")
     assert err < REL_TOL[prec]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "fp16x2"])
+def test_ho_200_steps(ctx, prec):
+    # harmonic oscillator with time-dependent potential, 200 Strang steps of
+    # tau = 0.02 (T = 4), Hermite m = 32
+    import paper_2103_01691_amd as mm
+    from gpu_util import cast
+    m, kmax, tau, eps, steps = 32, 8, 0.02, 0.1, 200
+    Phi, Psi, X = op.hermite_forward(m), op.hermite_backward(m), op.hermite_nodes(m)
+    c = synth.hermite_coefficients(m, kmax, 3, cfg_id=3)
+    psi0 = cast(om.tucker(c, [Psi] * 3), prec, True)
+    ref = sc.ho_strang(psi0, [Phi] * 3, [Psi] * 3, [X] * 3, 0.0, tau, eps, steps)
+    Xl, _ = mm.hermite_nodes(m)
+    Lh = ctx.mm_op_prepare(mm.hermite_ho_exponential(m, tau), prec)
+    psi = to_gpu(psi0, prec, True)
+    ctx.ho_strang_step(psi, [Lh] * 3, [Xl] * 3, 0.0, tau, eps, steps)
+    err = rel(from_gpu(psi), ref)
+    note(f"ho m={m} {steps} steps {prec}: rel L2 {err:.3e}")
+    assert err < (1e-11 if prec == "fp64" else 1e-5)      # measured 1.4e-12 / 3.1e-6 / 2.6e-6
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3", "fp16x2"])
+def test_free_schrodinger_100_steps(ctx, prec):
+    # free Schroedinger, 100 steps of tau = 0.01 (T = 1), n = 64 on [-10, 10]^3
+    import paper_2103_01691_amd as mm
+    from gpu_util import cast
+    n, a, b, tau, steps = 64, -10.0, 10.0, 0.01, 100
+    psi0 = cast(synth.wavepacket_initial(n, a, b, 3, cfg_id=2), prec, True)
+    Eo = op.free_schrodinger_exponential(n, a, b, tau)
+    ref = om.expstep(psi0, [Eo] * 3, steps)
+    E = mm.expm(mm.fd2_matrix(n, a, b), 0.5j * tau)
+    psi = to_gpu(psi0, prec, True)
+    ctx.mumode_expstep(psi, [ctx.mm_op_prepare(E, prec)] * 3, steps)
+    err = rel(from_gpu(psi), ref)
+    note(f"free schrodinger n={n} {steps} steps {prec}: rel L2 {err:.3e}")
+    assert err < (1e-11 if prec == "fp64" else 1e-5)      # measured 2e-13 / 3.9e-6 .. 5.4e-6
