@@ -268,9 +268,21 @@ mm_status mm_tune_load(mm_ctx ctx, const char* path);
  *     128 real rows runs all steps in one single-workgroup launch (the
  *     launch latency otherwise dominates such problems); 0 uses one launch
  *     per product.
- * MM_ERR_ARG for an unknown option. */
-enum { MM_OPT_SMALL_RUN = 1 };
+ *   MM_OPT_MONITOR_EVERY (default 0 = off): mumode_expstep and
+ *     gpe_strang_step record the FP64 sum |T|^2 (the discrete mass without the
+ *     cell volume, §2) after every `value` steps and after the last one, on
+ *     the device, and read the log back once when the call ends (one
+ *     synchronisation per call); a non-finite entry makes the call return
+ *     MM_ERR_NONFINITE.  The Strang phase flows keep |psi|, so the merged
+ *     steps give the mass at the step times.  Disables MM_OPT_SMALL_RUN.
+ * MM_ERR_ARG for an unknown option or value. */
+enum { MM_OPT_SMALL_RUN = 1, MM_OPT_MONITOR_EVERY = 2 };
 mm_status mm_set_option(mm_ctx ctx, int option, int64_t value);
+
+/* Monitor log of the last mumode_expstep / gpe_strang_step call on this
+ * context: *count entries (step count after which it was taken, sum |T|^2);
+ * at most max_records are written to steps / sums (either may be NULL). */
+mm_status mm_monitor_log(mm_ctx ctx, int max_records, int* count, int* steps, double* sums);
 
 /* Hand the context a caller-owned device workspace (256-byte aligned) for
  * products that cannot run in place and for the transform chain; the

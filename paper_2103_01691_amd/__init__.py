@@ -19,6 +19,7 @@ from ._lib import (MM_C64, MM_C128, MM_PREC_BF16, MM_PREC_FP32, MM_PREC_FP64,  #
                    MM_PREC_SPLIT_BF16X3, MM_PREC_SPLIT_FP16X2, MM_R32, MM_R64)
 
 MM_OPT_SMALL_RUN = 1
+MM_OPT_MONITOR_EVERY = 2
 
 PRECISIONS = {"fp64": MM_PREC_FP64, "fp32": MM_PREC_FP32, "bf16x3": MM_PREC_SPLIT_BF16X3,
               "fp16x2": MM_PREC_SPLIT_FP16X2, "bf16": MM_PREC_BF16}
@@ -315,6 +316,14 @@ class Context:
     # ------------------------------------------------- tuning, memory ----
     def mm_set_option(self, option: int, value: int):
         self._chk(_lib.lib.mm_set_option(self.handle, int(option), int(value)), "mm_set_option")
+
+    def mm_monitor_log(self, max_records: int = 1 << 16):
+        """List of (steps, sum |T|^2) recorded by the last monitored call."""
+        n = C.c_int()
+        st = (C.c_int * max_records)()
+        v = (C.c_double * max_records)()
+        self._chk(_lib.lib.mm_monitor_log(self.handle, max_records, C.byref(n), st, v), "mm_monitor_log")
+        return [(st[i], v[i]) for i in range(min(n.value, max_records))]
 
     def mm_autotune(self, T, E, budget_ms: int = 1000, stream=None):
         t = as_mm_tensor(T)

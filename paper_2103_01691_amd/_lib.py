@@ -28,7 +28,7 @@ EXPORTS = [
     "mm_fd2_matrix", "mm_expm", "mm_hermite_nodes", "mm_hermite_matrices",
     "mm_autotune", "mm_tune_count", "mm_tune_get", "mm_tune_clear", "mm_tune_save", "mm_tune_load",
     "mm_set_workspace", "mumode_magnus_step", "mm_expm_device",
-    "mm_fd2_periodic_order", "mm_fourier_d2", "mm_pipe_flow_operators", "mm_set_option",
+    "mm_fd2_periodic_order", "mm_fourier_d2", "mm_pipe_flow_operators", "mm_set_option", "mm_monitor_log",
 ]
 
 
@@ -90,6 +90,7 @@ def _load():
         "mm_fd2_periodic_order": (st, [C.c_int, d, d, C.c_int, C.POINTER(d)]),
         "mm_fourier_d2": (st, [C.c_int, d, d, C.POINTER(d)]),
         "mm_set_option": (st, [P, C.c_int, C.c_int64]),
+        "mm_monitor_log": (st, [P, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(d)]),
         "mm_pipe_flow_operators": (st, [C.c_int, C.c_int, d, d, d, d, C.POINTER(d), C.POINTER(d)]),
     }
     for name, (res, args) in sig.items():

@@ -40,6 +40,13 @@ struct mm_ctx_s {
   std::map<std::array<int64_t, 6>, std::pair<int, double>> tune;
   int force_cls = -1;            // set while the autotuner times a class
   bool small_run = true;         // whole-run single-workgroup kernel for small expsteps
+  // in-call monitor (MM_OPT_MONITOR_EVERY): sum |T|^2 every mon_every steps
+  // of mumode_expstep / gpe_strang_step, kept on the device until the call ends
+  int mon_every = 0;
+  double* mon_dev = nullptr;
+  size_t mon_cap = 0;
+  std::vector<int> mon_steps;
+  std::vector<double> mon_vals;
   double* red_partial = nullptr;
   double* red_result = nullptr;
   double* host_result = nullptr; // pinned
@@ -414,6 +421,49 @@ mm_status expm_device(mm_ctx ctx, int n, const double* A, const double* d, doubl
   return MM_OK;
 }
 
+// In-call monitor: FP64 sum |T|^2 after `step` steps into the next slot of
+// the device log (no host synchronisation until monitor_end).
+mm_status monitor_begin(mm_ctx ctx, int nsteps) {
+  ctx->mon_steps.clear();
+  ctx->mon_vals.clear();
+  if (ctx->mon_every <= 0 || nsteps <= 0) return MM_OK;
+  const size_t need = (size_t)(nsteps / ctx->mon_every + 2);
+  if (ctx->mon_cap < need) {
+    if (ctx->mon_dev) {
+      HIPCHK(ctx, hipDeviceSynchronize());
+      HIPCHK(ctx, hipFree(ctx->mon_dev));
+      ctx->mon_dev = nullptr;
+      ctx->mon_cap = 0;
+    }
+    if (hipMalloc((void**)&ctx->mon_dev, sizeof(double) * need) != hipSuccess)
+      return fail(ctx, MM_ERR_NOMEM, "monitor log");
+    ctx->mon_cap = need;
+  }
+  return MM_OK;
+}
+
+mm_status monitor_point(mm_ctx ctx, const mm_tensor* T, int step, hipStream_t s) {
+  const size_t k = ctx->mon_steps.size();
+  if (k >= ctx->mon_cap) return MM_OK;
+  const int64_t count = numel(T) * (is_complex(T->dtype) ? 2 : 1);
+  HIPCHK(ctx, mm::launch_reduce(mm::RED_SQ, T->data, nullptr, count, is_f64(T->dtype) ? 1 : 0, ctx->red_partial,
+                                ctx->mon_dev + k, s));
+  ctx->mon_steps.push_back(step);
+  return MM_OK;
+}
+
+mm_status monitor_end(mm_ctx ctx, hipStream_t s) {
+  const size_t k = ctx->mon_steps.size();
+  if (k == 0) return MM_OK;
+  ctx->mon_vals.resize(k);
+  HIPCHK(ctx, hipMemcpyAsync(ctx->mon_vals.data(), ctx->mon_dev, sizeof(double) * k, hipMemcpyDeviceToHost, s));
+  HIPCHK(ctx, hipStreamSynchronize(s));
+  for (size_t i = 0; i < k; ++i)
+    if (!std::isfinite(ctx->mon_vals[i]))
+      return fail(ctx, MM_ERR_NONFINITE, "sum |T|^2 is not finite after step %d", ctx->mon_steps[i]);
+  return MM_OK;
+}
+
 // Whole run of a small expstep in one single-workgroup launch, when every
 // operator is plain FP64 / FP32, the state is small enough to stay in one
 // XCD's L2 (<= 2 MiB) and every mode fits one tile of the small-run class.
@@ -558,6 +608,7 @@ mm_status mm_destroy(mm_ctx ctx) {
   if (ctx->red_partial) hipFree(ctx->red_partial);
   if (ctx->red_result) hipFree(ctx->red_result);
   if (ctx->smax) hipFree(ctx->smax);
+  if (ctx->mon_dev) hipFree(ctx->mon_dev);
   if (ctx->ex_buf) hipFree(ctx->ex_buf);
   if (ctx->ex_prep) hipFree(ctx->ex_prep);
   if (ctx->host_result) hipHostFree(ctx->host_result);
@@ -652,6 +703,8 @@ mm_status mumode_apply(mm_ctx ctx, mm_tensor* out, const mm_tensor* T, mm_op L, 
 
 mm_status mumode_expstep(mm_ctx ctx, mm_tensor* T, const mm_op* E, int nsteps, mm_stream stream) {
   if (!ctx) return MM_ERR_ARG;
+  ctx->mon_steps.clear();
+  ctx->mon_vals.clear();
   mm_status st = check_tensor(ctx, T, "T");
   if (st != MM_OK) return st;
   if (!E) return fail(ctx, MM_ERR_ARG, "E is NULL");
@@ -665,16 +718,22 @@ mm_status mumode_expstep(mm_ctx ctx, mm_tensor* T, const mm_op* E, int nsteps, m
   }
   HIPCHK(ctx, hipSetDevice(ctx->device));
   ctx->chain_end = nullptr;
-  if (ctx->small_run && nsteps >= 2) {
+  if (ctx->small_run && nsteps >= 2 && ctx->mon_every <= 0) {
     bool used = false;
     st = small_expstep(ctx, T, E, nsteps, (hipStream_t)stream, &used);
     if (st != MM_OK || used) return st;
   }
+  st = monitor_begin(ctx, nsteps);
+  if (st != MM_OK) return st;
   for (int it = 0; it < nsteps; ++it) {
     st = sweep(ctx, T, E, 0.0, 0.0, (hipStream_t)stream);
     if (st != MM_OK) return st;
+    if (ctx->mon_every > 0 && ((it + 1) % ctx->mon_every == 0 || it + 1 == nsteps)) {
+      st = monitor_point(ctx, T, it + 1, (hipStream_t)stream);
+      if (st != MM_OK) return st;
+    }
   }
-  return MM_OK;
+  return monitor_end(ctx, (hipStream_t)stream);
 }
 
 mm_status mumode_transform(mm_ctx ctx, mm_tensor* out, const mm_tensor* in, const mm_op* Phi, mm_stream stream) {
@@ -746,6 +805,8 @@ mm_status mumode_transform(mm_ctx ctx, mm_tensor* out, const mm_tensor* in, cons
 mm_status gpe_strang_step(mm_ctx ctx, mm_tensor* psi, const mm_op* E, double tau, double beta, int nsteps,
                           mm_stream stream) {
   if (!ctx) return MM_ERR_ARG;
+  ctx->mon_steps.clear();
+  ctx->mon_vals.clear();
   mm_status st = check_tensor(ctx, psi, "psi");
   if (st != MM_OK) return st;
   if (!is_complex(psi->dtype)) return fail(ctx, MM_ERR_DTYPE, "psi must be complex");
@@ -765,13 +826,21 @@ mm_status gpe_strang_step(mm_ctx ctx, mm_tensor* psi, const mm_op* E, double tau
   // between steps is fused into the staging of the next step's first product
   // (where it overlaps MFMA work), the last N(tau/2) into the final epilogue
   const double half = 0.5 * tau * beta, full = tau * beta;
+  st = monitor_begin(ctx, nsteps);
+  if (st != MM_OK) return st;
   for (int it = 0; it < nsteps; ++it) {
     const double pre = (it == 0) ? half : full;
     const double post = (it + 1 < nsteps) ? 0.0 : half;
     st = sweep(ctx, psi, E, pre, post, (hipStream_t)stream);
     if (st != MM_OK) return st;
+    // the phase flows keep |psi|, so the mass between merged steps is the
+    // mass after the step
+    if (ctx->mon_every > 0 && ((it + 1) % ctx->mon_every == 0 || it + 1 == nsteps)) {
+      st = monitor_point(ctx, psi, it + 1, (hipStream_t)stream);
+      if (st != MM_OK) return st;
+    }
   }
-  return MM_OK;
+  return monitor_end(ctx, (hipStream_t)stream);
 }
 
 mm_status ho_strang_step(mm_ctx ctx, mm_tensor* psi, const mm_op* Lh, const double* const* nodes, double t0,
@@ -1432,9 +1501,24 @@ mm_status mm_set_option(mm_ctx ctx, int option, int64_t value) {
     case MM_OPT_SMALL_RUN:
       ctx->small_run = value != 0;
       return MM_OK;
+    case MM_OPT_MONITOR_EVERY:
+      if (value < 0 || value > (1 << 30)) return fail(ctx, MM_ERR_ARG, "monitor interval %lld", (long long)value);
+      ctx->mon_every = (int)value;
+      return MM_OK;
     default:
       return fail(ctx, MM_ERR_ARG, "unknown option %d", option);
   }
+}
+
+mm_status mm_monitor_log(mm_ctx ctx, int max_records, int* count, int* steps, double* sums) {
+  if (!ctx || !count) return MM_ERR_ARG;
+  const int k = (int)ctx->mon_vals.size();
+  for (int i = 0; i < k && i < max_records; ++i) {
+    if (steps) steps[i] = ctx->mon_steps[i];
+    if (sums) sums[i] = ctx->mon_vals[i];
+  }
+  *count = k;
+  return MM_OK;
 }
 
 }  // extern "C"
