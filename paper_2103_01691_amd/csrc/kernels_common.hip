@@ -67,8 +67,9 @@ __global__ void prepare_kernel(const double* __restrict__ master, int64_t rows, 
     } else if constexpr (PR == KP_F32) {
       out[base] = (float)x;
     } else if constexpr (PR == KP_FP16X2) {
-      // stored pieces (h 2^11, l) of x 2^-a_exp = h + 2^-11 l (the kernel
-      // forms h itself); the residual is exact in FP64
+      // stored pieces (h 2^11, l) of x 2^-a_exp = h + 2^-11 l; the residual
+      // is exact in FP64.  h 2^11 multiplies both state pieces, l the high
+      // one.
       const double xs = ldexp(x, -a_exp);
       const _Float16 h = (_Float16)(float)xs;
       const _Float16 l = (_Float16)(float)((xs - (double)h) * 2048.0);

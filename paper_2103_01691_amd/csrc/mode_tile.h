@@ -90,9 +90,9 @@ template <> struct Tr<KP_FP16X2> {
   typedef _Float16 pc;
   typedef f16x8 afrag;
   typedef f32x16 acc;
-  // operator pieces used (h 2^11, h, l), of which (h 2^11, l) are stored and
-  // h is formed in registers; state pieces (h, l)
-  static constexpr int MB = 32, NB = 32, KB = 16, KPL = 8, NPA = 3, NPS = 2, NPB = 2, NACC = 16;
+  // operator pieces (h 2^11, l) as stored; state pieces (h, r) with r the
+  // unscaled residual
+  static constexpr int MB = 32, NB = 32, KB = 16, KPL = 8, NPA = 2, NPS = 2, NPB = 2, NACC = 16;
 };
 template <> struct Tr<KP_BF16> {
   typedef float st;
@@ -129,9 +129,9 @@ template <> struct Prods<KP_BF16X3> {
   __device__ static constexpr int b(int k) { return k == 1 ? 1 : k == 3 ? 2 : k == 4 ? 1 : 0; }
 };
 template <> struct Prods<KP_FP16X2> {
-  // (h_A 2^11) h_B + h_A l_B + l_A h_B
+  // (h_A 2^11) h_B + (h_A 2^11) r_B + l_A h_B, every term at scale 2^11
   static constexpr int N = 3;
-  __device__ static constexpr int a(int k) { return k; }
+  __device__ static constexpr int a(int k) { return k == 2 ? 1 : 0; }
   __device__ static constexpr int b(int k) { return k == 1 ? 1 : 0; }
 };
 
@@ -152,14 +152,24 @@ __device__ __forceinline__ void split_bf16(float x, __bf16* p) {
   }
 }
 
-// Split x 2^-e into two RNE half-precision pieces h + 2^-11 l.  The residual
-// x 2^-e - h is exact in FP32 (h is the value rounded to 11 bits) and is
-// stored scaled by 2^11 so that it keeps the range of h.
-__device__ __forceinline__ void split_f16x2(float x, int e, _Float16* p) {
-  const float xs = ldexpf(x, -e);
-  const _Float16 h = (_Float16)xs;
-  p[0] = h;
-  p[1] = (_Float16)((xs - (float)h) * 2048.0f);
+// Split x 2^-e into two RNE half-precision pieces h + r.  The residual
+// x 2^-e - h is exact in FP32 (h is the value rounded to 11 bits).  The
+// state exponent puts max |x| 2^-e in [2^14, 2^15), so r is a normal half
+// (11 significant bits) wherever |x| is above 2^-17 of the maximum, and
+// below that its absolute error (at most 2^-25) is under 2^-39 of the
+// maximum; the operator's high piece is stored times 2^11, so the product
+// with r lands at the scale of the other two terms.
+// Two values at a time, so that both roundings use one packed conversion.
+__device__ __forceinline__ void split_f16x2(float x0, float x1, int e, _Float16* p0, _Float16* p1) {
+  typedef _Float16 h2v __attribute__((ext_vector_type(2)));
+  typedef float f2v __attribute__((ext_vector_type(2)));
+  const float a = ldexpf(x0, -e), b = ldexpf(x1, -e);
+  const h2v h = __builtin_convertvector(f2v{a, b}, h2v);
+  const h2v r = __builtin_convertvector(f2v{a - (float)h.x, b - (float)h.y}, h2v);
+  p0[0] = h.x;
+  p1[0] = h.y;
+  p0[1] = r.x;
+  p1[1] = r.y;
 }
 
 // Exponent e with max * 2^-e < 2^15 for the float whose bits are `bits`
@@ -434,9 +444,14 @@ __device__ __forceinline__ void mode_tile(const ModeArgs& a, int64_t tile_x, int
           const int nf = fl / NB, nn = fl % NB;
           pc pieces[8][NPB];
 #pragma unroll
-          for (int e = 0; e < 8; ++e) {
-            if constexpr (F16) split_f16x2((float)v[e * TF + fi], s_exp, pieces[e]);
-            else split_bf16<NPB>((float)v[e * TF + fi], pieces[e]);
+          for (int e = 0; e < 8; e += 2) {
+            const float x0 = (float)v[e * TF + fi], x1 = (float)v[(e + 1) * TF + fi];
+            if constexpr (F16) {
+              split_f16x2(x0, x1, s_exp, pieces[e], pieces[e + 1]);
+            } else {
+              split_bf16<NPB>(x0, pieces[e]);
+              split_bf16<NPB>(x1, pieces[e + 1]);
+            }
           }
 #pragma unroll
           for (int p = 0; p < NPB; ++p) {
@@ -486,30 +501,21 @@ __device__ __forceinline__ void mode_tile(const ModeArgs& a, int64_t tile_x, int
   const int64_t a_kstride = (int64_t)a.MFT * NPS * 64;
   auto load_a = [&](int kbg, afrag (&dst)[WMF][NPA]) {
     const afrag* src = Aw + kbg * a_kstride;
-    if constexpr (F16) {
-      // stored (h 2^11, l); h = (h 2^11) 2^-11 is exact in half precision
 #pragma unroll
-      for (int i = 0; i < WMF; ++i) dst[i][0] = src[(i * NPS + 0) * 64];
+    for (int p = 0; p < NPA; ++p)
 #pragma unroll
-      for (int i = 0; i < WMF; ++i) dst[i][2] = src[(i * NPS + 1) * 64];
-    } else {
-#pragma unroll
-      for (int p = 0; p < NPA; ++p)
-#pragma unroll
-        for (int i = 0; i < WMF; ++i) dst[i][p] = src[(i * NPS + p) * 64];
-    }
-  };
-  // FP16X2: form the middle piece right before its products
-  auto finish_a = [&](afrag (&dst)[WMF][NPA]) {
-    if constexpr (F16) {
-#pragma unroll
-      for (int i = 0; i < WMF; ++i) dst[i][1] = dst[i][0] * (_Float16)(1.0f / 2048.0f);
-    }
+      for (int i = 0; i < WMF; ++i) dst[i][p] = src[(i * NPS + p) * 64];
   };
 
   auto store_chunk = [&](int buf) {
 #pragma unroll
     for (int u = 0; u < TPT; ++u) store_tile(u, buf);
+  };
+  // tiles [u0, u1) of the staged chunk
+  auto store_part = [&](int buf, int u0, int u1) {
+#pragma unroll
+    for (int u = 0; u < TPT; ++u)
+      if (u >= u0 && u < u1) store_tile(u, buf);
   };
 
   // B fragments of one K-block (local index kk of the LDS chunk) for this wave.
@@ -573,9 +579,24 @@ __device__ __forceinline__ void mode_tile(const ModeArgs& a, int64_t tile_x, int
         load_a(min(kbg + 1, kb_last), a_buf[nxt]);
         if (kk == 0 && more) load_chunk(c + 1);
         if (kk + 1 < KCH) read_b(L, kk + 1, b_buf[nxt]);
-        finish_a(a_buf[cur]);
         if constexpr (KPL != 8) __builtin_amdgcn_sched_barrier(0);
         mfma_kblock(a_buf[cur], b_buf[cur]);
+        // split and LDS writes of the next chunk, free to interleave with the
+        // MFMAs of the last K-block, or (FP16X2) of the last two when there
+        // are four or more (the fetch has landed by then: the operator loads
+        // issued after it are waited for at the start of K-block KCH-2).  On
+        // the last chunk this rewrites the idle buffer with stale data nobody
+        // reads.  FP16X2 spreads the split evenly over the MFMAs (measured
+        // faster); the three-piece BF16 split is left to the scheduler
+        // (measured faster there).
+        constexpr bool ST2 = F16 && KCH >= 4 && TPT >= 2;
+        const bool st_here = (kk + 1 == KCH) || (ST2 && kk + 2 == KCH);
+        if constexpr (ST2) {
+          if (kk + 2 == KCH) store_part(buf ^ 1, 0, TPT / 2);
+          if (kk + 1 == KCH) store_part(buf ^ 1, TPT / 2, TPT);
+        } else {
+          if (kk + 1 == KCH) store_chunk(buf ^ 1);
+        }
         if constexpr (KPL == 8) {
           // split kernels (many MFMAs per K-block): issue the next K-block's
           // operator loads and LDS reads one at a time between this
@@ -590,16 +611,22 @@ __device__ __forceinline__ void mode_tile(const ModeArgs& a, int64_t tile_x, int
             __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
             __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
           }
-          if (kk + 1 < KCH) __builtin_amdgcn_sched_group_barrier(0x008, 64, 0);
+          if (!st_here) {
+            __builtin_amdgcn_sched_group_barrier(0x008, 64, 0);
+          } else if constexpr (F16) {
+            // staging K-blocks: a few VALU instructions of the split after
+            // each MFMA, so that the matrix unit never waits behind a long
+            // VALU run (a pipeline of its own, sync id 1)
+            constexpr int REST = PP::N * WMF * WNF - WMF * NPS - WNF * NPB;
+            constexpr int PER = (PRO ? 24 : 8) / (ST2 ? 2 : 1);
+#pragma unroll
+            for (int g = 0; g < REST; ++g) {
+              __builtin_amdgcn_sched_group_barrier(0x008, 1, 1);
+              __builtin_amdgcn_sched_group_barrier(0x002, PER, 1);
+            }
+          }
         }
-        if (kk + 1 < KCH) {
-          __builtin_amdgcn_sched_barrier(0);
-        } else {
-          // split and LDS writes of the next chunk, free to interleave with
-          // this K-block's MFMAs (on the last chunk this rewrites the idle
-          // buffer with stale data nobody reads)
-          store_chunk(buf ^ 1);
-        }
+        if (kk + 1 < KCH) __builtin_amdgcn_sched_barrier(0);
       }
       __syncthreads();
       read_b(lds + (buf ^ 1) * CHUNK, 0, b_buf[0]);
@@ -619,7 +646,6 @@ __device__ __forceinline__ void mode_tile(const ModeArgs& a, int64_t tile_x, int
         load_a(kbg, af);
         if (kk == KCH - 1 && more) load_chunk(c + 1);
         read_b(L, kk, bf);
-        finish_a(af);
         mfma_kblock(af, bf);
       }
       if (more) {
