@@ -364,6 +364,7 @@ def main():
         "paths": side,
         "speedup_vs_fp64": (side["fp64"]["ms_per_step"] / ms) if "fp64" in side else None,
         "parity_rel_l2_vs_oracle": parity,
+        "parity_steps": args.cpu_steps if parity is not None else None,
         "cpu_baseline": cpu,
         "other_workloads": workloads,
         "wall_s_timed": wall,
