@@ -50,7 +50,7 @@ typedef enum {
   MM_ERR_ALIGN = 4,       /* tensor data not 16-byte aligned                  */
   MM_ERR_NOMEM = 5,       /* device allocation failed                         */
   MM_ERR_HIP = 6,         /* a HIP runtime call failed (text in last_error)   */
-  MM_ERR_UNSUPPORTED = 7, /* valid request this build does not implement      */
+  MM_ERR_UNSUPPORTED = 7, /* valid request the library does not implement    */
   MM_ERR_NONFINITE = 8,   /* a monitor found NaN / Inf                        */
   MM_ERR_NODEVICE = 9     /* no usable gfx950 device                          */
 } mm_status;
@@ -294,8 +294,10 @@ mm_status mm_set_workspace(mm_ctx ctx, void* dev_ptr, size_t bytes);
 
 /* ------------------------------------------------------------ timing ---- */
 
-/* Start recording a pair of HIP events around every mode-product kernel
- * launch of this context (on the launch stream).  Clears earlier records. */
+/* Start recording a pair of HIP events for every mode-product kernel launch
+ * of this context (on the launch stream), stamped by the launch itself
+ * (hipExtLaunchKernelGGL start / stop events: the kernel's execution time,
+ * no marker packets between launches).  Clears earlier records. */
 mm_status mm_profile_begin(mm_ctx ctx);
 /* Stop recording, wait for the recorded events and return, per launch in
  * issue order, a kernel kind code (prec*1000 + complex*100 + load*10 +

@@ -1,5 +1,6 @@
 // Operator preparation, FP64 reductions and the host-side planning and
 // dispatch of the mu-mode product kernels (tables in kern_<prec>.hip).
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -363,11 +364,17 @@ bool plan_mode(const ModeArgs& a, int prec, int cplx, bool want_pro, bool want_e
   return plan->grid_x > 0 && pick_kernel_any(prec, cplx, load, pro, epi, cls) != nullptr;
 }
 
-hipError_t launch_mode(const ModePlan& p, const ModeArgs& a, hipStream_t s) {
+hipError_t launch_mode(const ModePlan& p, const ModeArgs& a, hipStream_t s, hipEvent_t start, hipEvent_t stop) {
   KernFn fn = pick_kernel_any(p.prec, p.cplx, p.load, p.pro, p.epi, p.cls, p.full);
   if (!fn) return hipErrorInvalidDeviceFunction;
   dim3 grid(p.grid_x, p.grid_y, 1);
-  hipLaunchKernelGGL(fn, grid, dim3(p.threads), 0, s, a);
+  if (start || stop) {
+    // events stamped by the kernel's own dispatch (no separate marker
+    // packets between launches): the kernel's execution time
+    hipExtLaunchKernelGGL(fn, grid, dim3(p.threads), 0, s, start, stop, 0, a);
+  } else {
+    hipLaunchKernelGGL(fn, grid, dim3(p.threads), 0, s, a);
+  }
   return hipGetLastError();
 }
 

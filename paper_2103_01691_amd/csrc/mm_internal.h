@@ -112,7 +112,9 @@ bool plan_mode(const ModeArgs& a, int prec, int cplx, bool want_pro, bool want_e
                bool fcontig_ok, bool kcontig_ok, ModePlan* plan, bool batch = false, int force_cls = -1);
 // Number of tile classes of a precision (classes 0 .. n-1).
 int num_classes(int prec);
-hipError_t launch_mode(const ModePlan& plan, const ModeArgs& a, hipStream_t s);
+// start / stop (optional): events recorded by the launch itself
+hipError_t launch_mode(const ModePlan& plan, const ModeArgs& a, hipStream_t s, hipEvent_t start = nullptr,
+                       hipEvent_t stop = nullptr);
 // Batched launch: `count` work items (device array) that all use `plan`'s
 // kernel (same precision, complexity, load path and tile class).
 hipError_t launch_mode_batch(const ModePlan& plan, const BatchItem* items, int count, hipStream_t s);

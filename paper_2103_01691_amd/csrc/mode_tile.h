@@ -185,13 +185,18 @@ __device__ __forceinline__ int fp16x2_state_exp(uint32_t bits) {
 // the FP64 value), then the Taylor series of sin (to x^9) and cos (to x^10)
 // on |r| <= pi/4, whose truncation errors (< 2e-9, < 2e-10) are below FP32
 // rounding.  Accurate to a few ulp for |x| up to ~1e5; needs no scratch.
+// The two series alone, for |x| <= pi/4.
+__device__ __forceinline__ void sincos_small_f32(float x, float* s, float* c) {
+  const float r2 = x * x;
+  *s = x * (1.0f + r2 * (-1.0f / 6 + r2 * (1.0f / 120 + r2 * (-1.0f / 5040 + r2 * (1.0f / 362880)))));
+  *c = 1.0f + r2 * (-0.5f + r2 * (1.0f / 24 + r2 * (-1.0f / 720 + r2 * (1.0f / 40320 + r2 * (-1.0f / 3628800)))));
+}
+
 template <bool VOTE = true>
 __device__ __forceinline__ void sincos_f32(float x, float* s, float* c) {
   if (VOTE && __all(fabsf(x) <= 0.78539816f)) {
     // every active lane already in [-pi/4, pi/4]: no reduction needed
-    const float r2 = x * x;
-    *s = x * (1.0f + r2 * (-1.0f / 6 + r2 * (1.0f / 120 + r2 * (-1.0f / 5040 + r2 * (1.0f / 362880)))));
-    *c = 1.0f + r2 * (-0.5f + r2 * (1.0f / 24 + r2 * (-1.0f / 720 + r2 * (1.0f / 40320 + r2 * (-1.0f / 3628800)))));
+    sincos_small_f32(x, s, c);
     return;
   }
   constexpr double PIO2 = 1.57079632679489661923;
@@ -214,13 +219,16 @@ __device__ __forceinline__ void sincos_f32(float x, float* s, float* c) {
 
 // exp(-i s |z|^2) z.  VOTE: take the reduction-free path when every active
 // lane allows it (a wave-uniform branch); without it the code is branch-free
-// and can be interleaved with MFMA work by the scheduler.
-template <typename T, bool VOTE = true>
+// and can be interleaved with MFMA work by the scheduler.  SMALL: the caller
+// guarantees |s| |z|^2 <= pi/4 (FP32 only), so no reduction is compiled.
+template <typename T, bool VOTE = true, bool SMALL = false>
 __device__ __forceinline__ void phase(T& re, T& im, T s) {
   T th = s * (re * re + im * im);
   T sn, cs;
   if constexpr (sizeof(T) == 8) {
     sincos(th, &sn, &cs);
+  } else if constexpr (SMALL) {
+    sincos_small_f32(th, &sn, &cs);
   } else {
     sincos_f32<VOTE>(th, &sn, &cs);
   }
@@ -281,9 +289,17 @@ __device__ __forceinline__ void mode_tile(const ModeArgs& a, int64_t tile_x, int
   // FP16X2: state scale from the running bound; the first workgroup clears
   // the slot the previous launch read (it is complete: same stream)
   int s_exp = 0;
+  // FP16X2 with a prologue phase: the running bound b of every component
+  // bounds the phase angle by |s_pre| 2 b^2; when that is within pi/4 (with
+  // a margin for rounding) the staging compiles its sincos without range
+  // reduction (the main loop exists in both forms, chosen once here).
+  bool ph_small = false;
   if constexpr (F16) {
-    s_exp = fp16x2_state_exp(*a.smax_in);
+    const uint32_t bbits = *a.smax_in;
+    s_exp = fp16x2_state_exp(bbits);
     if (tile_x == 0 && tile_y == 0 && tid == 0) *a.smax_clr = 0u;
+    const float bnd = __uint_as_float(bbits);
+    ph_small = fabsf((float)a.s_pre) * 2.0f * bnd * bnd <= 0.78f;
   }
 
   // ---------------------------------------------------------------- staging
@@ -416,7 +432,8 @@ __device__ __forceinline__ void mode_tile(const ModeArgs& a, int64_t tile_x, int
 
   // Write the staged registers of tile u into LDS buffer `buf`, split into
   // pieces.
-  auto store_tile = [&](int u, int buf) {
+  auto store_tile = [&](int u, int buf, auto small) {
+    constexpr bool SMALL = decltype(small)::value;
     pc* L = lds + buf * CHUNK;
     {
       if (TILES < THREADS && tid >= TILES) return;
@@ -432,7 +449,7 @@ __device__ __forceinline__ void mode_tile(const ModeArgs& a, int64_t tile_x, int
 #pragma unroll
         for (int fi = 0; fi < TF; ++fi)
 #pragma unroll
-          for (int kl = 0; kl < TK; kl += 2) phase<st, false>(v[kl * TF + fi], v[(kl + 1) * TF + fi], s_pre);
+          for (int kl = 0; kl < TK; kl += 2) phase<st, false, SMALL>(v[kl * TF + fi], v[(kl + 1) * TF + fi], s_pre);
       }
       if constexpr (KPL == 8) {
         // each fibre of the tile gets 8 consecutive K values = one lane slot
@@ -507,16 +524,19 @@ __device__ __forceinline__ void mode_tile(const ModeArgs& a, int64_t tile_x, int
       for (int i = 0; i < WMF; ++i) dst[i][p] = src[(i * NPS + p) * 64];
   };
 
-  auto store_chunk = [&](int buf) {
+  auto store_chunk = [&](int buf, auto small) {
 #pragma unroll
-    for (int u = 0; u < TPT; ++u) store_tile(u, buf);
+    for (int u = 0; u < TPT; ++u) store_tile(u, buf, small);
   };
   // tiles [u0, u1) of the staged chunk
-  auto store_part = [&](int buf, int u0, int u1) {
+  auto store_part = [&](int buf, int u0, int u1, auto small) {
 #pragma unroll
     for (int u = 0; u < TPT; ++u)
-      if (u >= u0 && u < u1) store_tile(u, buf);
+      if (u >= u0 && u < u1) store_tile(u, buf, small);
   };
+  typedef std::integral_constant<bool, false> ph_full_t;
+  typedef std::integral_constant<bool, true> ph_small_t;
+  constexpr bool PH2 = F16 && PRO && CPLX && OCC == 1;   // two forms of the main loop
 
   // B fragments of one K-block (local index kk of the LDS chunk) for this wave.
   // Piece-major order: the first products of a K-block need piece 0 of
@@ -549,7 +569,8 @@ __device__ __forceinline__ void mode_tile(const ModeArgs& a, int64_t tile_x, int
   };
 
   load_chunk(0);
-  store_chunk(0);
+  if (PH2 && ph_small) store_chunk(0, ph_small_t{});
+  else store_chunk(0, ph_full_t{});
   __syncthreads();
 
   // Software pipeline over K-blocks.  While the MFMAs of K-block kb run, the
@@ -562,7 +583,7 @@ __device__ __forceinline__ void mode_tile(const ModeArgs& a, int64_t tile_x, int
   // slower fetch), then split and written to the idle LDS buffer after the
   // chunk's MFMAs.
   static_assert(KCH % 2 == 0, "K-blocks per chunk must be even (register double buffer)");
-  if constexpr (OCC == 1) {
+  auto main_loop = [&](auto small) {
     afrag a_buf[2][WMF][NPA];
     afrag b_buf[2][WNF][NPB];
     load_a(0, a_buf[0]);
@@ -592,10 +613,10 @@ __device__ __forceinline__ void mode_tile(const ModeArgs& a, int64_t tile_x, int
         constexpr bool ST2 = F16 && KCH >= 4 && TPT >= 2;
         const bool st_here = (kk + 1 == KCH) || (ST2 && kk + 2 == KCH);
         if constexpr (ST2) {
-          if (kk + 2 == KCH) store_part(buf ^ 1, 0, TPT / 2);
-          if (kk + 1 == KCH) store_part(buf ^ 1, TPT / 2, TPT);
+          if (kk + 2 == KCH) store_part(buf ^ 1, 0, TPT / 2, small);
+          if (kk + 1 == KCH) store_part(buf ^ 1, TPT / 2, TPT, small);
         } else {
-          if (kk + 1 == KCH) store_chunk(buf ^ 1);
+          if (kk + 1 == KCH) store_chunk(buf ^ 1, small);
         }
         if constexpr (KPL == 8) {
           // split kernels (many MFMAs per K-block): issue the next K-block's
@@ -631,6 +652,14 @@ __device__ __forceinline__ void mode_tile(const ModeArgs& a, int64_t tile_x, int
       __syncthreads();
       read_b(lds + (buf ^ 1) * CHUNK, 0, b_buf[0]);
     }
+  };
+  if constexpr (OCC == 1) {
+    if constexpr (PH2) {
+      if (ph_small) main_loop(ph_small_t{});
+      else main_loop(ph_full_t{});
+    } else {
+      main_loop(ph_full_t{});
+    }
   } else {
     // Two workgroups share each CU (register budget of two waves per SIMD):
     // single register buffers, the other workgroup's MFMAs cover the waits.
@@ -649,7 +678,7 @@ __device__ __forceinline__ void mode_tile(const ModeArgs& a, int64_t tile_x, int
         mfma_kblock(af, bf);
       }
       if (more) {
-        store_chunk(buf ^ 1);
+        store_chunk(buf ^ 1, ph_full_t{});
         __syncthreads();
       }
     }

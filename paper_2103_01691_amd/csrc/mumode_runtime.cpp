@@ -263,9 +263,7 @@ mm_status run_mode(mm_ctx ctx, const void* in, void* out, const int64_t* dims, i
     hipEvent_t e0, e1;
     HIPCHK(ctx, hipEventCreate(&e0));
     HIPCHK(ctx, hipEventCreate(&e1));
-    HIPCHK(ctx, hipEventRecord(e0, s));
-    HIPCHK(ctx, mm::launch_mode(plan, a, s));
-    HIPCHK(ctx, hipEventRecord(e1, s));
+    HIPCHK(ctx, mm::launch_mode(plan, a, s, e0, e1));
     const int kind = plan.prec * 1000 + plan.cplx * 100 + plan.load * 10 + plan.pro * 2 + plan.epi;
     ctx->recs.push_back({kind, e0, e1});
     return MM_OK;
