@@ -298,8 +298,14 @@ def main():
             k = max(10, args.steps // 4)
             log(f"timing {prec}: {k} steps")
             pms, _, _, _ = time_path(ctx, mm, torch, E, psi0, prec, k, 5, False, args.tune_ms)
-            side[prec] = {"ms_per_step": pms, "steps_per_s": 1e3 / pms,
-                          "tflops_effective": FLOPS_PER_STEP / (pms * 1e-3) / 1e12}
+            eff = FLOPS_PER_STEP / (pms * 1e-3) / 1e12
+            # MFMA work the path executes per step (split schemes: every
+            # piece product) over the whole step time, against the dense
+            # peak of the MFMA type it uses
+            mult, peak = {"fp64": (1, PEAK["fp64"]), "fp32": (1, PEAK["fp32"])}.get(
+                prec, (SPLIT_PRODUCTS.get(prec, 1), PEAK["bf16"]))
+            side[prec] = {"ms_per_step": pms, "steps_per_s": 1e3 / pms, "tflops_effective": eff,
+                          "executed_mfma_frac_per_step": mult * eff * 1e12 / peak}
 
     workloads = None
     if not args.no_workloads:
@@ -351,6 +357,7 @@ def main():
         "config": {"workload": f"gpe3d_strang_n256_split_{split}", "d": D, "n": N, "beta": BETA, "tau": TAU,
                    "domain": [A, B], "state": "complex64", "precision": f"split_{split}_fp32acc"},
         "tflops_effective": FLOPS_PER_STEP / (ms * 1e-3) / 1e12,
+        "executed_mfma_frac_per_step": SPLIT_PRODUCTS[split] * FLOPS_PER_STEP / (ms * 1e-3) / PEAK["bf16"],
         "roofline": {
             "bound": "mfma", "achieved": achieved / 1e12 if achieved else None, "peak": PEAK["bf16"] / 1e12,
             "unit": "TFLOP/s", "frac": (achieved / PEAK["bf16"]) if achieved else None, "traffic": traffic,
