@@ -193,6 +193,23 @@ def other_workloads(ctx, mm, torch):
                                 "tflops_effective": 3 * 8.0 * m * m ** 3 / (t / K) / 1e12}
         Lh.destroy()
         del psi
+    # free Schroedinger, d = 3, n = 256 on [-10, 10]^3, tau = 0.01: exact in
+    # time, one expstep (three mode products) per step, 100 steps per call
+    x0 = synth.wavepacket_initial(256, -10.0, 10.0, 3)
+    Ef = mm.expm(mm.fd2_matrix(256, -10.0, 10.0), 0.5j * 0.01)
+    fs = {}
+    for prec in ("fp64", "fp32", "bf16x3", "fp16x2"):
+        npdt = np.complex128 if prec == "fp64" else np.complex64
+        psi = torch.from_numpy(synth.to_device_layout(x0.astype(npdt))).cuda()
+        Eop = ctx.mm_op_prepare(Ef, prec)
+        ctx.mumode_expstep(psi, [Eop] * 3, 2)
+        t = timed(torch, lambda k: ctx.mumode_expstep(psi, [Eop] * 3, k), 100)
+        fs[prec] = {"ms_per_step": 1e3 * t / 100, "steps_per_s": 100 / t,
+                    "tflops_effective": FLOPS_PER_STEP / (t / 100) / 1e12}
+        Eop.destroy()
+        del psi
+    out["free_schroedinger256_100steps"] = fs
+    torch.cuda.empty_cache()
     # time-dependent Schroedinger problem of Section 4.3 in nodal Hermite
     # space, exponential midpoint rule: the mode-3 exponential is formed on
     # the device every step ("exp (int)"), then the three mode products
