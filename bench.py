@@ -183,9 +183,10 @@ def other_workloads(ctx, mm, torch):
     # harmonic oscillator, Hermite n = 128, complex64, time-dependent potential
     m = 128
     Xl, _ = mm.hermite_nodes(m)
-    for prec in ("fp32", "fp16x2"):
+    for prec in ("fp32", "bf16x3", "fp16x2"):
         Lh = ctx.mm_op_prepare(mm.hermite_ho_exponential(m, 0.02), prec)
         psi = torch.randn((m, m, m), dtype=torch.complex64, device="cuda", generator=gen)
+        ctx.mm_autotune(psi, [Lh] * 3, 500)   # tiles for these shapes (kept in the context)
         ctx.ho_strang_step(psi, [Lh] * 3, [Xl] * 3, 0.0, 0.02, 0.1, 2)
         K = 50
         t = timed(torch, lambda k: ctx.ho_strang_step(psi, [Lh] * 3, [Xl] * 3, 0.0, 0.02, 0.1, k), K)
@@ -202,6 +203,7 @@ def other_workloads(ctx, mm, torch):
         npdt = np.complex128 if prec == "fp64" else np.complex64
         psi = torch.from_numpy(synth.to_device_layout(x0.astype(npdt))).cuda()
         Eop = ctx.mm_op_prepare(Ef, prec)
+        ctx.mm_autotune(psi, [Eop] * 3, 500)
         ctx.mumode_expstep(psi, [Eop] * 3, 2)
         t = timed(torch, lambda k: ctx.mumode_expstep(psi, [Eop] * 3, k), 100)
         fs[prec] = {"ms_per_step": 1e3 * t / 100, "steps_per_s": 100 / t,
