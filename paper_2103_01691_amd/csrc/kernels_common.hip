@@ -169,7 +169,8 @@ __global__ __launch_bounds__(NORM_THREADS) void maxabs_final_kernel(const uint32
     if (threadIdx.x < w) red[threadIdx.x] = max(red[threadIdx.x], red[threadIdx.x + w]);
     __syncthreads();
   }
-  if (threadIdx.x < 3) slots[threadIdx.x] = threadIdx.x == 0 ? red[0] : 0u;
+  // slot 0 gets the bound (word 0; its other words and slots 1, 2 cleared)
+  for (int i = threadIdx.x; i < 3 * SMAX_WORDS; i += NORM_THREADS) slots[i] = i == 0 ? red[0] : 0u;
 }
 
 // ------------------------------------------------------ device expm ------

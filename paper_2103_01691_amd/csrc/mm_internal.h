@@ -25,6 +25,10 @@ void op_blocks(int prec, int64_t Mr, int64_t Kr, int* KBT, int* MFT);
 
 // Arguments of one mu-mode product launch (real-GEMM view, see
 // mode_kernels.hip).  Complex tensors: P, Q, n, m count complex entries.
+// Words per running-bound slot: the workgroups of a launch spread their
+// atomic maxima over this many words, so they do not all queue on one.
+constexpr int SMAX_WORDS = 8;
+
 struct ModeArgs {
   const void* in;
   void* out;
@@ -35,10 +39,11 @@ struct ModeArgs {
   int KBT, MFT;        // padded K-blocks and M-fragments of the prepared operator
   double s_pre;        // prologue phase: psi *= exp(-i s_pre |psi|^2) (0: off)
   double s_post;       // epilogue phase, same form
-  // FP16X2 only: running bound of the state.  smax_in holds the float bits of
-  // max |component| of `in`; the launch raises smax_out to that of `out` and
-  // clears smax_clr (the slot the launch before it read).  The operator
-  // pieces represent L * 2^-a_exp.
+  // FP16X2 only: running bound of the state.  Each slot is SMAX_WORDS words;
+  // the maximum over smax_in's words is the float bits of max |component| of
+  // `in`; the launch raises smax_out (workgroup tile_x into word
+  // tile_x % SMAX_WORDS) to that of `out` and clears smax_clr (the slot the
+  // launch before it read).  The operator pieces represent L * 2^-a_exp.
   const uint32_t* smax_in;
   uint32_t* smax_out;
   uint32_t* smax_clr;

@@ -295,9 +295,11 @@ __device__ __forceinline__ void mode_tile(const ModeArgs& a, int64_t tile_x, int
   // reduction (the main loop exists in both forms, chosen once here).
   bool ph_small = false;
   if constexpr (F16) {
-    const uint32_t bbits = *a.smax_in;
+    uint32_t bbits = 0;
+#pragma unroll
+    for (int w = 0; w < SMAX_WORDS; ++w) bbits = max(bbits, a.smax_in[w]);
     s_exp = fp16x2_state_exp(bbits);
-    if (tile_x == 0 && tile_y == 0 && tid == 0) *a.smax_clr = 0u;
+    if (tile_x == 0 && tile_y == 0 && tid < SMAX_WORDS) a.smax_clr[tid] = 0u;
     const float bnd = __uint_as_float(bbits);
     ph_small = fabsf((float)a.s_pre) * 2.0f * bnd * bnd <= 0.78f;
   }
@@ -887,12 +889,26 @@ __device__ __forceinline__ void mode_tile(const ModeArgs& a, int64_t tile_x, int
     }
   }
   if constexpr (F16) {
-    // wave maximum, then one atomic per wave into the next launch's slot
-    // (non-negative floats order like their bit patterns)
+    // wave maximum, the waves' maxima meet in LDS, then one atomic per
+    // workgroup into one word of the next launch's slot (non-negative floats
+    // order like their bit patterns).  Atomics on one word serialise, and
+    // the workgroups of a round finish together: one per workgroup rather
+    // than one per wave, spread over SMAX_WORDS words, keeps that queue
+    // short (one atomic per wave on a single word cost ~10 % per launch).
+    // Every thread of the workgroup reaches this point.
     uint32_t mb = __float_as_uint(vmax);
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) mb = max(mb, (uint32_t)__shfl_xor((int)mb, o));
-    if (lane == 0) atomicMax(a.smax_out, mb);
+    __syncthreads();   // every wave is done with the LDS buffers
+    uint32_t* wmx = (uint32_t*)lds;
+    if (lane == 0) wmx[wave] = mb;
+    __syncthreads();
+    if (tid == 0) {
+      uint32_t m = 0;
+#pragma unroll
+      for (int w = 0; w < WM * WN; ++w) m = max(m, wmx[w]);
+      atomicMax(a.smax_out + (int)(tile_x % SMAX_WORDS), m);
+    }
   }
 }
 

@@ -50,9 +50,10 @@ struct mm_ctx_s {
   double* red_partial = nullptr;
   double* red_result = nullptr;
   double* host_result = nullptr; // pinned
-  // FP16X2 state bounds: slots [0, 3) rotate along a chain of products
-  // (launch k reads slot k % 3, raises (k + 1) % 3, clears (k + 2) % 3);
-  // words [4, 4 + norm_partials()) are partial maxima.  chain_end is the
+  // FP16X2 state bounds: three slots of SMAX_WORDS words rotate along a
+  // chain of products (launch k reads slot k % 3, raises (k + 1) % 3,
+  // clears (k + 2) % 3); words [3 SMAX_WORDS, + norm_partials()) are the
+  // max-abs pass's partial maxima.  chain_end is the
   // output of the chain's last launch: a product whose input is anything
   // else (or the first one of an API call) starts a new chain with a
   // max-abs pass over its input.
@@ -250,12 +251,12 @@ mm_status run_mode(mm_ctx ctx, const void* in, void* out, const int64_t* dims, i
     if (in != ctx->chain_end) {
       int64_t count = (cplx ? 2 : 1);
       for (int k = 0; k < d; ++k) count *= dims[k];
-      HIPCHK(ctx, mm::launch_maxabs((const float*)in, count, ctx->smax + 4, ctx->smax, s));
+      HIPCHK(ctx, mm::launch_maxabs((const float*)in, count, ctx->smax + 3 * mm::SMAX_WORDS, ctx->smax, s));
       ctx->sidx = 0;
     }
-    a.smax_in = ctx->smax + ctx->sidx;
-    a.smax_out = ctx->smax + (ctx->sidx + 1) % 3;
-    a.smax_clr = ctx->smax + (ctx->sidx + 2) % 3;
+    a.smax_in = ctx->smax + mm::SMAX_WORDS * ctx->sidx;
+    a.smax_out = ctx->smax + mm::SMAX_WORDS * ((ctx->sidx + 1) % 3);
+    a.smax_clr = ctx->smax + mm::SMAX_WORDS * ((ctx->sidx + 2) % 3);
     ctx->sidx = (ctx->sidx + 1) % 3;
     ctx->chain_end = out;
   }
@@ -562,7 +563,7 @@ mm_status mm_create(mm_ctx* out, int device) {
   c->device = device;
   if (hipMalloc((void**)&c->red_partial, sizeof(double) * mm::norm_partials()) != hipSuccess ||
       hipMalloc((void**)&c->red_result, sizeof(double) * 4) != hipSuccess ||
-      hipMalloc((void**)&c->smax, sizeof(uint32_t) * (4 + mm::norm_partials())) != hipSuccess ||
+      hipMalloc((void**)&c->smax, sizeof(uint32_t) * (3 * mm::SMAX_WORDS + mm::norm_partials())) != hipSuccess ||
       hipHostMalloc((void**)&c->host_result, sizeof(double) * 4, hipHostMallocDefault) != hipSuccess) {
     delete c;
     return fail(nullptr, MM_ERR_NOMEM, "context buffers");
