@@ -76,8 +76,11 @@ def counter_traffic(summary):
         return None
 
 
+_T0 = time.perf_counter()
+
+
 def log(msg):
-    print(msg, file=sys.stderr, flush=True)
+    print(f"[{time.perf_counter() - _T0:6.1f} s] {msg}", file=sys.stderr, flush=True)
 
 
 def build_operator(mm):
