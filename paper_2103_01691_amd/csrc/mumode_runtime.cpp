@@ -1021,6 +1021,13 @@ mm_status mumode_expstep_batched(mm_ctx ctx, int count, mm_tensor* const* T, con
         for (int tx = 0; tx < plan.grid_x; ++tx) byk[g].second.push_back(mm::BatchItem{a, tx, 0, kind});
       }
       for (size_t g = 0; g < byk.size(); ++g) {
+        // longest tiles first (work ~ K x M of the instance's product), so the
+        // launch does not end on a few large tiles started last; the items
+        // are independent, so the order changes no result
+        std::stable_sort(byk[g].second.begin(), byk[g].second.end(),
+                         [](const mm::BatchItem& x, const mm::BatchItem& y) {
+                           return (int64_t)x.a.Kr * x.a.Mr > (int64_t)y.a.Kr * y.a.Mr;
+                         });
         groups.push_back({plans[g], (int)items.size(), (int)byk[g].second.size()});
         items.insert(items.end(), byk[g].second.begin(), byk[g].second.end());
       }
