@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
 #include <atomic>
 #include <cmath>
 #include <cstdlib>
@@ -15,15 +16,15 @@ namespace {
 
 // -------------------------------------------------------- preparation -----
 
+// One fragment slot s = (kb, mf, lane) of the prepared operator.
 template <int PR>
-__global__ void prepare_kernel(const double* __restrict__ master, int64_t rows, int64_t cols,
-                               int64_t ld, int cplx, PhaseScale ph, void* __restrict__ outv, int KBT,
-                               int MFT, int a_exp) {
+__device__ __forceinline__ void prepare_slot(int64_t s, const double* __restrict__ master, int64_t rows,
+                                             int64_t cols, int64_t ld, int cplx, const PhaseScale& ph,
+                                             void* __restrict__ outv, int KBT, int MFT, int a_exp) {
   typedef Tr<PR> T;
   typedef typename T::pc pc;
   constexpr int MB = T::MB, KB = T::KB, KPL = T::KPL, NPC = T::NPS;
   const int64_t slots = (int64_t)KBT * MFT * 64;   // (kb, mf, lane)
-  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= slots) return;
   const int lane = (int)(s % 64);
   const int64_t t = s / 64;
@@ -86,6 +87,23 @@ __global__ void prepare_kernel(const double* __restrict__ master, int64_t rows, 
       }
     }
   }
+}
+
+template <int PR>
+__global__ void prepare_kernel(const double* __restrict__ master, int64_t rows, int64_t cols,
+                               int64_t ld, int cplx, PhaseScale ph, void* __restrict__ outv, int KBT,
+                               int MFT, int a_exp) {
+  prepare_slot<PR>((int64_t)blockIdx.x * blockDim.x + threadIdx.x, master, rows, cols, ld, cplx, ph, outv, KBT,
+                   MFT, a_exp);
+}
+
+// Several operators of one precision in one launch (blockIdx.y selects the
+// operator): the per-step operators of a time-dependent splitting step.
+template <int PR>
+__global__ void prepare_multi_kernel(PrepJobs jobs) {
+  const PrepJob& p = jobs.j[blockIdx.y];
+  prepare_slot<PR>((int64_t)blockIdx.x * blockDim.x + threadIdx.x, p.master, p.rows, p.cols, p.ld, p.cplx, p.ph,
+                   p.out, p.KBT, p.MFT, p.a_exp);
 }
 
 // ------------------------------------------------------------- norm2 ------
@@ -398,6 +416,22 @@ hipError_t launch_mode_batch_merged(int prec, const BatchItem* items, int count,
   }
   if (count <= 0) return hipSuccess;
   hipLaunchKernelGGL(fn, dim3(count), dim3(256), 0, s, items);
+  return hipGetLastError();
+}
+
+hipError_t launch_prepare_multi(int prec, const PrepJobs& jobs, hipStream_t s) {
+  if (jobs.n < 1 || jobs.n > MAX_PREP_JOBS) return hipErrorInvalidValue;
+  int64_t slots = 0;
+  for (int k = 0; k < jobs.n; ++k) slots = std::max(slots, (int64_t)jobs.j[k].KBT * jobs.j[k].MFT * 64);
+  const int threads = 256;
+  const dim3 grid((unsigned)((slots + threads - 1) / threads), (unsigned)jobs.n);
+  switch (prec) {
+    case KP_F64: hipLaunchKernelGGL(prepare_multi_kernel<KP_F64>, grid, dim3(threads), 0, s, jobs); break;
+    case KP_F32: hipLaunchKernelGGL(prepare_multi_kernel<KP_F32>, grid, dim3(threads), 0, s, jobs); break;
+    case KP_BF16X3: hipLaunchKernelGGL(prepare_multi_kernel<KP_BF16X3>, grid, dim3(threads), 0, s, jobs); break;
+    case KP_FP16X2: hipLaunchKernelGGL(prepare_multi_kernel<KP_FP16X2>, grid, dim3(threads), 0, s, jobs); break;
+    default: hipLaunchKernelGGL(prepare_multi_kernel<KP_BF16>, grid, dim3(threads), 0, s, jobs); break;
+  }
   return hipGetLastError();
 }
 

@@ -150,6 +150,23 @@ struct PhaseScale {
   double cc = 0.0;
 };
 
+// One operator preparation (the arguments of launch_prepare).
+struct PrepJob {
+  const double* master = nullptr;
+  int64_t rows = 0, cols = 0, ld = 0;
+  int cplx = 0;
+  PhaseScale ph;
+  void* out = nullptr;
+  int KBT = 0, MFT = 0, a_exp = 0;
+};
+constexpr int MAX_PREP_JOBS = 6;
+struct PrepJobs {
+  PrepJob j[MAX_PREP_JOBS];
+  int n = 0;
+};
+// Up to MAX_PREP_JOBS preparations of one precision in one launch.
+hipError_t launch_prepare_multi(int prec, const PrepJobs& jobs, hipStream_t s);
+
 // Convert an FP64 master (device, column-major, ld) into fragment order.
 // a_exp (FP16X2 only): the pieces represent master * 2^-a_exp.
 hipError_t launch_prepare(int prec, int cplx, const double* master, int64_t rows, int64_t cols,

@@ -892,14 +892,41 @@ mm_status ho_strang_step(mm_ctx ctx, mm_tensor* psi, const mm_op* Lh, const doub
     const double cb = 0.5 * eps * (std::cos(t) - std::cos(t + 0.5 * tau));
     const double ca = 0.5 * eps * (std::cos(t + 0.5 * tau) - std::cos(t + tau));
     void* cur = psi->data;
-    for (int k = 0; k < psi->d; ++k) {
+    auto phase_of = [&](int k) {
       mm::PhaseScale ph;
       ph.rx2 = ctx->x2 + (size_t)k * 4096;
       ph.rc = ca;
       ph.cx2 = ph.rx2;
       ph.cc = cb;
-      HIPCHK(ctx, mm::launch_prepare(kprec(Lh[k]->prec), 1, Lh[k]->dev_master, Lh[k]->rows, Lh[k]->cols,
-                                     Lh[k]->rows, ph, ctx->step_prep[k], Lh[k]->KBT, Lh[k]->MFT, s, Lh[k]->a_exp));
+      return ph;
+    };
+    // the step's operators: all modes in one launch when they share a
+    // precision (each buffer is read only by its own mode's product below)
+    bool one_prec = psi->d <= mm::MAX_PREP_JOBS;
+    for (int k = 1; k < psi->d; ++k) one_prec = one_prec && Lh[k]->prec == Lh[0]->prec;
+    if (one_prec) {
+      mm::PrepJobs jobs;
+      jobs.n = psi->d;
+      for (int k = 0; k < psi->d; ++k) {
+        mm::PrepJob& j = jobs.j[k];
+        j.master = Lh[k]->dev_master;
+        j.rows = Lh[k]->rows;
+        j.cols = Lh[k]->cols;
+        j.ld = Lh[k]->rows;
+        j.cplx = 1;
+        j.ph = phase_of(k);
+        j.out = ctx->step_prep[k];
+        j.KBT = Lh[k]->KBT;
+        j.MFT = Lh[k]->MFT;
+        j.a_exp = Lh[k]->a_exp;
+      }
+      HIPCHK(ctx, mm::launch_prepare_multi(kprec(Lh[0]->prec), jobs, s));
+    }
+    for (int k = 0; k < psi->d; ++k) {
+      if (!one_prec)
+        HIPCHK(ctx, mm::launch_prepare(kprec(Lh[k]->prec), 1, Lh[k]->dev_master, Lh[k]->rows, Lh[k]->cols,
+                                       Lh[k]->rows, phase_of(k), ctx->step_prep[k], Lh[k]->KBT, Lh[k]->MFT, s,
+                                       Lh[k]->a_exp));
       mm::ModePlan plan;
       st = run_mode(ctx, cur, cur, psi->dims, psi->d, psi->dtype, Lh[k], k + 1, 0, 0, s, &plan, true);
       if (st != MM_OK) return st;
