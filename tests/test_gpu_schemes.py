@@ -39,6 +39,27 @@ def test_ho_strang_matches_oracle(ctx, prec, nsteps):
     assert err < REL_TOL[prec] * nsteps
 
 
+@pytest.mark.parametrize("nsteps", [1, 3])
+def test_ho_strang_mixed_precision_operators(ctx, nsteps):
+    # one operator precision per mode: the step's operators are then prepared
+    # one launch per mode (the same-precision case prepares all in one), and
+    # the FP16x2 product starts its own running bound after the others
+    import paper_2103_01691_amd as mm
+    m, kmax, t0, tau, eps = 40, 8, 0.1, 0.02, 0.1
+    Phi, Psi, X = op.hermite_forward(m), op.hermite_backward(m), op.hermite_nodes(m)
+    c = synth.hermite_coefficients(m, kmax, 3, cfg_id=3)
+    psi0 = cast(om.tucker(c, [Psi] * 3), "fp32", True)
+    ref = sc.ho_strang(psi0, [Phi] * 3, [Psi] * 3, [X] * 3, t0, tau, eps, nsteps)
+    Xl, _ = mm.hermite_nodes(m)
+    H = mm.hermite_ho_exponential(m, tau)
+    Lh = [ctx.mm_op_prepare(H, p) for p in ("fp32", "bf16x3", "fp16x2")]
+    psi = to_gpu(psi0, "fp32", True)
+    ctx.ho_strang_step(psi, Lh, [Xl] * 3, t0, tau, eps, nsteps)
+    err = rel(from_gpu(psi), ref)
+    note(f"ho mixed precisions nsteps={nsteps} rel err {err:.3e}")
+    assert err < REL_TOL["fp32"] * nsteps
+
+
 def test_ho_eigenstate_phase_on_gpu(ctx):
     import paper_2103_01691_amd as mm
     m, tau = 32, 0.37
