@@ -901,10 +901,13 @@ mm_status ho_strang_step(mm_ctx ctx, mm_tensor* psi, const mm_op* Lh, const doub
       return ph;
     };
     // the step's operators: all modes in one launch when they share a
-    // precision (each buffer is read only by its own mode's product below)
+    // precision (each buffer is read only by its own mode's product below);
+    // without the time-dependent potential (eps = 0) they are the same every
+    // step and are prepared once
+    const bool prep = it == 0 || eps != 0.0;
     bool one_prec = psi->d <= mm::MAX_PREP_JOBS;
     for (int k = 1; k < psi->d; ++k) one_prec = one_prec && Lh[k]->prec == Lh[0]->prec;
-    if (one_prec) {
+    if (prep && one_prec) {
       mm::PrepJobs jobs;
       jobs.n = psi->d;
       for (int k = 0; k < psi->d; ++k) {
@@ -923,7 +926,7 @@ mm_status ho_strang_step(mm_ctx ctx, mm_tensor* psi, const mm_op* Lh, const doub
       HIPCHK(ctx, mm::launch_prepare_multi(kprec(Lh[0]->prec), jobs, s));
     }
     for (int k = 0; k < psi->d; ++k) {
-      if (!one_prec)
+      if (prep && !one_prec)
         HIPCHK(ctx, mm::launch_prepare(kprec(Lh[k]->prec), 1, Lh[k]->dev_master, Lh[k]->rows, Lh[k]->cols,
                                        Lh[k]->rows, phase_of(k), ctx->step_prep[k], Lh[k]->KBT, Lh[k]->MFT, s,
                                        Lh[k]->a_exp));
