@@ -84,9 +84,8 @@ def log(msg):
 
 
 def build_operator(mm):
-    x = np.linspace(A, B, N + 2)[1:-1]
-    H = -0.5 * mm.fd2_matrix(N, A, B) + np.diag(0.5 * x ** 2)
-    return mm.expm(H, -1j * TAU)
+    # exp(-i tau H), H = -1/2 D2 + 1/2 x^2 (library FP64 builder)
+    return mm.schrodinger_fd_exponential(N, A, B, 1.0, TAU)
 
 
 def time_path(ctx, mm, torch, E, psi0_np, prec, steps, warmup, profile, tune_ms=0, tune_file=None):
@@ -162,7 +161,7 @@ def other_workloads(ctx, mm, torch):
             key = (inst["kind"], n)
             if key not in cache:
                 if cplx:
-                    E = mm.expm(mm.fd2_matrix(n, -10.0, 10.0), 0.5j * 1e-3)
+                    E = mm.schrodinger_fd_exponential(n, -10.0, 10.0, 0.0, 1e-3)
                 else:
                     E = mm.expm(mm.fd2_matrix(n, 0.0, 1.0), 1e-3).real.copy()
                 cache[key] = ctx.mm_op_prepare(E, "fp32")
@@ -200,7 +199,7 @@ def other_workloads(ctx, mm, torch):
     # free Schroedinger, d = 3, n = 256 on [-10, 10]^3, tau = 0.01: exact in
     # time, one expstep (three mode products) per step, 100 steps per call
     x0 = synth.wavepacket_initial(256, -10.0, 10.0, 3)
-    Ef = mm.expm(mm.fd2_matrix(256, -10.0, 10.0), 0.5j * 0.01)
+    Ef = mm.schrodinger_fd_exponential(256, -10.0, 10.0, 0.0, 0.01)
     fs = {}
     for prec in ("fp64", "fp32", "bf16x3", "fp16x2"):
         npdt = np.complex128 if prec == "fp64" else np.complex64
@@ -219,9 +218,8 @@ def other_workloads(ctx, mm, torch):
     # space, exponential midpoint rule: the mode-3 exponential is formed on
     # the device every step ("exp (int)"), then the three mode products
     for m in (128, 256):
-        Phi, Psi = mm.hermite_matrices(m)
         X, _ = mm.hermite_nodes(m)
-        Bm = Psi @ np.diag(-1j * (np.arange(m) + 0.5)) @ Phi
+        Bm = mm.hermite_ho_generator(m)
         K = 20
         g = np.zeros((K, 3), dtype=np.complex128)
         g[:, 2] = -1j * np.sin((np.arange(K) + 0.5) * 0.02) ** 2

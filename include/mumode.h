@@ -334,6 +334,26 @@ mm_status mm_hermite_matrices(int m, double* Phi, double* Psi);
  * interleaved), Phi / Psi as in mm_hermite_matrices. */
 mm_status mm_hermite_ho_exponential(int m, double tau, double* out);
 
+/* 1-D Schroedinger Hamiltonian H = -1/2 D2 + (omega2 / 2) diag(x^2), D2 the
+ * Dirichlet second difference of mm_fd2_matrix on the n interior nodes
+ * x_j = a + j h of [a, b] (h = (b-a)/(n+1)): omega2 = 1 is the harmonic trap
+ * of the Gross-Pitaevskii set-up (Section 4.5, with the trap of the
+ * Section 4.3 oscillator), omega2 = 0 the free particle.  out: n*n doubles,
+ * column-major.  MM_ERR_SHAPE for n < 1 or b <= a. */
+mm_status mm_schrodinger_fd_hamiltonian(int n, double a, double b, double omega2, double* out);
+
+/* E = exp(-i tau H), H as in mm_schrodinger_fd_hamiltonian: the exact flow
+ * over tau of i psi_t = H psi, the mode exponential of the mu-mode integrator
+ * (Section 2) for the Schroedinger and Gross-Pitaevskii set-ups (Taylor
+ * scaling and squaring of mm_expm).  out: n*n complex (interleaved),
+ * column-major.  n <= 4096. */
+mm_status mm_schrodinger_fd_exponential(int n, double a, double b, double omega2, double tau, double* out);
+
+/* Generator (i/2)(d^2/dx^2 - x^2) of one mode of the Section 4.4 Hamiltonian in
+ * nodal Hermite space: Psi diag(-i (k + 1/2)) Phi (m x m complex, purely
+ * imaginary, column-major interleaved; Phi / Psi as in mm_hermite_matrices). */
+mm_status mm_hermite_ho_generator(int m, double* out);
+
 /* Centred second difference of even order `order` (2..16) on n periodic
  * nodes of [a, b) (h = (b-a)/n), the symmetric circulant of the classical
  * central weights (Section 4.1, Test 2 varies the order).  out: n*n doubles,

@@ -85,6 +85,32 @@ def hermite_ho_exponential(m: int, tau: float) -> np.ndarray:
     return np.asarray(out)
 
 
+def schrodinger_fd_hamiltonian(n: int, a: float, b: float, omega2: float = 1.0) -> np.ndarray:
+    """-1/2 D2 + (omega2/2) diag(x^2) on n interior Dirichlet nodes of [a, b]."""
+    out = np.zeros((n, n), dtype=np.float64, order="F")
+    _check(_lib.lib.mm_schrodinger_fd_hamiltonian(n, float(a), float(b), float(omega2),
+                                                  out.ctypes.data_as(C.POINTER(C.c_double))),
+           "mm_schrodinger_fd_hamiltonian")
+    return np.asarray(out)
+
+
+def schrodinger_fd_exponential(n: int, a: float, b: float, omega2: float, tau: float) -> np.ndarray:
+    """exp(-i tau H), H = schrodinger_fd_hamiltonian(n, a, b, omega2)."""
+    out = np.zeros((n, n), dtype=np.complex128, order="F")
+    _check(_lib.lib.mm_schrodinger_fd_exponential(n, float(a), float(b), float(omega2), float(tau),
+                                                  out.ctypes.data_as(C.POINTER(C.c_double))),
+           "mm_schrodinger_fd_exponential")
+    return np.asarray(out)
+
+
+def hermite_ho_generator(m: int) -> np.ndarray:
+    """(i/2)(d^2/dx^2 - x^2) in nodal Hermite space, Psi diag(-i (k + 1/2)) Phi."""
+    out = np.zeros((m, m), dtype=np.complex128, order="F")
+    _check(_lib.lib.mm_hermite_ho_generator(m, out.ctypes.data_as(C.POINTER(C.c_double))),
+           "mm_hermite_ho_generator")
+    return np.asarray(out)
+
+
 def fd2_periodic_order(n: int, a: float, b: float, order: int) -> np.ndarray:
     """Centred second difference of even `order` on n periodic nodes of [a, b)."""
     out = np.zeros((n, n), dtype=np.float64, order="F")

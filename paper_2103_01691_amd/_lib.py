@@ -29,6 +29,7 @@ EXPORTS = [
     "mm_autotune", "mm_tune_count", "mm_tune_get", "mm_tune_clear", "mm_tune_save", "mm_tune_load",
     "mm_set_workspace", "mumode_magnus_step", "mm_expm_device",
     "mm_fd2_periodic_order", "mm_fourier_d2", "mm_pipe_flow_operators", "mm_set_option", "mm_monitor_log",
+    "mm_schrodinger_fd_hamiltonian", "mm_schrodinger_fd_exponential", "mm_hermite_ho_generator",
 ]
 
 
@@ -92,6 +93,9 @@ def _load():
         "mm_set_option": (st, [P, C.c_int, C.c_int64]),
         "mm_monitor_log": (st, [P, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(d)]),
         "mm_pipe_flow_operators": (st, [C.c_int, C.c_int, d, d, d, d, C.POINTER(d), C.POINTER(d)]),
+        "mm_schrodinger_fd_hamiltonian": (st, [C.c_int, d, d, d, C.POINTER(d)]),
+        "mm_schrodinger_fd_exponential": (st, [C.c_int, d, d, d, d, C.POINTER(d)]),
+        "mm_hermite_ho_generator": (st, [C.c_int, C.POINTER(d)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)

@@ -199,6 +199,51 @@ mm_status mm_hermite_ho_exponential(int m, double tau, double* out) {
   return MM_OK;
 }
 
+mm_status mm_schrodinger_fd_hamiltonian(int n, double a, double b, double omega2, double* out) {
+  if (!out) return MM_ERR_ARG;
+  if (!std::isfinite(omega2)) return MM_ERR_ARG;
+  mm_status st = mm_fd2_matrix(n, a, b, 0, out);
+  if (st != MM_OK) return st;
+  // H = -1/2 D2 + (omega2 / 2) diag(x^2) on the interior nodes x_j = a + j h
+  const double h = (b - a) / (n + 1);
+  for (size_t e = 0; e < (size_t)n * n; ++e) out[e] *= -0.5;
+  for (int j = 0; j < n; ++j) {
+    const double x = a + (j + 1) * h;
+    out[j + (size_t)j * n] += 0.5 * omega2 * x * x;
+  }
+  return MM_OK;
+}
+
+mm_status mm_schrodinger_fd_exponential(int n, double a, double b, double omega2, double tau, double* out) {
+  if (!out) return MM_ERR_ARG;
+  if (!std::isfinite(tau)) return MM_ERR_ARG;
+  if (n < 1 || n > 4096) return MM_ERR_SHAPE;
+  std::vector<double> H((size_t)n * n), Hc(2 * (size_t)n * n, 0.0);
+  mm_status st = mm_schrodinger_fd_hamiltonian(n, a, b, omega2, H.data());
+  if (st != MM_OK) return st;
+  for (size_t e = 0; e < H.size(); ++e) Hc[2 * e] = H[e];
+  // i psi_t = H psi  =>  psi(tau) = exp(-i tau H) psi(0)
+  return mm_expm(n, Hc.data(), 0.0, -tau, out);
+}
+
+mm_status mm_hermite_ho_generator(int m, double* out) {
+  if (!out) return MM_ERR_ARG;
+  if (m < 1 || m > 4096) return MM_ERR_SHAPE;
+  std::vector<double> Phi((size_t)m * m), Psi((size_t)m * m);
+  mm_status st = mm_hermite_matrices(m, Phi.data(), Psi.data());
+  if (st != MM_OK) return st;
+  // (i/2)(d^2 - x^2) phi_k = -i (k + 1/2) phi_k (Section 3), so in nodal
+  // space the generator is Psi diag(-i (k + 1/2)) Phi (purely imaginary)
+  for (int j = 0; j < m; ++j)
+    for (int i = 0; i < m; ++i) {
+      double acc = 0.0;
+      for (int k = 0; k < m; ++k) acc += Psi[i + (size_t)k * m] * (k + 0.5) * Phi[k + (size_t)j * m];
+      out[2 * (i + (size_t)j * m)] = 0.0;
+      out[2 * (i + (size_t)j * m) + 1] = -acc;
+    }
+  return MM_OK;
+}
+
 mm_status mm_fd2_periodic_order(int n, double a, double b, int order, double* out) {
   if (!out) return MM_ERR_ARG;
   if (order < 2 || order > 16 || (order & 1)) return MM_ERR_ARG;

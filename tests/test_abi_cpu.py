@@ -158,3 +158,26 @@ def test_front_end_builders_validate():
         mm.fourier_d2(8, 1.0, 1.0)
     with pytest.raises(mm.MumodeError):
         mm.pipe_flow_operators(10, 10, 0.0, 5.0, 8.0)   # r_min must be > 0
+
+
+@pytest.mark.parametrize("n", [8, 96, 256])
+def test_library_schrodinger_builders_match_oracle(n):
+    # the library's Hamiltonian and exponentials against the oracle's, whose
+    # constants are pinned to the continuum physics (tests/test_oracle_physics.py)
+    import paper_2103_01691_amd as mm
+    H = mm.schrodinger_fd_hamiltonian(n, -8.0, 8.0, 1.0)
+    assert np.max(np.abs(H - op.ho_hamiltonian(n, -8.0, 8.0))) <= 1e-12 * np.max(np.abs(H))
+    E = mm.schrodinger_fd_exponential(n, -8.0, 8.0, 1.0, 0.1)
+    ref = op.ho_exponential(n, -8.0, 8.0, 0.1)
+    assert np.linalg.norm(E - ref) / np.linalg.norm(ref) < 1e-12
+    F = mm.schrodinger_fd_exponential(n, -10.0, 10.0, 0.0, 0.01)
+    ref = op.free_schrodinger_exponential(n, -10.0, 10.0, 0.01)
+    assert np.linalg.norm(F - ref) / np.linalg.norm(ref) < 1e-12
+
+
+def test_library_hermite_generator_matches_oracle():
+    import paper_2103_01691_amd as mm
+    for m in (4, 40):
+        G = mm.hermite_ho_generator(m)
+        ref = op.hermite_ho_generator(m)
+        assert np.max(np.abs(G - ref)) <= 1e-11 * np.max(np.abs(ref))

@@ -22,7 +22,7 @@ def ctx():
 def _lib_exponential(mm, kind, n, tau):
     if kind == "heat":
         return mm.expm(mm.fd2_matrix(n, 0.0, 1.0), tau).real.copy()
-    return mm.expm(mm.fd2_matrix(n, -10.0, 10.0), 0.5j * tau)
+    return mm.schrodinger_fd_exponential(n, -10.0, 10.0, 0.0, tau)
 
 
 def _oracle_exponential(kind, n, tau):

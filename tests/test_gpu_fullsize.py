@@ -29,9 +29,7 @@ def ctx():
 
 
 def _lib_ho_exp(mm, n, a, b, tau):
-    x = synth.dirichlet_nodes(n, a, b)
-    H = -0.5 * mm.fd2_matrix(n, a, b) + np.diag(0.5 * x ** 2)
-    return mm.expm(H, -1j * tau)
+    return mm.schrodinger_fd_exponential(n, a, b, 1.0, tau)
 
 
 @pytest.mark.parametrize("prec", ["bf16x3", "fp16x2"])
@@ -59,7 +57,7 @@ def test_free_schrodinger_256_one_step(ctx, prec):
     import paper_2103_01691_amd as mm
     n, a, b, tau = 256, -10.0, 10.0, 0.01
     psi0 = cast(synth.wavepacket_initial(n, a, b, 3, cfg_id=2), prec, True)
-    E = mm.expm(mm.fd2_matrix(n, a, b), 0.5j * tau)
+    E = mm.schrodinger_fd_exponential(n, a, b, 0.0, tau)
     Eop = ctx.mm_op_prepare(E, prec)
     psi = to_gpu(psi0, prec, True)
     ctx.mumode_expstep(psi, [Eop] * 3, 1)
@@ -117,7 +115,7 @@ def test_batch_512_sampled(ctx, prec):
             if kind == "heat":
                 E = mm.expm(mm.fd2_matrix(n, 0.0, 1.0), tau).real.copy()
             else:
-                E = mm.expm(mm.fd2_matrix(n, -10.0, 10.0), 0.5j * tau)
+                E = mm.schrodinger_fd_exponential(n, -10.0, 10.0, 0.0, tau)
             cache[key] = ctx.mm_op_prepare(E, prec)
         return cache[key]
 

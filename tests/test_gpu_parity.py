@@ -135,10 +135,8 @@ def test_gpe_strang_small(ctx, prec, tau, nsteps):
     psi0 = cast(synth.thomas_fermi_initial(n, a, b, 3, beta, cfg_id=4), prec, True)
     Eo = op.ho_exponential(n, a, b, tau)
     ref = sc.gpe_strang(psi0, [Eo] * 3, tau, beta, nsteps)
-    # the library forms its own operator (host FP64 expm of its own FD matrix)
-    x = synth.dirichlet_nodes(n, a, b)
-    H = -0.5 * mm.fd2_matrix(n, a, b) + np.diag(0.5 * x ** 2)
-    El = mm.expm(H, -1j * tau)
+    # the library forms its own operator (host FP64 expm of its own FD Hamiltonian)
+    El = mm.schrodinger_fd_exponential(n, a, b, 1.0, tau)
     Eop = ctx.mm_op_prepare(El, prec)
     psi = to_gpu(psi0, prec, True)
     ctx.gpe_strang_step(psi, [Eop] * 3, tau, beta, nsteps)

@@ -81,8 +81,7 @@ def test_energy_gpe_matches_oracle(ctx, prec):
     psi0 = cast(synth.thomas_fermi_initial(n, a, b, 3, beta, cfg_id=4), prec, True)
     Ho = op.ho_hamiltonian(n, a, b)
     ref = sc.energy_gpe(psi0, [Ho] * 3, beta, h ** 3)
-    x = synth.dirichlet_nodes(n, a, b)
-    Hl = -0.5 * mm.fd2_matrix(n, a, b) + np.diag(0.5 * x ** 2)
+    Hl = mm.schrodinger_fd_hamiltonian(n, a, b, 1.0)
     Hop = ctx.mm_op_prepare(Hl, prec)
     e = ctx.mm_energy_gpe(to_gpu(psi0, prec, True), [Hop] * 3, beta, h ** 3)
     note(f"energy prec={prec} gpu={e:.12g} oracle={ref:.12g}")

@@ -55,9 +55,7 @@ def trajectory():
 
 def _lib_op(ctx, prec):
     import paper_2103_01691_amd as mm
-    x = synth.dirichlet_nodes(N, A, B)
-    H = -0.5 * mm.fd2_matrix(N, A, B) + np.diag(0.5 * x ** 2)
-    return ctx.mm_op_prepare(mm.expm(H, -1j * TAU), prec)
+    return ctx.mm_op_prepare(mm.schrodinger_fd_exponential(N, A, B, 1.0, TAU), prec)
 
 
 def _run(ctx, trajectory, prec):
@@ -133,7 +131,7 @@ def test_free_schrodinger_100_steps(ctx, prec):
     psi0 = cast(synth.wavepacket_initial(n, a, b, 3, cfg_id=2), prec, True)
     Eo = op.free_schrodinger_exponential(n, a, b, tau)
     ref = om.expstep(psi0, [Eo] * 3, steps)
-    E = mm.expm(mm.fd2_matrix(n, a, b), 0.5j * tau)
+    E = mm.schrodinger_fd_exponential(n, a, b, 0.0, tau)
     psi = to_gpu(psi0, prec, True)
     ctx.mumode_expstep(psi, [ctx.mm_op_prepare(E, prec)] * 3, steps)
     err = rel(from_gpu(psi), ref)
