@@ -214,7 +214,7 @@ def other_workloads(ctx, mm, torch):
         del psi
     out["free_schroedinger256_100steps"] = fs
     torch.cuda.empty_cache()
-    # time-dependent Schroedinger problem of Section 4.3 in nodal Hermite
+    # time-dependent Schroedinger problem of Section 4.4 in nodal Hermite
     # space, exponential midpoint rule: the mode-3 exponential is formed on
     # the device every step ("exp (int)"), then the three mode products
     for m in (128, 256):

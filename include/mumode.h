@@ -190,7 +190,7 @@ mm_status mumode_expstep_batched(mm_ctx ctx, int count, mm_tensor* const* T, con
                                  mm_stream stream);
 
 /* Exponential midpoint rule (the second-order Magnus integrator of Section
- * 4.3, equation mag2) for u' = A(t) u with A(t) in Kronecker-sum form whose
+ * 4.4, equation mag2) for u' = A(t) u with A(t) in Kronecker-sum form whose
  * mode parts depend on time as A_mu(t) = B_mu + g_mu(t) diag(d_mu):
  * each step u <- exp(tau A(t_n + tau/2)) u is the mu-mode integrator with
  * E_mu = exp(tau A_mu(t_n + tau/2)) (the exponential of a Kronecker sum is

@@ -154,7 +154,7 @@ def hermite_ho_generator(m: int) -> np.ndarray:
 
 def hkmp_problem(m: int):
     """Mode generators of the time-dependent Schroedinger problem of Section
-    4.3 in nodal Hermite space: psi_t = (i/2)(Laplace - |x|^2 - 2 x_3 sin^2 t) psi,
+    4.4 in nodal Hermite space: psi_t = (i/2)(Laplace - |x|^2 - 2 x_3 sin^2 t) psi,
     i.e. A_mu = hermite_ho_generator for every mode plus, on mode 3,
     -i sin^2(t) diag(x_3).  Returns (B, d, g) for schemes.magnus_midpoint."""
     X = hermite_nodes(m)

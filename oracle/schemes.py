@@ -122,7 +122,7 @@ def magnus_generators(B, d, coef):
 
 def magnus_midpoint(psi: np.ndarray, B, d, g, tau: float, nsteps: int = 1, t0: float = 0.0) -> np.ndarray:
     """Exponential midpoint rule (second-order Magnus integrator, equation
-    mag2 of Section 4.3) for u' = A(t) u with A(t) in Kronecker-sum form,
+    mag2 of Section 4.4) for u' = A(t) u with A(t) in Kronecker-sum form,
     A(t) = sum_mu I x A_mu(t) x I, A_mu(t) = B_mu + g(mu, t) diag(d_mu):
     u_{n+1} = exp(tau A(t_n + tau/2)) u_n.  The exponential of a Kronecker
     sum is the Kronecker product of the mode exponentials (Section 2), so a

@@ -1,6 +1,6 @@
 """GPU parity of the device matrix exponential and of the exponential
 midpoint (second-order Magnus) integrator against the oracle, on the
-time-dependent Schroedinger problem of Section 4.3 in nodal Hermite space."""
+time-dependent Schroedinger problem of Section 4.4 in nodal Hermite space."""
 import numpy as np
 import pytest
 
