@@ -164,17 +164,30 @@ mm_status gpe_strang_step(mm_ctx ctx, mm_tensor* psi, const mm_op* E, double tau
 
 /* Strang step for the harmonic oscillator with a time-dependent potential,
  * i psi_t = -1/2 Laplace psi + 1/2 |x|^2 (1 + eps sin t) psi, in nodal
- * Hermite space (Section 3; the Hermite part is exact, Section 4.3).  One
- * step from t: P(t+tau/2, t+tau) L(tau) P(t, t+tau/2), where L(tau) =
- * x_1 Lh[0] ... x_d Lh[d-1] with Lh[k] = Psi diag(exp(-i tau (j+1/2))) Phi
- * (from mm_hermite_ho_exponential) and P(a,b) is the exact flow of the
- * remainder, exp(-i (eps/2) |x|^2 (cos a - cos b)).  P is separable over
- * the modes, so each step folds it into the operators as diagonal factors
- * (re-prepared on the device every step) and needs no pointwise pass.
- * nodes[k]: host array of the n_{k+1} Gauss-Hermite nodes of mode k+1.  psi
- * is complex, updated in place; the caller advances t0 by nsteps*tau. */
-mm_status ho_strang_step(mm_ctx ctx, mm_tensor* psi, const mm_op* Lh, const double* const* nodes,
-                         double t0, double tau, double eps, int nsteps, mm_stream stream);
+ * Hermite space (Section 3, equations real2spec / spec2real; the Hermite
+ * part is exact, Section 4.3).  One step from t: P(t+tau/2, t+tau) L(tau)
+ * P(t, t+tau/2), where L(tau) = x_1 Lh[0] ... x_d Lh[d-1] with the collapsed
+ * propagator Lh[k] = Psi_bwd[k] diag(exp(-i tau (j + 1/2))) Phi_fwd[k]
+ * (phi_j has oscillator energy j + 1/2), and P(a,b) is the exact flow of the
+ * remainder, exp(-i (eps/2) |x|^2 (cos a - cos b)).
+ *   Phi_fwd[k] : forward transform of mode k+1, K x n_{k+1} (K <= n_{k+1}
+ *                Hermite functions), Phi[j, l] = phi_j(X_l) w_l, prepared
+ *                from a real FP64 master (mm_hermite_matrices).
+ *   Psi_bwd[k] : backward transform, n_{k+1} x K, Psi[l, j] = phi_j(X_l),
+ *                same precision as Phi_fwd[k].
+ *   nodes[k]   : host array of the n_{k+1} quadrature nodes X_l of mode k+1.
+ * Lh[k] is formed on the device in FP64 from the operators' masters when the
+ * operators, tau or the precision differ from the previous call on this
+ * context (for MM_PREC_SPLIT_FP16X2 that formation reads the largest entry
+ * back and synchronises `stream` once); later calls with the same ones reuse
+ * it.  The node squares are uploaded only when the nodes change.  P is
+ * separable over the modes, so each step folds it into the operators as
+ * diagonal factors (re-prepared on the device every step when eps != 0) and
+ * needs no pointwise pass.  psi is complex, updated in place; the caller
+ * advances t0 by nsteps*tau.  Otherwise nothing synchronises. */
+mm_status ho_strang_step(mm_ctx ctx, mm_tensor* psi, const mm_op* Phi_fwd, const mm_op* Psi_bwd,
+                         const double* const* nodes, double t0, double tau, double eps, int nsteps,
+                         mm_stream stream);
 
 /* Batched integrator: count independent instances, each
  * T[i] <- T[i] x_1 E[i][0] ... x_{d_i} E[i][d_i - 1], nsteps times, in place.
@@ -225,12 +238,21 @@ mm_status mm_expm_device(mm_ctx ctx, int n, const double* A, double c_re, double
 
 /* Discrete GPE energy cell * [Re sum conj(psi) (sum_mu psi x_mu H[mu-1])
  * + (beta/2) sum |psi|^4], FP64 accumulation on the device; H[k] are the 1-D
- * Hamiltonians prepared in psi's precision.  Synchronises `stream`. */
+ * Hamiltonians prepared in psi's precision.  The Hamiltonian of the
+ * Gross-Pitaevskii problem of Section 4.5 is the Kronecker sum of the H[k]
+ * (Section 2), so its quadratic form is the sum over the modes of
+ * <psi, psi x_mu H[mu-1]>; the quartic term is the nonlinearity's energy.
+ * The Strang step of gpe_strang_step conserves this energy up to O(tau^2).
+ * Synchronises `stream`. */
 mm_status mm_energy_gpe(mm_ctx ctx, const mm_tensor* psi, const mm_op* H, double beta, double cell,
                         double* host_out, mm_stream stream);
 
-/* Discrete mass cell * sum |T|^2, accumulated in FP64 on the device;
- * synchronises `stream`.  Returns MM_ERR_NONFINITE if T holds NaN / Inf. */
+/* Discrete mass cell * sum |T|^2, accumulated in FP64 on the device: the
+ * squared L2 norm that the unitary Schroedinger and Gross-Pitaevskii flows
+ * conserve (Section 2 names the conserved mass among the invariants an
+ * integrator should keep; every mode exponential of a Hermitian generator is
+ * unitary, so each mu-mode step keeps it up to rounding).  Synchronises
+ * `stream`.  Returns MM_ERR_NONFINITE if T holds NaN / Inf. */
 mm_status mm_norm2(mm_ctx ctx, const mm_tensor* T, double cell, double* host_out, mm_stream stream);
 
 /* ---------------------------------------------------- tuning, memory ---- */

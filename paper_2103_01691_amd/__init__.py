@@ -273,12 +273,16 @@ class Context:
                   "mumode_expstep_batched")
         return tensors
 
-    def ho_strang_step(self, psi, Lh, nodes, t0: float, tau: float, eps: float, nsteps: int = 1, stream=None):
+    def ho_strang_step(self, psi, Phi_fwd, Psi_bwd, nodes, t0: float, tau: float, eps: float, nsteps: int = 1,
+                       stream=None):
+        """Phi_fwd / Psi_bwd: per-mode prepared real forward / backward Hermite
+        transforms (Op); nodes: per-mode arrays of the quadrature nodes."""
         t = as_mm_tensor(psi)
         keep = [np.ascontiguousarray(np.asarray(x, dtype=np.float64)) for x in nodes]
         arr = (C.POINTER(C.c_double) * len(keep))(*[k.ctypes.data_as(C.POINTER(C.c_double)) for k in keep])
-        self._chk(_lib.lib.ho_strang_step(self.handle, C.byref(t), _op_array(Lh), arr, float(t0), float(tau),
-                                          float(eps), nsteps, _stream(stream)), "ho_strang_step")
+        self._chk(_lib.lib.ho_strang_step(self.handle, C.byref(t), _op_array(Phi_fwd), _op_array(Psi_bwd), arr,
+                                          float(t0), float(tau), float(eps), nsteps, _stream(stream)),
+                  "ho_strang_step")
         return psi
 
     def mm_energy_gpe(self, psi, H, beta: float, cell: float, stream=None) -> float:

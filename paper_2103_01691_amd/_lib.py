@@ -69,7 +69,8 @@ def _load():
         "gpe_strang_step": (st, [P, C.POINTER(MMTensor), C.POINTER(P), d, d, C.c_int, P]),
         "mm_norm2": (st, [P, C.POINTER(MMTensor), d, C.POINTER(d), P]),
         "mm_profile_begin": (st, [P]),
-        "ho_strang_step": (st, [P, C.POINTER(MMTensor), C.POINTER(P), C.POINTER(C.POINTER(d)), d, d, d, C.c_int, P]),
+        "ho_strang_step": (st, [P, C.POINTER(MMTensor), C.POINTER(P), C.POINTER(P), C.POINTER(C.POINTER(d)), d, d, d,
+                                C.c_int, P]),
         "mumode_expstep_batched": (st, [P, C.c_int, C.POINTER(C.POINTER(MMTensor)), C.POINTER(C.POINTER(P)), C.c_int, P]),
         "mm_energy_gpe": (st, [P, C.POINTER(MMTensor), C.POINTER(P), d, d, C.POINTER(d), P]),
         "mm_hermite_ho_exponential": (st, [C.c_int, d, C.POINTER(d)]),

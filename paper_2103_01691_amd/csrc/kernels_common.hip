@@ -255,20 +255,30 @@ __global__ void expm_colsum_kernel(const double* __restrict__ A, int n, const do
   out[j] = s;
 }
 
-// ---------------------------------------------------------- host side -----
-
-std::atomic<int> g_split_cls{-2};   // -2: not read yet, -1: automatic
-
-int split_class() {
-  int v = g_split_cls.load();
-  if (v == -2) {
-    const char* e = std::getenv("MUMODE_SPLIT_TILE");
-    int x = e ? std::atoi(e) : 0;
-    v = (x >= 3 && x <= 6) ? x : (x == 1 ? 0 : -1);   // 1: class 0, 3..6: that class
-    g_split_cls.store(v);
+// Collapsed exact harmonic-oscillator propagator in nodal Hermite space:
+// out[i, l] = sum_k Psi[i, k] exp(-i tau (k + 1/2)) Phi[k, l] (complex FP64,
+// column-major interleaved, m x m); Phi is K x m, Psi m x K, real, ld = rows.
+// One thread per entry; the phase of coefficient k is that mode's exact
+// flow under the oscillator (phi_k has energy k + 1/2).
+__global__ void hermite_collapse_kernel(const double* __restrict__ Phi, const double* __restrict__ Psi, int m,
+                                        int K, double tau, double* __restrict__ out) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (int64_t)m * m) return;
+  const int i = (int)(e % m);
+  const int l = (int)(e / m);
+  double re = 0.0, im = 0.0;
+  for (int k = 0; k < K; ++k) {
+    double sn, cs;
+    sincos(tau * (k + 0.5), &sn, &cs);
+    const double v = Psi[i + (int64_t)k * m] * Phi[k + (int64_t)l * K];
+    re += v * cs;
+    im -= v * sn;
   }
-  return v;
+  out[2 * e] = re;
+  out[2 * e + 1] = im;
 }
+
+// ---------------------------------------------------------- host side -----
 
 KernFn pick_kernel_any(int prec, int cplx, int ld, int pro, int epi, int cls, int full = 0) {
   switch (prec) {
@@ -291,8 +301,6 @@ BatchFn pick_batch_any(int prec, int cplx, int ld, int cls) {
 }
 
 }  // namespace
-
-void set_split_class(int cls) { g_split_cls.store((cls == 0 || (cls >= 3 && cls <= 6)) ? cls : -1); }
 
 bool tile_shape(int prec, int cls, TileShape* out) {
   switch (prec) {
@@ -349,8 +357,6 @@ bool plan_mode(const ModeArgs& a, int prec, int cplx, bool want_pro, bool want_e
       (batch ? pick_batch_any(prec, cplx, load, force_cls) != nullptr
              : pick_kernel_any(prec, cplx, load, pro, epi, force_cls) != nullptr)) {
     cls = force_cls;
-  } else if (!batch && split && cplx && load != KL_GENERIC && split_class() >= 0) {
-    cls = split_class();
   } else if (!batch && split && cplx && load != KL_GENERIC && a.Mr > 2 * rw) {
     cls = 4;   // 4 x 128 rows, 128 fibres, 2 K-blocks per chunk: fastest for 256-long complex modes
   } else if (!pro && !epi && load != KL_GENERIC) {
@@ -501,6 +507,14 @@ int fp16x2_op_exp(double amax) {
   int e = 0;
   std::frexp(amax, &e);   // amax in [2^(e-1), 2^e)
   return e - 4;           // amax 2^-a_exp in [8, 16)
+}
+
+hipError_t launch_hermite_collapse(const double* Phi, const double* Psi, int m, int K, double tau, double* out,
+                                  hipStream_t s) {
+  const int64_t n = (int64_t)m * m;
+  hipLaunchKernelGGL(hermite_collapse_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, Phi, Psi, m, K, tau,
+                     out);
+  return hipGetLastError();
 }
 
 hipError_t launch_maxabs(const float* x, int64_t count, uint32_t* partial, uint32_t* slots, hipStream_t s) {

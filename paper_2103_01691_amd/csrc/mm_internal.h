@@ -136,10 +136,6 @@ struct SmallRun {
 };
 hipError_t launch_small_run(int prec, int cplx, const SmallRun& r, int* threads_out, hipStream_t s);
 
-// Force the tile class of split complex kernels (-1: automatic).  Also read
-// from MUMODE_SPLIT_TILE at first use.
-void set_split_class(int cls);
-
 // Optional diagonal phase scaling of a complex master before conversion:
 // L'[i,j] = exp(-i rc rx2[i]) L[i,j] exp(-i cc cx2[j]); rx2 / cx2 are device
 // arrays (null = no factor).
@@ -186,6 +182,10 @@ hipError_t launch_expm_colsum(const double* A, int n, const double* d, double gr
 // P = W + c[0] I + c[1] X + c[2] X2 + c[3] X3 (W nullable)
 hipError_t launch_expm_ps(double* P, const double* W, const double* X, const double* X2, const double* X3, int n,
                           const double* c, hipStream_t s);
+// out = Psi diag(exp(-i tau (k + 1/2))) Phi (Phi: K x m, Psi: m x K, real
+// FP64 device masters with ld = rows; out: m x m complex FP64 interleaved).
+hipError_t launch_hermite_collapse(const double* Phi, const double* Psi, int m, int K, double tau, double* out,
+                                   hipStream_t s);
 // FP16X2 chain start: slots[0] = float bits of max |x_k| over `count` floats,
 // slots[1] = slots[2] = 0.  partial: >= norm_partials() words.
 hipError_t launch_maxabs(const float* x, int64_t count, uint32_t* partial, uint32_t* slots, hipStream_t s);

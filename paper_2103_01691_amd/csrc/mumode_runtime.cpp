@@ -15,6 +15,7 @@
 #include "../../include/mumode.h"
 #include "mm_internal.h"
 
+
 struct mm_op_s {
   int64_t rows = 0, cols = 0;
   int cplx = 0;
@@ -69,7 +70,22 @@ struct mm_ctx_s {
   // per-mode scratch for operators re-prepared every step (ho_strang_step)
   void* step_prep[MM_MAXD] = {nullptr};
   size_t step_prep_bytes[MM_MAXD] = {0};
+  // ho_strang_step: per mode, the collapsed propagator Psi diag(exp(-i tau
+  // (k + 1/2))) Phi (FP64 complex master on the device) for the operators,
+  // tau and precision of the last call that formed it
+  struct HoMode {
+    mm_op phi = nullptr, psi = nullptr;
+    double tau = 0.0;
+    int prec = -1;
+    double* master = nullptr;
+    size_t master_bytes = 0;
+    mm_op_s op;
+  };
+  HoMode ho[MM_MAXD];
   double* x2 = nullptr;          // squared node coordinates, MM_MAXD * 4096 doubles
+  double* x2_stage = nullptr;    // pinned staging of x2
+  hipEvent_t x2_ev = nullptr;    // the last upload from x2_stage
+  std::vector<double> x2_nodes[MM_MAXD];   // nodes of the last upload, per mode
   // batched integrator: work items of the last batch signature, its
   // launch groups and the captured per-step graph
   struct BatchGroup { mm::ModePlan plan; int offset, count; };
@@ -244,6 +260,12 @@ mm_status run_mode(mm_ctx ctx, const void* in, void* out, const int64_t* dims, i
   if (!mm::plan_mode(a, kprec(L->prec), cplx ? 1 : 0, s_pre != 0.0, s_post != 0.0, fcontig, kcontig, &plan, batch,
                      force))
     return fail(ctx, MM_ERR_UNSUPPORTED, "no kernel plan for this shape");
+  // batched work items run in place, so each must own all rows of its
+  // fibres: a tuned class that splits the rows gives way to the built-in one
+  if (batch && !plan.covers_all_rows && force >= 0 &&
+      !mm::plan_mode(a, kprec(L->prec), cplx ? 1 : 0, s_pre != 0.0, s_post != 0.0, fcontig, kcontig, &plan, batch,
+                     -1))
+    return fail(ctx, MM_ERR_UNSUPPORTED, "no kernel plan for this shape");
   if (plan_out) *plan_out = plan;
   if (args_out) *args_out = a;
   if (dry) return MM_OK;
@@ -286,6 +308,19 @@ mm_status ensure_ws(mm_ctx ctx, size_t bytes) {
   if (hipMalloc(&ctx->ws, bytes) != hipSuccess) return fail(ctx, MM_ERR_NOMEM, "workspace of %zu bytes", bytes);
   ctx->ws_bytes = bytes;
   return MM_OK;
+}
+
+// Drop the captured batch graph and its signature: its work items hold
+// prepared-operator addresses and tile classes, so it must be rebuilt after
+// an operator is destroyed or the tile choice changes.
+void batch_invalidate(mm_ctx ctx) {
+  if (!ctx->bexec && !ctx->bgraph && ctx->bsig.empty()) return;
+  hipDeviceSynchronize();
+  if (ctx->bexec) hipGraphExecDestroy(ctx->bexec);
+  if (ctx->bgraph) hipGraphDestroy(ctx->bgraph);
+  ctx->bexec = nullptr;
+  ctx->bgraph = nullptr;
+  ctx->bsig.clear();
 }
 
 // Tucker sweep over the modes with per-mode ops (square), in place on T.
@@ -578,6 +613,9 @@ mm_status mm_op_destroy(mm_ctx ctx, mm_op op) {
   if (it == ctx->ops.end()) return fail(ctx, MM_ERR_ARG, "operator not owned by this context");
   ctx->ops.erase(it);
   hipSetDevice(ctx->device);
+  batch_invalidate(ctx);
+  for (int k = 0; k < MM_MAXD; ++k)
+    if (ctx->ho[k].phi == op || ctx->ho[k].psi == op) ctx->ho[k].phi = ctx->ho[k].psi = nullptr;
   hipDeviceSynchronize();
   if (op->dev_master) hipFree(op->dev_master);
   if (op->prep) hipFree(op->prep);
@@ -600,6 +638,10 @@ mm_status mm_destroy(mm_ctx ctx) {
   for (int k = 0; k < MM_MAXD; ++k)
     if (ctx->step_prep[k]) hipFree(ctx->step_prep[k]);
   if (ctx->x2) hipFree(ctx->x2);
+  if (ctx->x2_stage) hipHostFree(ctx->x2_stage);
+  if (ctx->x2_ev) hipEventDestroy(ctx->x2_ev);
+  for (int k = 0; k < MM_MAXD; ++k)
+    if (ctx->ho[k].master) hipFree(ctx->ho[k].master);
   if (ctx->bexec) hipGraphExecDestroy(ctx->bexec);
   if (ctx->bgraph) hipGraphDestroy(ctx->bgraph);
   if (ctx->bitems) hipFree(ctx->bitems);
@@ -842,37 +884,85 @@ mm_status gpe_strang_step(mm_ctx ctx, mm_tensor* psi, const mm_op* E, double tau
   return monitor_end(ctx, (hipStream_t)stream);
 }
 
-mm_status ho_strang_step(mm_ctx ctx, mm_tensor* psi, const mm_op* Lh, const double* const* nodes, double t0,
-                         double tau, double eps, int nsteps, mm_stream stream) {
+mm_status ho_strang_step(mm_ctx ctx, mm_tensor* psi, const mm_op* Phi_fwd, const mm_op* Psi_bwd,
+                         const double* const* nodes, double t0, double tau, double eps, int nsteps, mm_stream stream) {
   if (!ctx) return MM_ERR_ARG;
   mm_status st = check_tensor(ctx, psi, "psi");
   if (st != MM_OK) return st;
   if (!is_complex(psi->dtype)) return fail(ctx, MM_ERR_DTYPE, "psi must be complex");
-  if (!Lh || !nodes) return fail(ctx, MM_ERR_ARG, "Lh / nodes is NULL");
+  if (!Phi_fwd || !Psi_bwd || !nodes) return fail(ctx, MM_ERR_ARG, "Phi_fwd / Psi_bwd / nodes is NULL");
   if (nsteps < 0) return fail(ctx, MM_ERR_ARG, "nsteps < 0");
   if (!std::isfinite(t0) || !std::isfinite(tau) || !std::isfinite(eps)) return fail(ctx, MM_ERR_ARG, "t0 / tau / eps not finite");
   for (int k = 0; k < psi->d; ++k) {
-    if (!Lh[k] || !nodes[k]) return fail(ctx, MM_ERR_ARG, "Lh[%d] / nodes[%d] is NULL", k, k);
-    if (!Lh[k]->cplx) return fail(ctx, MM_ERR_DTYPE, "Lh[%d] must be complex", k);
-    if (Lh[k]->rows != Lh[k]->cols || Lh[k]->cols != psi->dims[k])
-      return fail(ctx, MM_ERR_SHAPE, "Lh[%d] must be %lld x %lld", k, (long long)psi->dims[k], (long long)psi->dims[k]);
-    st = check_op_dtype(ctx, Lh[k], psi->dtype);
+    const mm_op F = Phi_fwd[k], B = Psi_bwd[k];
+    if (!F || !B || !nodes[k]) return fail(ctx, MM_ERR_ARG, "Phi_fwd[%d] / Psi_bwd[%d] / nodes[%d] is NULL", k, k, k);
+    if (F->cplx || B->cplx) return fail(ctx, MM_ERR_DTYPE, "Phi_fwd[%d] / Psi_bwd[%d] must be real", k, k);
+    if (F->prec != B->prec) return fail(ctx, MM_ERR_DTYPE, "Phi_fwd[%d] and Psi_bwd[%d] differ in precision", k, k);
+    if (F->cols != psi->dims[k] || B->rows != psi->dims[k] || F->rows != B->cols || F->rows > F->cols)
+      return fail(ctx, MM_ERR_SHAPE, "mode %d: Phi_fwd must be K x %lld and Psi_bwd %lld x K, K <= %lld", k + 1,
+                  (long long)psi->dims[k], (long long)psi->dims[k], (long long)psi->dims[k]);
+    st = check_op_dtype(ctx, F, psi->dtype);
     if (st != MM_OK) return st;
+    for (int64_t i = 0; i < psi->dims[k]; ++i)
+      if (!std::isfinite(nodes[k][i])) return fail(ctx, MM_ERR_ARG, "nodes[%d] holds NaN / Inf", k);
   }
   HIPCHK(ctx, hipSetDevice(ctx->device));
   ctx->chain_end = nullptr;
   hipStream_t s = (hipStream_t)stream;
+  bool one_prec = psi->d <= mm::MAX_PREP_JOBS;
+  for (int k = 1; k < psi->d; ++k) one_prec = one_prec && Phi_fwd[k]->prec == Phi_fwd[0]->prec;
+  // the collapsed propagators of this tau, formed on the device once per
+  // (operators, tau, precision)
+  for (int k = 0; k < psi->d; ++k) {
+    mm_ctx_s::HoMode& H = ctx->ho[k];
+    const mm_op F = Phi_fwd[k], B = Psi_bwd[k];
+    if (H.phi == F && H.psi == B && H.tau == tau && H.prec == (int)F->prec) continue;
+    const int n = (int)psi->dims[k];
+    st = grow(ctx, (void**)&H.master, &H.master_bytes, sizeof(double) * 2 * (size_t)n * n);
+    if (st != MM_OK) return st;
+    HIPCHK(ctx, mm::launch_hermite_collapse(F->dev_master, B->dev_master, n, (int)F->rows, tau, H.master, s));
+    H.op = scratch_op(n, F->prec, 0);
+    H.op.dev_master = H.master;
+    if (F->prec == MM_PREC_SPLIT_FP16X2) {
+      // operator scale from the largest entry (one read-back per formation)
+      std::vector<double> h((size_t)2 * n * n);
+      HIPCHK(ctx, hipMemcpyAsync(h.data(), H.master, h.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+      HIPCHK(ctx, hipStreamSynchronize(s));
+      double amax = 0.0;
+      for (double v : h) amax = std::max(amax, std::fabs(v));
+      H.op.a_exp = mm::fp16x2_op_exp(amax);
+    }
+    H.phi = F;
+    H.psi = B;
+    H.tau = tau;
+    H.prec = (int)F->prec;
+  }
+  // squared node coordinates, uploaded when the nodes change (from pinned
+  // staging, once the previous upload from it has completed)
   if (!ctx->x2) {
     if (hipMalloc((void**)&ctx->x2, sizeof(double) * MM_MAXD * 4096) != hipSuccess)
       return fail(ctx, MM_ERR_NOMEM, "node buffer");
+    if (hipHostMalloc((void**)&ctx->x2_stage, sizeof(double) * MM_MAXD * 4096, hipHostMallocDefault) != hipSuccess)
+      return fail(ctx, MM_ERR_NOMEM, "node staging");
+    HIPCHK(ctx, hipEventCreateWithFlags(&ctx->x2_ev, hipEventDisableTiming));
   }
-  std::vector<double> hx2((size_t)MM_MAXD * 4096, 0.0);
-  for (int k = 0; k < psi->d; ++k)
-    for (int64_t i = 0; i < psi->dims[k]; ++i) hx2[(size_t)k * 4096 + i] = nodes[k][i] * nodes[k][i];
-  HIPCHK(ctx, hipMemcpyAsync(ctx->x2, hx2.data(), sizeof(double) * psi->d * 4096, hipMemcpyHostToDevice, s));
-  HIPCHK(ctx, hipStreamSynchronize(s));
+  bool changed = false;
+  for (int k = 0; k < psi->d && !changed; ++k)
+    changed = ctx->x2_nodes[k].size() != (size_t)psi->dims[k] ||
+              std::memcmp(ctx->x2_nodes[k].data(), nodes[k], sizeof(double) * psi->dims[k]) != 0;
+  if (changed) {
+    HIPCHK(ctx, hipEventSynchronize(ctx->x2_ev));
+    for (int k = 0; k < MM_MAXD; ++k) ctx->x2_nodes[k].clear();
+    for (int k = 0; k < psi->d; ++k) {
+      ctx->x2_nodes[k].assign(nodes[k], nodes[k] + psi->dims[k]);
+      for (int64_t i = 0; i < psi->dims[k]; ++i) ctx->x2_stage[(size_t)k * 4096 + i] = nodes[k][i] * nodes[k][i];
+    }
+    HIPCHK(ctx, hipMemcpyAsync(ctx->x2, ctx->x2_stage, sizeof(double) * psi->d * 4096, hipMemcpyHostToDevice, s));
+    HIPCHK(ctx, hipEventRecord(ctx->x2_ev, s));
+  }
   for (int k = 0; k < psi->d; ++k) {
-    const size_t need = mm::prepared_bytes(kprec(Lh[k]->prec), Lh[k]->KBT, Lh[k]->MFT);
+    const mm_op_s& L = ctx->ho[k].op;
+    const size_t need = mm::prepared_bytes(kprec(L.prec), L.KBT, L.MFT);
     if (ctx->step_prep_bytes[k] < need) {
       if (ctx->step_prep[k]) {
         HIPCHK(ctx, hipDeviceSynchronize());
@@ -900,38 +990,37 @@ mm_status ho_strang_step(mm_ctx ctx, mm_tensor* psi, const mm_op* Lh, const doub
       ph.cc = cb;
       return ph;
     };
-    // the step's operators: all modes in one launch when they share a
+    // the step's operators, all modes in one launch when they share a
     // precision (each buffer is read only by its own mode's product below);
     // without the time-dependent potential (eps = 0) they are the same every
     // step and are prepared once
     const bool prep = it == 0 || eps != 0.0;
-    bool one_prec = psi->d <= mm::MAX_PREP_JOBS;
-    for (int k = 1; k < psi->d; ++k) one_prec = one_prec && Lh[k]->prec == Lh[0]->prec;
     if (prep && one_prec) {
       mm::PrepJobs jobs;
       jobs.n = psi->d;
       for (int k = 0; k < psi->d; ++k) {
+        const mm_op_s& L = ctx->ho[k].op;
         mm::PrepJob& j = jobs.j[k];
-        j.master = Lh[k]->dev_master;
-        j.rows = Lh[k]->rows;
-        j.cols = Lh[k]->cols;
-        j.ld = Lh[k]->rows;
+        j.master = L.dev_master;
+        j.rows = L.rows;
+        j.cols = L.cols;
+        j.ld = L.rows;
         j.cplx = 1;
         j.ph = phase_of(k);
         j.out = ctx->step_prep[k];
-        j.KBT = Lh[k]->KBT;
-        j.MFT = Lh[k]->MFT;
-        j.a_exp = Lh[k]->a_exp;
+        j.KBT = L.KBT;
+        j.MFT = L.MFT;
+        j.a_exp = L.a_exp;
       }
-      HIPCHK(ctx, mm::launch_prepare_multi(kprec(Lh[0]->prec), jobs, s));
+      HIPCHK(ctx, mm::launch_prepare_multi(kprec(Phi_fwd[0]->prec), jobs, s));
     }
     for (int k = 0; k < psi->d; ++k) {
+      mm_op_s* L = &ctx->ho[k].op;
       if (prep && !one_prec)
-        HIPCHK(ctx, mm::launch_prepare(kprec(Lh[k]->prec), 1, Lh[k]->dev_master, Lh[k]->rows, Lh[k]->cols,
-                                       Lh[k]->rows, phase_of(k), ctx->step_prep[k], Lh[k]->KBT, Lh[k]->MFT, s,
-                                       Lh[k]->a_exp));
+        HIPCHK(ctx, mm::launch_prepare(kprec(L->prec), 1, L->dev_master, L->rows, L->cols, L->rows, phase_of(k), ctx->step_prep[k],
+                                       L->KBT, L->MFT, s, L->a_exp));
       mm::ModePlan plan;
-      st = run_mode(ctx, cur, cur, psi->dims, psi->d, psi->dtype, Lh[k], k + 1, 0, 0, s, &plan, true);
+      st = run_mode(ctx, cur, cur, psi->dims, psi->d, psi->dtype, L, k + 1, 0, 0, s, &plan, true);
       if (st != MM_OK) return st;
       void* dst = cur;
       if (!plan.covers_all_rows) {
@@ -939,7 +1028,7 @@ mm_status ho_strang_step(mm_ctx ctx, mm_tensor* psi, const mm_op* Lh, const doub
         if (st != MM_OK) return st;
         dst = (cur == psi->data) ? ctx->ws : psi->data;
       }
-      st = run_mode(ctx, cur, dst, psi->dims, psi->d, psi->dtype, Lh[k], k + 1, 0, 0, s, nullptr, false,
+      st = run_mode(ctx, cur, dst, psi->dims, psi->d, psi->dtype, L, k + 1, 0, 0, s, nullptr, false,
                     ctx->step_prep[k]);
       if (st != MM_OK) return st;
       cur = dst;
@@ -989,8 +1078,11 @@ mm_status mumode_expstep_batched(mm_ctx ctx, int count, mm_tensor* const* T, con
     sig.push_back((uint64_t)(uintptr_t)T[i]->data);
     sig.push_back((uint64_t)T[i]->d * 16 + (uint64_t)T[i]->dtype);
     for (int k = 0; k < T[i]->d; ++k) {
+      const mm_op L = E[i][k];
       sig.push_back((uint64_t)T[i]->dims[k]);
-      sig.push_back((uint64_t)(uintptr_t)E[i][k]);
+      sig.push_back((uint64_t)(uintptr_t)L);
+      sig.push_back(L ? (uint64_t)L->prec : ~(uint64_t)0);
+      sig.push_back(L ? (uint64_t)(uintptr_t)L->prep : 0);
     }
   }
   if (sig != ctx->bsig || !ctx->bexec) {
@@ -1312,6 +1404,7 @@ mm_status mm_autotune(mm_ctx ctx, const mm_tensor* T, const mm_op* E, int budget
     }
     ctx->tune[key] = {best, best_ms * 1e3};
   }
+  batch_invalidate(ctx);
   ctx->chain_end = nullptr;
   return MM_OK;
 }
@@ -1335,6 +1428,7 @@ mm_status mm_tune_get(mm_ctx ctx, int index, int64_t* key6, int* cls, double* us
 
 mm_status mm_tune_clear(mm_ctx ctx) {
   if (!ctx) return MM_ERR_ARG;
+  batch_invalidate(ctx);
   ctx->tune.clear();
   return MM_OK;
 }
@@ -1378,6 +1472,7 @@ mm_status mm_tune_load(mm_ctx ctx, const char* path) {
   const bool eof = n == EOF;
   std::fclose(f);
   if (!eof) return fail(ctx, MM_ERR_ARG, "%s: malformed line", path);
+  batch_invalidate(ctx);
   for (const auto& e : t) ctx->tune[e.first] = e.second;
   return MM_OK;
 }
@@ -1435,6 +1530,9 @@ mm_status mumode_magnus_step(mm_ctx ctx, mm_tensor* T, const mm_matrix* B, const
     double* E = nullptr;
     void* P = nullptr;
     double bnorm = 0.0, dmax = 0.0;
+    // Gershgorin discs of the Hermitian part (B + B^H)/2: centres Re b_ii,
+    // radii sum_{j != i} |b_ij + conj(b_ji)| / 2
+    std::vector<double> hc, hr;
     mm_op_s op;
   };
   std::vector<Mode> modes(d);
@@ -1472,6 +1570,17 @@ mm_status mumode_magnus_step(mm_ctx ctx, mm_tensor* T, const mm_matrix* B, const
         colsum[j] += std::hypot(re, im);
       }
     for (double v : colsum) M.bnorm = std::max(M.bnorm, v);
+    M.hc.assign(n, 0.0);
+    M.hr.assign(n, 0.0);
+    for (int i = 0; i < n; ++i) {
+      M.hc[i] = host[2 * ((size_t)i * n + i)];
+      for (int j = 0; j < n; ++j) {
+        if (j == i) continue;
+        const double re = host[2 * ((size_t)j * n + i)] + host[2 * ((size_t)i * n + j)];
+        const double im = host[2 * ((size_t)j * n + i) + 1] - host[2 * ((size_t)i * n + j) + 1];
+        M.hr[i] += 0.5 * std::hypot(re, im);
+      }
+    }
     if (hipMalloc((void**)&M.Bd, host.size() * sizeof(double)) != hipSuccess ||
         hipMalloc((void**)&M.E, host.size() * sizeof(double)) != hipSuccess)
       return fail(ctx, MM_ERR_NOMEM, "mode buffers");
@@ -1505,8 +1614,23 @@ mm_status mumode_magnus_step(mm_ctx ctx, mm_tensor* T, const mm_matrix* B, const
         const double bound = M.bnorm + std::hypot(gr, gi) * M.dmax;
         st = expm_device(ctx, M.n, M.Bd, M.dd, gr, gi, tau, 0.0, bound, M.E, s);
         if (st != MM_OK) return st;
-        // FP16X2: |E_ij| <= ||E||_1 <= exp(|tau| bound)
-        M.op.a_exp = prec == MM_PREC_SPLIT_FP16X2 ? mm::fp16x2_op_exp(std::exp(std::min(700.0, std::fabs(tau) * bound))) : 0;
+        // FP16X2 operator scale from a bound of max |E_ij|: |E_ij| <= ||E||_2
+        // <= exp(tau mu(A)) with mu the logarithmic 2-norm, the largest
+        // eigenvalue of the Hermitian part of A = B + g diag(d) (that part is
+        // (B + B^H)/2 + Re(g) diag(d)), bounded by its Gershgorin discs; for
+        // tau < 0 the same with -A.  For a skew-Hermitian (unitary-flow)
+        // generator the bound is 1, the true size of the entries.
+        if (prec == MM_PREC_SPLIT_FP16X2) {
+          double mu = -HUGE_VAL;
+          const double sg = tau >= 0.0 ? 1.0 : -1.0;
+          for (int i = 0; i < M.n; ++i) {
+            const double c = M.hc[i] + (M.dd ? gr * dg[k][i] : 0.0);
+            mu = std::max(mu, sg * c + M.hr[i]);
+          }
+          M.op.a_exp = mm::fp16x2_op_exp(std::exp(std::min(700.0, std::fabs(tau) * mu)));
+        } else {
+          M.op.a_exp = 0;
+        }
         HIPCHK(ctx, mm::launch_prepare(kp, 1, M.E, M.n, M.n, M.n, mm::PhaseScale(), M.P, M.op.KBT, M.op.MFT, s,
                                        M.op.a_exp));
       }

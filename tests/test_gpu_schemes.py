@@ -31,9 +31,10 @@ def test_ho_strang_matches_oracle(ctx, prec, nsteps):
     psi0 = cast(om.tucker(c, [Psi] * 3), prec, True)
     ref = sc.ho_strang(psi0, [Phi] * 3, [Psi] * 3, [X] * 3, t0, tau, eps, nsteps)
     Xl, _ = mm.hermite_nodes(m)
-    Lh = ctx.mm_op_prepare(mm.hermite_ho_exponential(m, tau), prec)
+    Fl, Bl = mm.hermite_matrices(m)
+    F, B = ctx.mm_op_prepare(Fl, prec), ctx.mm_op_prepare(Bl, prec)
     psi = to_gpu(psi0, prec, True)
-    ctx.ho_strang_step(psi, [Lh] * 3, [Xl] * 3, t0, tau, eps, nsteps)
+    ctx.ho_strang_step(psi, [F] * 3, [B] * 3, [Xl] * 3, t0, tau, eps, nsteps)
     err = rel(from_gpu(psi), ref)
     note(f"ho prec={prec} nsteps={nsteps} rel err {err:.3e}")
     assert err < REL_TOL[prec] * nsteps
@@ -51,10 +52,11 @@ def test_ho_strang_mixed_precision_operators(ctx, nsteps):
     psi0 = cast(om.tucker(c, [Psi] * 3), "fp32", True)
     ref = sc.ho_strang(psi0, [Phi] * 3, [Psi] * 3, [X] * 3, t0, tau, eps, nsteps)
     Xl, _ = mm.hermite_nodes(m)
-    H = mm.hermite_ho_exponential(m, tau)
-    Lh = [ctx.mm_op_prepare(H, p) for p in ("fp32", "bf16x3", "fp16x2")]
+    Fl, Bl = mm.hermite_matrices(m)
+    F = [ctx.mm_op_prepare(Fl, p) for p in ("fp32", "bf16x3", "fp16x2")]
+    B = [ctx.mm_op_prepare(Bl, p) for p in ("fp32", "bf16x3", "fp16x2")]
     psi = to_gpu(psi0, "fp32", True)
-    ctx.ho_strang_step(psi, Lh, [Xl] * 3, t0, tau, eps, nsteps)
+    ctx.ho_strang_step(psi, F, B, [Xl] * 3, t0, tau, eps, nsteps)
     err = rel(from_gpu(psi), ref)
     note(f"ho mixed precisions nsteps={nsteps} rel err {err:.3e}")
     assert err < REL_TOL["fp32"] * nsteps
@@ -67,9 +69,10 @@ def test_ho_eigenstate_phase_on_gpu(ctx):
     f = op.hermite_functions(m, op.hermite_nodes(m))
     k = (3, 1, 6)
     psi0 = f[k[0]][:, None, None] * f[k[1]][None, :, None] * f[k[2]][None, None, :]
-    Lh = ctx.mm_op_prepare(mm.hermite_ho_exponential(m, tau), "fp64")
+    Fl, Bl = mm.hermite_matrices(m)
+    F, B = ctx.mm_op_prepare(Fl, "fp64"), ctx.mm_op_prepare(Bl, "fp64")
     psi = to_gpu(psi0.astype(np.complex128), "fp64", True)
-    ctx.ho_strang_step(psi, [Lh] * 3, [X] * 3, 0.0, tau, 0.0, 2)
+    ctx.ho_strang_step(psi, [F] * 3, [B] * 3, [X] * 3, 0.0, tau, 0.0, 2)
     assert rel(from_gpu(psi), np.exp(-2j * tau * (sum(k) + 1.5)) * psi0) < 1e-12
 
 

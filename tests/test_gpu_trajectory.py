@@ -114,9 +114,10 @@ def test_ho_200_steps(ctx, prec):
     psi0 = cast(om.tucker(c, [Psi] * 3), prec, True)
     ref = sc.ho_strang(psi0, [Phi] * 3, [Psi] * 3, [X] * 3, 0.0, tau, eps, steps)
     Xl, _ = mm.hermite_nodes(m)
-    Lh = ctx.mm_op_prepare(mm.hermite_ho_exponential(m, tau), prec)
+    Fl, Bl = mm.hermite_matrices(m)
+    F, B = ctx.mm_op_prepare(Fl, prec), ctx.mm_op_prepare(Bl, prec)
     psi = to_gpu(psi0, prec, True)
-    ctx.ho_strang_step(psi, [Lh] * 3, [Xl] * 3, 0.0, tau, eps, steps)
+    ctx.ho_strang_step(psi, [F] * 3, [B] * 3, [Xl] * 3, 0.0, tau, eps, steps)
     err = rel(from_gpu(psi), ref)
     note(f"ho m={m} {steps} steps {prec}: rel L2 {err:.3e}")
     assert err < (1e-11 if prec == "fp64" else 1e-5)      # measured 1.4e-12 / 3.1e-6 / 2.6e-6
