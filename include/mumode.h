@@ -162,6 +162,23 @@ mm_status mumode_transform(mm_ctx ctx, mm_tensor* out, const mm_tensor* in, cons
 mm_status gpe_strang_step(mm_ctx ctx, mm_tensor* psi, const mm_op* E, double tau, double beta,
                           int nsteps, mm_stream stream);
 
+/* gpe_strang_step for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same computation and kernels, bit for bit, with no hipMalloc, hipFree
+ * or other allocating call.  The device memory the split FP16X2 products need
+ * besides psi (the running-bound slots and the max-abs partial maxima,
+ * 4192 bytes) is a fixed array in the library that each GPU holds until the
+ * process ends; every call on one GPU shares it (each call's first product
+ * rewrites all of it), so calls that overlap on one GPU, from any context or
+ * stream, race.  Limits: every n_mu <= 256 (each product runs in place, no
+ * workspace; MM_ERR_SHAPE otherwise), complex operators only (a real
+ * operator on a complex state needs a promoted copy: MM_ERR_UNSUPPORTED), no
+ * in-call monitor (MM_OPT_MONITOR_EVERY is ignored) and no per-launch
+ * profiling records.  Operators are prepared beforehand (mm_op_prepare
+ * allocates). */
+mm_status gpe_strang_step_noalloc(mm_ctx ctx, mm_tensor* psi, const mm_op* E, double tau, double beta,
+                                  int nsteps, mm_stream stream);
+
 /* Strang step for the harmonic oscillator with a time-dependent potential,
  * i psi_t = -1/2 Laplace psi + 1/2 |x|^2 (1 + eps sin t) psi, in nodal
  * Hermite space (Section 3, equations real2spec / spec2real; the Hermite

@@ -262,6 +262,12 @@ class Context:
                                            nsteps, _stream(stream)), "gpe_strang_step")
         return psi
 
+    def gpe_strang_step_noalloc(self, psi, E, tau: float, beta: float, nsteps: int = 1, stream=None):
+        t = as_mm_tensor(psi)
+        self._chk(_lib.lib.gpe_strang_step_noalloc(self.handle, C.byref(t), _op_array(E), float(tau), float(beta),
+                                                   nsteps, _stream(stream)), "gpe_strang_step_noalloc")
+        return psi
+
     def mumode_expstep_batched(self, tensors, ops, nsteps: int = 1, stream=None):
         """tensors: list of torch tensors; ops: list of per-instance op lists."""
         n = len(tensors)

@@ -30,6 +30,7 @@ EXPORTS = [
     "mm_set_workspace", "mumode_magnus_step", "mm_expm_device",
     "mm_fd2_periodic_order", "mm_fourier_d2", "mm_pipe_flow_operators", "mm_set_option", "mm_monitor_log",
     "mm_schrodinger_fd_hamiltonian", "mm_schrodinger_fd_exponential", "mm_hermite_ho_generator",
+    "gpe_strang_step_noalloc",
 ]
 
 
@@ -67,6 +68,7 @@ def _load():
         "mumode_expstep": (st, [P, C.POINTER(MMTensor), C.POINTER(P), C.c_int, P]),
         "mumode_transform": (st, [P, C.POINTER(MMTensor), C.POINTER(MMTensor), C.POINTER(P), P]),
         "gpe_strang_step": (st, [P, C.POINTER(MMTensor), C.POINTER(P), d, d, C.c_int, P]),
+        "gpe_strang_step_noalloc": (st, [P, C.POINTER(MMTensor), C.POINTER(P), d, d, C.c_int, P]),
         "mm_norm2": (st, [P, C.POINTER(MMTensor), d, C.POINTER(d), P]),
         "mm_profile_begin": (st, [P]),
         "ho_strang_step": (st, [P, C.POINTER(MMTensor), C.POINTER(P), C.POINTER(P), C.POINTER(C.POINTER(d)), d, d, d,

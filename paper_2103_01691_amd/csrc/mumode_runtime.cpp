@@ -12,9 +12,18 @@
 #include <string>
 #include <vector>
 
+#include <mutex>
+
 #include "../../include/mumode.h"
 #include "mm_internal.h"
 
+// Device memory of gpe_strang_step_noalloc: the FP16X2 running-bound slots
+// (3 x SMAX_WORDS words) and the max-abs pass's partial maxima, in a
+// file-scope array each GPU holds for the life of the process, so that call
+// allocates nothing.  Host code never uses the array's name as an address:
+// the device address comes from hipGetSymbolAddress, once per device.
+constexpr int NOALLOC_SCRATCH_WORDS = 3 * mm::SMAX_WORDS + 1024;
+static __device__ __align__(256) uint32_t scratch[NOALLOC_SCRATCH_WORDS];
 
 struct mm_op_s {
   int64_t rows = 0, cols = 0;
@@ -59,6 +68,7 @@ struct mm_ctx_s {
   // else (or the first one of an API call) starts a new chain with a
   // max-abs pass over its input.
   uint32_t* smax = nullptr;
+  uint32_t* smax_static = nullptr;  // device address of `scratch` on this context's device
   const void* chain_end = nullptr;
   int sidx = 0;
   // device matrix exponential scratch: X, T, W (complex FP64 n x n each),
@@ -105,6 +115,26 @@ struct mm_ctx_s {
 namespace {
 
 std::string g_create_err;
+
+// Device address of `scratch` per device, looked up once per device with
+// that device current.
+std::mutex g_scratch_mu;
+std::map<int, uint32_t*> g_scratch_addr;
+
+hipError_t scratch_address(int device, uint32_t** out) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  auto it = g_scratch_addr.find(device);
+  if (it != g_scratch_addr.end()) {
+    *out = it->second;
+    return hipSuccess;
+  }
+  void* p = nullptr;
+  hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return e;
+  g_scratch_addr[device] = (uint32_t*)p;
+  *out = (uint32_t*)p;
+  return hipSuccess;
+}
 
 mm_status fail(mm_ctx ctx, mm_status st, const char* fmt, ...) {
   char buf[512];
@@ -603,6 +633,13 @@ mm_status mm_create(mm_ctx* out, int device) {
     delete c;
     return fail(nullptr, MM_ERR_NOMEM, "context buffers");
   }
+  {
+    const hipError_t e = scratch_address(device, &c->smax_static);
+    if (e != hipSuccess) {
+      mm_destroy(c);
+      return fail(nullptr, MM_ERR_HIP, "hipGetSymbolAddress(scratch) failed: %s", hipGetErrorString(e));
+    }
+  }
   *out = c;
   return MM_OK;
 }
@@ -843,8 +880,10 @@ mm_status mumode_transform(mm_ctx ctx, mm_tensor* out, const mm_tensor* in, cons
   return MM_OK;
 }
 
-mm_status gpe_strang_step(mm_ctx ctx, mm_tensor* psi, const mm_op* E, double tau, double beta, int nsteps,
-                          mm_stream stream) {
+namespace {
+
+mm_status gpe_strang_impl(mm_ctx ctx, mm_tensor* psi, const mm_op* E, double tau, double beta, int nsteps,
+                          hipStream_t s, bool noalloc) {
   if (!ctx) return MM_ERR_ARG;
   ctx->mon_steps.clear();
   ctx->mon_vals.clear();
@@ -860,28 +899,77 @@ mm_status gpe_strang_step(mm_ctx ctx, mm_tensor* psi, const mm_op* E, double tau
       return fail(ctx, MM_ERR_SHAPE, "E[%d] must be %lld x %lld", k, (long long)psi->dims[k], (long long)psi->dims[k]);
     st = check_op_dtype(ctx, E[k], psi->dtype);
     if (st != MM_OK) return st;
+    if (noalloc && !E[k]->cplx)
+      return fail(ctx, MM_ERR_UNSUPPORTED, "E[%d] is real: the allocation-free step takes complex operators", k);
   }
   HIPCHK(ctx, hipSetDevice(ctx->device));
   ctx->chain_end = nullptr;
+  const double half = 0.5 * tau * beta, full = tau * beta;
+  if (noalloc) {
+    // every product must run in place (no workspace), i.e. its plan must
+    // give one workgroup all rows of its fibres; checked for each plan the
+    // sweeps below use (phase in the first product, in the last one only on
+    // the last step)
+    for (int k = 0; k < psi->d; ++k)
+      for (int lastep = 0; lastep < 2; ++lastep) {
+        mm::ModePlan plan;
+        const double pre = k == 0 ? half : 0.0;
+        const double post = (k == psi->d - 1 && lastep) ? half : 0.0;
+        st = run_mode(ctx, psi->data, psi->data, psi->dims, psi->d, psi->dtype, E[k], k + 1, pre, post, s, &plan,
+                      true);
+        if (st != MM_OK) return st;
+        if (!plan.covers_all_rows)
+          return fail(ctx, MM_ERR_SHAPE,
+                      "n_%d = %lld: the allocation-free step runs every product in place, which needs "
+                      "n_mu <= 256", k + 1, (long long)psi->dims[k]);
+      }
+  }
   // merged steps: N(tau/2) [L N(tau)]^(nsteps-1) L N(tau/2); each N(tau)
   // between steps is fused into the staging of the next step's first product
   // (where it overlaps MFMA work), the last N(tau/2) into the final epilogue
-  const double half = 0.5 * tau * beta, full = tau * beta;
-  st = monitor_begin(ctx, nsteps);
-  if (st != MM_OK) return st;
+  if (!noalloc) {
+    st = monitor_begin(ctx, nsteps);
+    if (st != MM_OK) return st;
+  }
   for (int it = 0; it < nsteps; ++it) {
     const double pre = (it == 0) ? half : full;
     const double post = (it + 1 < nsteps) ? 0.0 : half;
-    st = sweep(ctx, psi, E, pre, post, (hipStream_t)stream);
+    st = sweep(ctx, psi, E, pre, post, s);
     if (st != MM_OK) return st;
     // the phase flows keep |psi|, so the mass between merged steps is the
     // mass after the step
-    if (ctx->mon_every > 0 && ((it + 1) % ctx->mon_every == 0 || it + 1 == nsteps)) {
-      st = monitor_point(ctx, psi, it + 1, (hipStream_t)stream);
+    if (!noalloc && ctx->mon_every > 0 && ((it + 1) % ctx->mon_every == 0 || it + 1 == nsteps)) {
+      st = monitor_point(ctx, psi, it + 1, s);
       if (st != MM_OK) return st;
     }
   }
-  return monitor_end(ctx, (hipStream_t)stream);
+  return noalloc ? MM_OK : monitor_end(ctx, s);
+}
+
+}  // namespace
+
+mm_status gpe_strang_step(mm_ctx ctx, mm_tensor* psi, const mm_op* E, double tau, double beta, int nsteps,
+                          mm_stream stream) {
+  return gpe_strang_impl(ctx, psi, E, tau, beta, nsteps, (hipStream_t)stream, false);
+}
+
+mm_status gpe_strang_step_noalloc(mm_ctx ctx, mm_tensor* psi, const mm_op* E, double tau, double beta, int nsteps,
+                                  mm_stream stream) {
+  if (!ctx) return MM_ERR_ARG;
+  if (3 * mm::SMAX_WORDS + mm::norm_partials() > NOALLOC_SCRATCH_WORDS)
+    return fail(ctx, MM_ERR_UNSUPPORTED, "scratch array smaller than the FP16X2 bound slots and partials");
+  // the running-bound slots and max-abs partials of the FP16X2 products come
+  // from `scratch` (every chain starts with the max-abs pass, which writes
+  // all of them, so nothing needs clearing); no monitor, no per-launch events
+  uint32_t* own = ctx->smax;
+  const bool prof = ctx->profiling;
+  ctx->smax = ctx->smax_static;
+  ctx->profiling = false;
+  const mm_status st = gpe_strang_impl(ctx, psi, E, tau, beta, nsteps, (hipStream_t)stream, true);
+  ctx->smax = own;
+  ctx->profiling = prof;
+  ctx->chain_end = nullptr;
+  return st;
 }
 
 mm_status ho_strang_step(mm_ctx ctx, mm_tensor* psi, const mm_op* Phi_fwd, const mm_op* Psi_bwd,

@@ -1,0 +1,73 @@
+"""The allocation-free Gross-Pitaevskii step (gpe_strang_step_noalloc)
+against the allocating one (gpe_strang_step) and the oracle: two calls in a
+row, the second on a smaller state, in every precision; and its rejections.
+Collected last: the name sorts after every other test module."""
+import numpy as np
+import pytest
+
+import synth
+from gpu_util import REL_TOL, cast, from_gpu, note, rel, to_gpu
+from oracle import operators as op
+from oracle import schemes as sc
+
+pytestmark = pytest.mark.gpu
+
+A, B, BETA, TAU = -8.0, 8.0, 100.0, 1e-3
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import paper_2103_01691_amd as mm
+    c = mm.Context(0)
+    yield c
+    c.close()
+
+
+def _run(ctx, n, prec, nsteps):
+    import paper_2103_01691_amd as mm
+    psi0 = cast(synth.thomas_fermi_initial(n, A, B, 3, BETA, cfg_id=4), prec, True)
+    E = ctx.mm_op_prepare(mm.schrodinger_fd_exponential(n, A, B, 1.0, TAU), prec)
+    a = to_gpu(psi0, prec, True)
+    b = to_gpu(psi0, prec, True)
+    note(f"noalloc n={n} {prec} nsteps={nsteps}")
+    ctx.gpe_strang_step_noalloc(a, [E] * 3, TAU, BETA, nsteps)
+    ctx.gpe_strang_step(b, [E] * 3, TAU, BETA, nsteps)
+    ga, gb = from_gpu(a), from_gpu(b)
+    E.destroy()
+    ref = sc.gpe_strang(psi0, [op.ho_exponential(n, A, B, TAU)] * 3, TAU, BETA, nsteps)
+    return ga, gb, ref
+
+
+@pytest.mark.parametrize("prec", ["fp16x2", "bf16x3", "fp32", "fp64"])
+def test_noalloc_matches_allocating_step_twice(ctx, prec):
+    # same kernels, same arithmetic: bit-identical to the allocating entry
+    # point, and within the oracle tolerance; the second call has a smaller
+    # state and finds the first call's contents in the shared scratch
+    for n, nsteps in ((96, 3), (40, 2)):
+        ga, gb, ref = _run(ctx, n, prec, nsteps)
+        assert np.array_equal(ga, gb), f"n={n}: differs from gpe_strang_step"
+        err = rel(ga, ref)
+        note(f"noalloc n={n} {prec}: rel err vs oracle {err:.3e}")
+        assert err < nsteps * REL_TOL[prec]
+
+
+def test_noalloc_rejects_what_needs_memory(ctx):
+    import torch
+    import paper_2103_01691_amd as mm
+    n = 260                                   # a product that cannot run in place
+    E = ctx.mm_op_prepare(np.eye(n, dtype=np.complex128), "fp32")
+    psi = torch.zeros((4, 4, n), dtype=torch.complex64, device="cuda")
+    with pytest.raises(mm.MumodeError) as e:
+        ctx.gpe_strang_step_noalloc(psi, [E, None, None], TAU, BETA, 1)
+    assert e.value.status == 1                # NULL operator first
+    E4 = ctx.mm_op_prepare(np.eye(4, dtype=np.complex128), "fp32")
+    with pytest.raises(mm.MumodeError) as e:
+        ctx.gpe_strang_step_noalloc(psi, [E, E4, E4], TAU, BETA, 1)
+    assert e.value.status == 2                # MM_ERR_SHAPE
+    R = ctx.mm_op_prepare(np.eye(4), "fp32")  # real operator
+    small = torch.zeros((4, 4, 4), dtype=torch.complex64, device="cuda")
+    with pytest.raises(mm.MumodeError) as e:
+        ctx.gpe_strang_step_noalloc(small, [R, R, R], TAU, BETA, 1)
+    assert e.value.status == 7                # MM_ERR_UNSUPPORTED
+    for o in (E, E4, R):
+        o.destroy()
