@@ -211,9 +211,18 @@ def other_workloads(ctx, mm, torch):
         t = timed(torch, lambda k: ctx.ho_strang_step(psi, [F] * 3, [B] * 3, [Xl] * 3, 0.0, 0.02, 0.1, k), K)
         out[f"ho128_{prec}"] = {"steps_per_s": K / t, "ms_per_step": 1e3 * t / K,
                                 "tflops_effective": 3 * 8.0 * m * m ** 3 / (t / K) / 1e12}
+        # the forward and backward Hermite transforms alone (Section 3): six
+        # real-operator products on the complex state, each on the (re, im)
+        # planes as real fibres (4 flops per complex entry and operator column)
+        spec = torch.empty_like(psi)
+        ctx.mumode_transform(spec, psi, [F] * 3)
+        t6 = timed(torch, lambda k: [(ctx.mumode_transform(spec, psi, [F] * 3),
+                                      ctx.mumode_transform(psi, spec, [B] * 3)) for _ in range(k)], K)
+        out[f"ho128_{prec}"]["transforms_6pass_ms"] = 1e3 * t6 / K
+        out[f"ho128_{prec}"]["transforms_6pass_tflops_effective"] = 6 * 4.0 * m * m ** 3 / (t6 / K) / 1e12
         for o in (Lh, F, B):
             o.destroy()
-        del psi
+        del psi, spec
     # free Schroedinger, d = 3, n = 256 on [-10, 10]^3, tau = 0.01: exact in
     # time, one expstep (three mode products) per step, 100 steps per call
     x0 = synth.wavepacket_initial(256, -10.0, 10.0, 3)

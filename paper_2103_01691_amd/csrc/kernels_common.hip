@@ -344,7 +344,9 @@ int num_classes(int prec) {
 bool plan_mode(const ModeArgs& a, int prec, int cplx, bool want_pro, bool want_epi, bool fcontig_ok,
                bool kcontig_ok, ModePlan* plan, bool batch, int force_cls) {
   FragGeom g = frag_geom(prec);
-  const int load = kcontig_ok ? KL_KCONTIG : (fcontig_ok ? KL_FCONTIG : KL_GENERIC);
+  // two interleaved real fibres (P == 2), 16-byte aligned runs of 8 rows
+  const bool pair_ok = !kcontig_ok && !cplx && a.P == 2 && a.Kr % 8 == 0;
+  const int load = kcontig_ok ? KL_KCONTIG : (pair_ok ? KL_PAIR : (fcontig_ok ? KL_FCONTIG : KL_GENERIC));
   const int pro = (want_pro && cplx) ? 1 : 0;
   const int epi = (want_epi && cplx) ? 1 : 0;
   TileShape t0;

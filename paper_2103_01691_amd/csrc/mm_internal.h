@@ -7,7 +7,12 @@
 namespace mm {
 
 enum KPrec { KP_F64 = 0, KP_F32 = 1, KP_BF16X3 = 2, KP_FP16X2 = 3, KP_BF16 = 4 };
-enum KLoad { KL_KCONTIG = 0, KL_FCONTIG = 1, KL_GENERIC = 2 };
+// Fibre load paths: KCONTIG fibres contiguous (mu = 1, P = 1); FCONTIG
+// fibres interleaved with P % 4 == 0 (16-byte loads along P); GENERIC any
+// P (gather); PAIR P == 2, pairs of fibres interleaved (a real operator on
+// the (re, im) planes of a complex state along mode 1: each 16-byte load
+// holds two fibres' consecutive entries).
+enum KLoad { KL_KCONTIG = 0, KL_FCONTIG = 1, KL_GENERIC = 2, KL_PAIR = 3 };
 
 // Geometry of the MFMA fragment a precision uses: M rows and K values per
 // fragment, K values each lane holds, operator pieces per value (FP16X2

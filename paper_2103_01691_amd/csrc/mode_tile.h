@@ -307,8 +307,10 @@ __device__ __forceinline__ void mode_tile(const ModeArgs& a, int64_t tile_x, int
   // ---------------------------------------------------------------- staging
   // Tile of TK real K values x TF fibres handled by one thread at a time.
   constexpr int VL = 16 / sizeof(st);    // scalars per 16-byte vector
-  constexpr int TK = (KPL == 8) ? 8 : (LD == KL_KCONTIG ? VL : (CPLX ? 2 : 1));
-  constexpr int TF = (LD == KL_FCONTIG) ? (KPL == 8 ? (CPLX ? VL / 2 : VL) : (CPLX ? VL / 2 : VL)) : 1;
+  constexpr int TK = (KPL == 8) ? 8 : (LD == KL_KCONTIG ? VL : (LD == KL_PAIR ? VL / 2 : (CPLX ? 2 : 1)));
+  constexpr int TF = (LD == KL_FCONTIG) ? (KPL == 8 ? (CPLX ? VL / 2 : VL) : (CPLX ? VL / 2 : VL))
+                                        : (LD == KL_PAIR ? 2 : 1);
+  static_assert(LD != KL_PAIR || !CPLX, "paired fibres are real");
   constexpr int TILES_K = CK / TK;
   constexpr int TILES_F = NT / TF;
   constexpr int TILES = TILES_K * TILES_F;
@@ -318,7 +320,7 @@ __device__ __forceinline__ void mode_tile(const ModeArgs& a, int64_t tile_x, int
   st stage[TPT][VPT];
 
   auto tile_coords = [&](int t, int& tk, int& tf) {
-    if constexpr (LD == KL_KCONTIG) {
+    if constexpr (LD == KL_KCONTIG || LD == KL_PAIR) {
       tk = t % TILES_K;
       tf = t / TILES_K;
     } else {
@@ -342,13 +344,17 @@ __device__ __forceinline__ void mode_tile(const ModeArgs& a, int64_t tile_x, int
     tkl[u] = tk * TK;
     if constexpr (LD == KL_KCONTIG) {
       tsrc[u] = in + (tok[u] ? fg * (int64_t)a.Kr + tk * TK : 0);
+    } else if constexpr (LD == KL_PAIR) {
+      // fibres fg, fg + 1 (fg even) are entries 0 and 1 of the pair fg / 2,
+      // whose row j sits at 2 (j + n (fg / 2)) and 2 (j + n (fg / 2)) + 1
+      tsrc[u] = in + (tok[u] ? (fg / 2) * (int64_t)(2 * a.Kr) + tk * TK * 2 : 0);
     } else if constexpr (LD == KL_FCONTIG) {
       tsrc[u] = in + (tok[u] ? fibre_base(fg, a.P, a.n, COMPS) + (int64_t)(tk * TK / COMPS) * a.P * COMPS : 0);
     } else {
       tsrc[u] = in;
     }
   }
-  const int64_t cstride = (LD == KL_KCONTIG) ? (int64_t)CK : (int64_t)CK * a.P;
+  const int64_t cstride = (LD == KL_KCONTIG) ? (int64_t)CK : (LD == KL_PAIR ? (int64_t)2 * CK : (int64_t)CK * a.P);
 
   // Load chunk `c` (real K values [c*CK, c*CK + CK)) into registers.
   auto load_chunk = [&](int c) {
@@ -363,6 +369,28 @@ __device__ __forceinline__ void mode_tile(const ModeArgs& a, int64_t tile_x, int
           const st* src = tsrc[u] + c * cstride;
 #pragma unroll
           for (int w = 0; w < TK / VL; ++w) {
+            if constexpr (sizeof(st) == 4) {
+              f32x4 x = *(const f32x4*)(src + w * VL);
+#pragma unroll
+              for (int e = 0; e < 4; ++e) v[w * VL + e] = x[e];
+            } else {
+              f64x2 x = *(const f64x2*)(src + w * VL);
+              v[w * VL + 0] = x[0];
+              v[w * VL + 1] = x[1];
+            }
+          }
+        } else {
+#pragma unroll
+          for (int e = 0; e < VPT; ++e) v[e] = (st)0;
+        }
+      } else if constexpr (LD == KL_PAIR) {
+        // TK rows of a fibre pair: 2 TK contiguous scalars, row-major over
+        // (row, fibre of the pair), which is already the v[row * TF + fibre]
+        // order of the staging tile.
+        if (tok[u] && tkl[u] < klim) {
+          const st* src = tsrc[u] + c * cstride;
+#pragma unroll
+          for (int w = 0; w < 2 * TK / VL; ++w) {
             if constexpr (sizeof(st) == 4) {
               f32x4 x = *(const f32x4*)(src + w * VL);
 #pragma unroll
@@ -1000,6 +1028,16 @@ BatchFn bfn() {
 // contiguous and strided fibres.
 template <int PR>
 KernFn pick_kernel(int cplx, int ld, int pro, int epi, int cls, int full) {
+  if (ld == KL_PAIR) {
+    // real operator on paired fibres: classes 0..2, no phases
+    if (cplx || pro || epi) return nullptr;
+    switch (cls) {
+      case 0: return kfx<PR, false, KL_PAIR, false, false, 0>(full);
+      case 1: return kfn<PR, false, KL_PAIR, false, false, 1>();
+      case 2: return kfn<PR, false, KL_PAIR, false, false, 2>();
+      default: return nullptr;
+    }
+  }
 #define MM_PH(C_, L_, K_)                                                     \
   do {                                                                        \
     if (pro && epi) return kfx<PR, C_, L_, true, true, K_>(full);            \
@@ -1047,7 +1085,7 @@ template <int PR>
 BatchFn pick_batch(int cplx, int ld, int cls) {
   // FP16X2 needs a state bound per instance: no batched instances
   if constexpr (PR == KP_FP16X2) return nullptr;
-  if (ld == KL_GENERIC || cls > 2) return nullptr;
+  if (ld == KL_GENERIC || ld == KL_PAIR || cls > 2) return nullptr;
 #define MM_B(K_)                                                                      \
   do {                                                                                \
     if (cplx) return ld == KL_KCONTIG ? bfn<PR, true, KL_KCONTIG, K_>() : bfn<PR, true, KL_FCONTIG, K_>(); \

@@ -49,6 +49,7 @@ struct mm_ctx_s {
   // path, real rows Mr, real columns Kr, fibres F) -> (class, microseconds)
   std::map<std::array<int64_t, 6>, std::pair<int, double>> tune;
   int force_cls = -1;            // set while the autotuner times a class
+  std::array<int64_t, 6> last_key{};   // tune key of the last planned product
   bool small_run = true;         // whole-run single-workgroup kernel for small expsteps
   // in-call monitor (MM_OPT_MONITOR_EVERY): sum |T|^2 every mon_every steps
   // of mumode_expstep / gpe_strang_step, kept on the device until the call ends
@@ -242,7 +243,13 @@ mm_status run_mode(mm_ctx ctx, const void* in, void* out, const int64_t* dims, i
                    mm_op L, int mu, double s_pre, double s_post, hipStream_t s, mm::ModePlan* plan_out,
                    bool dry, const void* prep_override = nullptr, bool batch = false,
                    mm::ModeArgs* args_out = nullptr) {
-  const bool cplx = is_complex(dt);
+  // A real operator on a complex state (with no fused phase) acts on the
+  // (re, im) planes separately: the state is then the real tensor
+  // (2, n_1, ..., n_d) and mode mu its mode mu + 1, i.e. two real fibres per
+  // complex one (half the MFMA work of the complex block form, and no
+  // promoted copy of the operator).
+  const bool rview = !L->cplx && is_complex(dt) && !batch && s_pre == 0.0 && s_post == 0.0 && !prep_override;
+  const bool cplx = is_complex(dt) && !rview;
   void* prep = nullptr;
   int KBT = 0, MFT = 0;
   if (prep_override) {
@@ -256,7 +263,7 @@ mm_status run_mode(mm_ctx ctx, const void* in, void* out, const int64_t* dims, i
     mm::op_blocks(kprec(L->prec), (cplx ? 2 : 1) * L->rows, (cplx ? 2 : 1) * L->cols, &KBT, &MFT);
   }
   mm::ModeArgs a;
-  int64_t P = 1, Q = 1;
+  int64_t P = rview ? 2 : 1, Q = 1;
   for (int k = 0; k < mu - 1; ++k) P *= dims[k];
   for (int k = mu; k < d; ++k) Q *= dims[k];
   a.in = in;
@@ -280,10 +287,12 @@ mm_status run_mode(mm_ctx ctx, const void* in, void* out, const int64_t* dims, i
   a.pad_ = 0;
   const bool kcontig = (P == 1) && (a.Kr % 8 == 0);
   const bool fcontig = (P % 4 == 0);
+  const bool pair = !kcontig && !cplx && P == 2 && a.Kr % 8 == 0;   // as the planner decides
+  const int load = kcontig ? mm::KL_KCONTIG : (pair ? mm::KL_PAIR : (fcontig ? mm::KL_FCONTIG : mm::KL_GENERIC));
+  ctx->last_key = {(int64_t)kprec(L->prec), cplx ? 1 : 0, load, a.Mr, a.Kr, a.F};
   int force = ctx->force_cls;
   if (force < 0 && !ctx->tune.empty()) {
-    const int load = kcontig ? mm::KL_KCONTIG : (fcontig ? mm::KL_FCONTIG : mm::KL_GENERIC);
-    auto it = ctx->tune.find({(int64_t)kprec(L->prec), cplx ? 1 : 0, load, a.Mr, a.Kr, a.F});
+    auto it = ctx->tune.find(ctx->last_key);
     if (it != ctx->tune.end()) force = it->second.first;
   }
   mm::ModePlan plan;
@@ -301,7 +310,7 @@ mm_status run_mode(mm_ctx ctx, const void* in, void* out, const int64_t* dims, i
   if (dry) return MM_OK;
   if (plan.prec == mm::KP_FP16X2) {
     if (in != ctx->chain_end) {
-      int64_t count = (cplx ? 2 : 1);
+      int64_t count = is_complex(dt) ? 2 : 1;
       for (int k = 0; k < d; ++k) count *= dims[k];
       HIPCHK(ctx, mm::launch_maxabs((const float*)in, count, ctx->smax + 3 * mm::SMAX_WORDS, ctx->smax, s));
       ctx->sidx = 0;
@@ -546,6 +555,7 @@ mm_status small_expstep(mm_ctx ctx, mm_tensor* T, const mm_op* E, int nsteps, hi
     if (!E[k]) continue;
     const int p = kprec(E[k]->prec);
     if ((p != mm::KP_F64 && p != mm::KP_F32) || (kp >= 0 && p != kp)) return MM_OK;
+    if (cplx && !E[k]->cplx) return MM_OK;   // real operator on complex planes: one launch per product
     kp = p;
     mm::ModePlan plan;
     mm::ModeArgs a;
@@ -1456,8 +1466,7 @@ mm_status mm_autotune(mm_ctx ctx, const mm_tensor* T, const mm_op* E, int budget
       ctx->chain_end = nullptr;
       st = run_mode(ctx, T->data, ctx->ws, T->dims, T->d, T->dtype, L, k + 1, 0, 0, s, &plan, false);
       if (st == MM_OK) {
-        key = {(int64_t)kp, cplx ? 1 : 0, plan.load, (cplx ? 2 : 1) * L->rows, (cplx ? 2 : 1) * T->dims[k],
-               plan.grid_x > 0 ? onum / odims[k] : 0};
+        key = ctx->last_key;
         HIPCHK(ctx, hipEventRecord(e0, s));
         ctx->chain_end = T->data;
         ctx->sidx = 0;

@@ -54,17 +54,86 @@ def test_apply_rectangular(ctx, prec, cplx, dims, mu):
     Lop.destroy()
 
 
-@pytest.mark.parametrize("prec", ["fp64", "bf16x3", "fp16x2"])
-def test_apply_real_operator_on_complex_state(ctx, prec):
-    dims = (40, 24, 12)
-    g = synth.rng(1002, 0)
+PREC_CODE = {"fp64": 0, "fp32": 1, "bf16x3": 2, "fp16x2": 3, "bf16": 4}
+
+
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("dims", [(48, 40, 36), (37, 30, 21), (64, 6, 10)])
+@pytest.mark.parametrize("mu", [1, 2, 3])
+def test_apply_real_operator_on_complex_state(ctx, prec, dims, mu):
+    # a real (rectangular, non-symmetric) operator on a complex state runs
+    # the real kernels on the (re, im) planes as two real fibres per complex
+    # one: mode 1 with n_1 % 8 == 0 through the paired-fibre load, the other
+    # modes through the strided load (2P % 4 == 0) or the gather
+    note(f"real op on complex prec={prec} dims={dims} mu={mu}")
+    g = synth.rng(1002, mu)
     U = cast(synth.random_tensor(dims, True, g), prec, True)
-    L = synth.random_matrix(24, 24, False, g)
-    ref = om.mode_product(U, L, 2)
+    m = dims[mu - 1] + 3
+    L = synth.random_matrix(m, dims[mu - 1], False, g)
+    ref = om.mode_product(U, L, mu)
     Lop = ctx.mm_op_prepare(L, prec)
-    out = empty_gpu(dims, prec, True)
-    ctx.mumode_apply(out, to_gpu(U, prec, True), Lop, 2)
-    assert rel(from_gpu(out), ref) < REL_TOL[prec]
+    out_dims = list(dims)
+    out_dims[mu - 1] = m
+    out = empty_gpu(out_dims, prec, True)
+    ctx.mm_profile_begin()
+    ctx.mumode_apply(out, to_gpu(U, prec, True), Lop, mu)
+    rec = ctx.mm_profile_end()
+    err = rel(from_gpu(out), ref)
+    Lop.destroy()
+    note(f"  rel err {err:.3e}, kernels {[k for k, _ in rec]}")
+    assert err < REL_TOL[prec]
+    # one launch of the real kernel (complex digit 0); mode 1 with whole
+    # 8-row runs uses the paired-fibre load (load digit 3)
+    assert len(rec) == 1 and (rec[0][0] // 100) % 10 == 0 and rec[0][0] // 1000 == PREC_CODE[prec]
+    P2 = 2 * int(np.prod(dims[:mu - 1]))
+    want = 3 if (P2 == 2 and dims[0] % 8 == 0) else (1 if P2 % 4 == 0 else 2)
+    assert (rec[0][0] // 10) % 10 == want
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3", "fp16x2"])
+def test_expstep_real_operators_on_complex_state(ctx, prec):
+    # in place over all modes, twice (the FP16x2 bound follows the chain)
+    dims = (64, 40, 24)
+    g = synth.rng(1007, 0)
+    U = cast(synth.random_tensor(dims, True, g), prec, True)
+    E = [synth.random_matrix(n, n, False, g) for n in dims]
+    ref = om.expstep(U, E, 2)
+    ops = [ctx.mm_op_prepare(e, prec) for e in E]
+    T = to_gpu(U, prec, True)
+    ctx.mumode_expstep(T, ops, 2)
+    err = rel(from_gpu(T), ref)
+    note(f"expstep real ops on complex prec={prec} rel err {err:.3e}")
+    assert err < 2 * REL_TOL[prec]
+    for o in ops:
+        o.destroy()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3", "fp16x2"])
+def test_hermite_transform_real_on_complex_128(ctx, prec):
+    # the forward / backward Hermite transforms of Section 3 (real Phi, Psi)
+    # on a complex state, n = 128 per mode: spec = psi x_1 Phi x_2 Phi x_3 Phi
+    # and back
+    import paper_2103_01691_amd as mm
+    m = 128
+    Phi, Psi = op.hermite_forward(m), op.hermite_backward(m)
+    c = synth.hermite_coefficients(m, 16, 3, cfg_id=3)
+    psi0 = cast(om.tucker(c, [Psi] * 3), prec, True)
+    Fl, Bl = mm.hermite_matrices(m)
+    F, B = ctx.mm_op_prepare(Fl, prec), ctx.mm_op_prepare(Bl, prec)
+    spec = empty_gpu((m, m, m), prec, True)
+    back = empty_gpu((m, m, m), prec, True)
+    ctx.mm_profile_begin()
+    ctx.mumode_transform(spec, to_gpu(psi0, prec, True), [F] * 3)
+    ctx.mumode_transform(back, spec, [B] * 3)
+    rec = ctx.mm_profile_end()
+    ref_spec = om.tucker(psi0, [Phi] * 3)
+    e1 = rel(from_gpu(spec), ref_spec)
+    e2 = rel(from_gpu(back), om.tucker(ref_spec, [Psi] * 3))
+    note(f"hermite transform 128 {prec}: forward {e1:.3e}, back {e2:.3e}")
+    assert e1 < REL_TOL[prec] and e2 < 2 * REL_TOL[prec]
+    assert len(rec) == 6 and all((k // 100) % 10 == 0 for k, _ in rec)
+    F.destroy()
+    B.destroy()
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3", "fp16x2"])
