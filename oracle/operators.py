@@ -23,6 +23,13 @@ Pins (tests/test_oracle_operators.py):
                            on functions that satisfy the boundary conditions
                            (Neumann / Dirichlet-Neumann), against the
                            analytic operator including the 1/r and s(z) terms.
+  nonuniform_neumann_d2 -- on a uniform grid, the similarity transform of the
+                           textbook ghost-point Neumann matrix and its closed-
+                           form cosine spectrum; constants in the kernel
+                           (W^(1/2) 1 is a null vector); second-order
+                           consistency of W^(-1/2) M W^(1/2) on a smoothly
+                           graded grid; the W-weighted mass is conserved by
+                           the exponential of i M.
 """
 from __future__ import annotations
 
@@ -246,3 +253,35 @@ def pipe_flow_operators(n_rho: int, n_z: int, rho_min: float, rho_max: float, z_
     s = 2.0 + np.tanh(4.0 * (z - 2.5)) - np.tanh(4.0 * (z - 5.0))
     A_z = alpha * D2z - np.diag(s) @ D1z
     return A_r, A_z, r, z
+
+
+def nonuniform_neumann_d2(x: np.ndarray):
+    """Second derivative on the non-uniform nodes x_0 < ... < x_{n-1} of
+    [x_0, x_{n-1}] with homogeneous Neumann conditions at both ends, in the
+    symmetrised form of Section 4.5 (reading: the conservative three-point
+    scheme with dual cells, then the variable change that makes it
+    symmetric).
+
+    Cells h_j = x_{j+1} - x_j; dual cells w_0 = h_0 / 2, w_j = (h_{j-1} +
+    h_j) / 2, w_{n-1} = h_{n-2} / 2.  The scheme is
+        (D u)_j = (1/w_j) [(u_{j+1} - u_j)/h_j - (u_j - u_{j-1})/h_{j-1}],
+    with the flux through each end set to zero (homogeneous Neumann), i.e.
+    D = W^-1 S with S symmetric tridiagonal and W = diag(w).  The variable
+    v = W^(1/2) u turns it into the symmetric M_W = W^(-1/2) S W^(-1/2), and
+    sum_j w_j |u_j|^2 = |v|^2.  Returns (M_W, w)."""
+    x = np.asarray(x, dtype=np.float64)
+    n = x.size
+    h = np.diff(x)
+    w = np.empty(n)
+    w[0] = 0.5 * h[0]
+    w[-1] = 0.5 * h[-1]
+    w[1:-1] = 0.5 * (h[:-1] + h[1:])
+    S = np.zeros((n, n))
+    for j in range(n - 1):
+        c = 1.0 / h[j]          # flux between nodes j and j + 1
+        S[j, j] -= c
+        S[j + 1, j + 1] -= c
+        S[j, j + 1] += c
+        S[j + 1, j] += c
+    r = 1.0 / np.sqrt(w)
+    return S * r[:, None] * r[None, :], w

@@ -61,6 +61,18 @@ def periodic_nodes(n: int, a: float, b: float) -> np.ndarray:
 # random tensors and matrices
 # --------------------------------------------------------------------------
 
+def graded_nodes(n: int, a: float, b: float, alpha: float = 2.0) -> np.ndarray:
+    """n nodes from a to b (both included), denser near the centre:
+    x = c + r sinh(alpha xi) / sinh(alpha), xi uniform on [-1, 1] (c the
+    centre, r the half-width); alpha -> 0 gives the uniform grid.  A smooth
+    grading, so three-point differences on it stay second order."""
+    xi = np.linspace(-1.0, 1.0, n)
+    c, r = 0.5 * (a + b), 0.5 * (b - a)
+    if alpha == 0.0:
+        return c + r * xi
+    return c + r * np.sinh(alpha * xi) / np.sinh(alpha)
+
+
 def random_tensor(dims, complex_: bool, g: np.random.Generator, dist: str = "normal") -> np.ndarray:
     dims = tuple(int(x) for x in dims)
     if dist == "uniform":

@@ -126,3 +126,75 @@ def test_hkmp_generators_are_the_papers_hamiltonian():
             if mu == 2:
                 want = want + 0.5j * (-2.0 * X * np.sin(t) ** 2 * f)
             assert np.max(np.abs(A @ f - want)) < 1e-11 * np.max(np.abs(want)), (t, mu)
+
+
+# ------------------------------------- non-uniform Neumann (Section 4.5) ---
+
+def test_nonuniform_neumann_uniform_grid_is_symmetrised_ghost_point_matrix():
+    # on a uniform grid the textbook ghost-point Neumann matrix is
+    # h^-2 [-2 2; 1 -2 1; ...; 2 -2]; with T = diag(1/2, 1, ..., 1, 1/2) the
+    # similarity T^(1/2) D T^(-1/2) is symmetric and must be M_W
+    n, a, b = 17, -3.0, 5.0
+    x = np.linspace(a, b, n)
+    h = x[1] - x[0]
+    D = (np.diag(-2.0 * np.ones(n)) + np.diag(np.ones(n - 1), 1) + np.diag(np.ones(n - 1), -1)) / h ** 2
+    D[0, 1] = D[n - 1, n - 2] = 2.0 / h ** 2
+    t = np.ones(n)
+    t[0] = t[-1] = 0.5
+    M, w = op.nonuniform_neumann_d2(x)
+    assert np.allclose(w, h * t, rtol=1e-14, atol=0)
+    ref = np.sqrt(t)[:, None] * D / np.sqrt(t)[None, :]
+    assert np.max(np.abs(M - ref)) < 1e-12 * np.max(np.abs(ref))
+
+
+def test_nonuniform_neumann_uniform_spectrum_closed_form():
+    # Neumann cosine modes cos(k pi j/(n-1)): lambda_k = -(4/h^2) sin^2(k pi/(2(n-1)))
+    n = 40
+    x = np.linspace(0.0, 2.0, n)
+    h = x[1] - x[0]
+    lam = np.sort(np.linalg.eigvalsh(op.nonuniform_neumann_d2(x)[0]))
+    k = np.arange(n)
+    ref = np.sort(-(4.0 / h ** 2) * np.sin(k * np.pi / (2 * (n - 1))) ** 2)
+    assert np.max(np.abs(lam - ref)) < 1e-10 * np.max(np.abs(ref))
+
+
+def test_nonuniform_neumann_constants_in_kernel():
+    # homogeneous Neumann: constants are harmonic, so W^(1/2) 1 is a null
+    # vector of M_W on any grid (a wrong end weight or flux breaks this)
+    g = np.random.default_rng(7)
+    x = np.sort(g.uniform(-20.0, 20.0, 37))
+    M, w = op.nonuniform_neumann_d2(x)
+    v = np.sqrt(w)
+    assert np.linalg.norm(M @ v) < 1e-12 * np.linalg.norm(M) * np.linalg.norm(v)
+    assert np.max(np.abs(M - M.T)) < 1e-15 * np.max(np.abs(M))
+
+
+def test_nonuniform_neumann_second_order_on_graded_grid():
+    # u = cos(pi (x - a)/(b - a)) has u' = 0 and u''' = 0 at both ends; the
+    # unsymmetrised operator W^(-1/2) M W^(1/2) approximates u'' at second
+    # order on a smoothly graded grid, boundary rows included
+    a, b = -20.0, 20.0
+    errs = []
+    for n in (81, 161, 321):
+        x = synth.graded_nodes(n, a, b, 2.0)
+        M, w = op.nonuniform_neumann_d2(x)
+        u = np.cos(np.pi * (x - a) / (b - a))
+        D = (M * np.sqrt(w)[None, :]) / np.sqrt(w)[:, None]
+        exact = -(np.pi / (b - a)) ** 2 * u
+        errs.append(np.max(np.abs(D @ u - exact)) / np.max(np.abs(exact)))
+    assert errs[-1] < 1e-3
+    for e0, e1 in zip(errs, errs[1:]):
+        assert 3.6 < e0 / e1 < 4.4
+
+
+def test_nonuniform_neumann_flow_keeps_weighted_mass():
+    # i psi_t = -1/2 D psi in the variable v = W^(1/2) psi: exp(i tau/2 M_W)
+    # is unitary, so sum_j w_j |psi_j|^2 is conserved
+    g = np.random.default_rng(8)
+    x = synth.graded_nodes(50, -20.0, 20.0, 1.5)
+    M, w = op.nonuniform_neumann_d2(x)
+    E = op.exp_symmetric(M, 0.5j * 0.1)
+    psi = g.standard_normal(50) + 1j * g.standard_normal(50)
+    v = np.sqrt(w) * psi
+    psi1 = (E @ v) / np.sqrt(w)
+    assert abs(np.sum(w * np.abs(psi1) ** 2) / np.sum(w * np.abs(psi) ** 2) - 1.0) < 1e-13
