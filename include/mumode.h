@@ -416,6 +416,20 @@ mm_status mm_fourier_d2(int n, double a, double b, double* out);
 mm_status mm_pipe_flow_operators(int n_r, int n_z, double r_min, double r_max, double z_max, double alpha,
                                  double* A_r, double* A_z);
 
+/* Second derivative on the non-uniform nodes x[0] < ... < x[n-1] (both
+ * ends are boundary nodes) with homogeneous Neumann conditions, in the
+ * symmetrised form of Section 4.5: the conservative three-point scheme
+ * (D u)_j = (1/w_j) [(u_{j+1} - u_j)/h_j - (u_j - u_{j-1})/h_{j-1}],
+ * h_j = x[j+1] - x[j], dual cells w_j = (h_{j-1} + h_j)/2 (w_0 = h_0/2,
+ * w_{n-1} = h_{n-2}/2), no flux through the ends, is D = W^-1 S with S
+ * symmetric; the variable v = W^(1/2) u makes it M = W^(-1/2) S W^(-1/2),
+ * symmetric, and sum_j w_j |u_j|^2 = |v|^2.  In d dimensions the generator
+ * of the transformed problem is the Kronecker sum of the modes' M and the
+ * weight the Kronecker product of their W.  M: n*n doubles, column-major;
+ * w: n doubles (nullable).  MM_ERR_ARG for n outside [2, 4096] or NULL x /
+ * M, MM_ERR_SHAPE for nodes not strictly increasing. */
+mm_status mm_nonuniform_neumann_d2(int n, const double* x, double* M, double* w);
+
 #ifdef __cplusplus
 }
 #endif

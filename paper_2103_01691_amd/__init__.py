@@ -137,6 +137,19 @@ def pipe_flow_operators(n_r: int, n_z: int, r_min: float = 0.1, r_max: float = 5
     return np.asarray(A_r), np.asarray(A_z)
 
 
+def nonuniform_neumann_d2(x):
+    """(M_W, w): symmetrised second derivative on the non-uniform nodes x with
+    homogeneous Neumann ends, and the dual-cell weights (Section 4.5)."""
+    x = np.ascontiguousarray(np.asarray(x, dtype=np.float64))
+    n = x.size
+    M = np.zeros((n, n), dtype=np.float64, order="F")
+    w = np.zeros(n)
+    _check(_lib.lib.mm_nonuniform_neumann_d2(n, x.ctypes.data_as(C.POINTER(C.c_double)),
+                                             M.ctypes.data_as(C.POINTER(C.c_double)),
+                                             w.ctypes.data_as(C.POINTER(C.c_double))), "mm_nonuniform_neumann_d2")
+    return np.asarray(M), w
+
+
 # -------------------------------------------------------------- tensors ----
 
 def _dtype_code(t) -> int:

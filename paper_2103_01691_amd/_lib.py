@@ -30,7 +30,7 @@ EXPORTS = [
     "mm_set_workspace", "mumode_magnus_step", "mm_expm_device",
     "mm_fd2_periodic_order", "mm_fourier_d2", "mm_pipe_flow_operators", "mm_set_option", "mm_monitor_log",
     "mm_schrodinger_fd_hamiltonian", "mm_schrodinger_fd_exponential", "mm_hermite_ho_generator",
-    "gpe_strang_step_noalloc",
+    "gpe_strang_step_noalloc", "mm_nonuniform_neumann_d2",
 ]
 
 
@@ -99,6 +99,7 @@ def _load():
         "mm_schrodinger_fd_hamiltonian": (st, [C.c_int, d, d, d, C.POINTER(d)]),
         "mm_schrodinger_fd_exponential": (st, [C.c_int, d, d, d, d, C.POINTER(d)]),
         "mm_hermite_ho_generator": (st, [C.c_int, C.POINTER(d)]),
+        "mm_nonuniform_neumann_d2": (st, [C.c_int, C.POINTER(d), C.POINTER(d), C.POINTER(d)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)

@@ -328,4 +328,30 @@ mm_status mm_pipe_flow_operators(int n_r, int n_z, double r_min, double r_max, d
   return MM_OK;
 }
 
+mm_status mm_nonuniform_neumann_d2(int n, const double* x, double* M, double* w) {
+  if (n < 2 || n > 4096 || !x || !M) return MM_ERR_ARG;
+  for (int j = 0; j + 1 < n; ++j)
+    if (!(x[j + 1] > x[j]) || !std::isfinite(x[j]) || !std::isfinite(x[j + 1])) return MM_ERR_SHAPE;
+  // dual-cell widths: half of each neighbouring cell
+  std::vector<double> wd(n, 0.0);
+  for (int j = 0; j + 1 < n; ++j) {
+    const double h = x[j + 1] - x[j];
+    wd[j] += 0.5 * h;
+    wd[j + 1] += 0.5 * h;
+  }
+  std::memset(M, 0, sizeof(double) * (size_t)n * n);
+  // M = W^-1/2 S W^-1/2, S the stiffness of the fluxes (u_{j+1} - u_j) / h_j;
+  // no flux through the ends (homogeneous Neumann)
+  for (int j = 0; j + 1 < n; ++j) {
+    const double c = 1.0 / (x[j + 1] - x[j]);
+    const double off = c / std::sqrt(wd[j] * wd[j + 1]);
+    M[(size_t)j * n + j] -= c / wd[j];
+    M[(size_t)(j + 1) * n + (j + 1)] -= c / wd[j + 1];
+    M[(size_t)(j + 1) * n + j] = off;
+    M[(size_t)j * n + (j + 1)] = off;
+  }
+  if (w) std::memcpy(w, wd.data(), sizeof(double) * n);
+  return MM_OK;
+}
+
 }  // extern "C"

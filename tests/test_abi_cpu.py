@@ -181,3 +181,22 @@ def test_library_hermite_generator_matches_oracle():
         G = mm.hermite_ho_generator(m)
         ref = op.hermite_ho_generator(m)
         assert np.max(np.abs(G - ref)) <= 1e-11 * np.max(np.abs(ref))
+
+
+@pytest.mark.parametrize("alpha", [0.0, 2.0])
+def test_library_nonuniform_neumann_matches_oracle(alpha):
+    import paper_2103_01691_amd as mm
+    for n in (2, 5, 64):
+        x = synth.graded_nodes(n, -20.0, 20.0, alpha)
+        M, w = mm.nonuniform_neumann_d2(x)
+        Mo, wo = op.nonuniform_neumann_d2(x)
+        assert np.max(np.abs(M - Mo)) <= 1e-14 * np.max(np.abs(Mo))
+        assert np.max(np.abs(w - wo)) <= 1e-14 * np.max(wo)
+
+
+def test_library_nonuniform_neumann_validates():
+    import paper_2103_01691_amd as mm
+    with pytest.raises(mm.MumodeError):
+        mm.nonuniform_neumann_d2(np.array([0.0, 1.0, 1.0, 2.0]))     # not strictly increasing
+    with pytest.raises(mm.MumodeError):
+        mm.nonuniform_neumann_d2(np.array([0.0]))

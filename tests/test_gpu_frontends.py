@@ -75,3 +75,46 @@ def test_pipe_flow_step(ctx, prec):
     err = rel(from_gpu(c), ref)
     note(f"pipe flow n={n} {prec} rel err {err:.3e}")
     assert err < REL_TOL[prec] * (10 if prec == "fp64" else 1)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3", "fp16x2"])
+def test_nonuniform_neumann_schroedinger_flow(ctx, prec):
+    # the linear part of the Section 4.5 vortex problem, i psi_t = -1/2 Laplace
+    # psi on [-20, 20]^3 with homogeneous Neumann ends, discretised on graded
+    # non-uniform nodes (a different count per mode) and symmetrised: in
+    # v = W^(1/2) psi the flow is the mu-mode integrator with
+    # E_mu = exp(i tau/2 M_mu), and the W-weighted mass sum W |psi|^2 = |v|^2
+    # is conserved
+    import synth
+    import paper_2103_01691_amd as mm
+    dims, tau, steps = (48, 40, 32), 0.1, 3
+    xs = [synth.graded_nodes(n, -20.0, 20.0, 2.0) for n in dims]
+    El, Eo, ws = [], [], []
+    for x in xs:
+        Ml, wl = mm.nonuniform_neumann_d2(x)
+        Mo, wo = op.nonuniform_neumann_d2(x)
+        El.append(mm.expm(Ml, 0.5j * tau))
+        Eo.append(op.exp_symmetric(Mo, 0.5j * tau))
+        ws.append(wo)
+    g = synth.rng(1401, 0)
+    W = ws[0][:, None, None] * ws[1][None, :, None] * ws[2][None, None, :]
+    # two displaced Gaussian blobs with opposite momenta plus noise
+    psi = (np.exp(-((xs[0][:, None, None] - 3) ** 2 + xs[1][None, :, None] ** 2 + xs[2][None, None, :] ** 2) / 8
+                  + 1j * xs[0][:, None, None])
+           + np.exp(-((xs[0][:, None, None] + 3) ** 2 + xs[1][None, :, None] ** 2 + xs[2][None, None, :] ** 2) / 8
+                    - 1j * xs[0][:, None, None]))
+    psi = psi + 1e-3 * synth.random_tensor(dims, True, g)
+    v0 = cast(np.sqrt(W) * psi, prec, True)
+    ref = om.expstep(v0, Eo, steps)
+    ops = [ctx.mm_op_prepare(e, prec) for e in El]
+    v = to_gpu(v0, prec, True)
+    ctx.mumode_expstep(v, ops, steps)
+    got = from_gpu(v)
+    err = rel(got, ref)
+    mass0 = float(np.sum(np.abs(v0) ** 2))
+    mass = ctx.mm_norm2(v, 1.0)
+    note(f"non-uniform Neumann {prec}: rel L2 {err:.3e}, weighted mass drift {abs(mass / mass0 - 1):.2e}")
+    assert err < steps * REL_TOL[prec]
+    assert abs(mass / mass0 - 1.0) < (1e-12 if prec == "fp64" else 1e-5)
+    for o in ops:
+        o.destroy()
