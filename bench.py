@@ -88,12 +88,13 @@ def build_operator(mm):
     return mm.schrodinger_fd_exponential(N, A, B, 1.0, TAU)
 
 
-def time_path(ctx, mm, torch, E, psi0_np, prec, steps, warmup, profile, tune_ms=0, tune_file=None):
+def time_path(ctx, mm, torch, E, psi0_np, prec, steps, warmup, profile, tune_ms=0, tune_file=None,
+              identity_split=False):
     cdt = torch.complex128 if prec == "fp64" else torch.complex64
     npdt = np.complex128 if prec == "fp64" else np.complex64
     import synth
     psi = torch.from_numpy(synth.to_device_layout(psi0_np.astype(npdt))).cuda()
-    op = ctx.mm_op_prepare(E, prec)
+    op = ctx.mm_op_prepare(E, prec, identity_split=identity_split)
     ops = [op] * D
     tuned = []
     if tune_ms > 0 or tune_file:
@@ -353,6 +354,14 @@ def main():
                 prec, (SPLIT_PRODUCTS.get(prec, 1), PEAK["bf16"]))
             side[prec] = {"ms_per_step": pms, "steps_per_s": 1e3 / pms, "tflops_effective": eff,
                           "executed_mfma_frac_per_step": mult * eff * 1e12 / peak}
+        # trajectory-accurate variants: operators prepared as L - I (identity
+        # split), each product adding its input back in the epilogue
+        for prec in SPLIT_PRODUCTS:
+            k = max(10, args.steps // 4)
+            log(f"timing {prec} with the identity split: {k} steps")
+            pms, _, _, _ = time_path(ctx, mm, torch, E, psi0, prec, k, 5, False, args.tune_ms, identity_split=True)
+            side[f"{prec}_identity_split"] = {"ms_per_step": pms, "steps_per_s": 1e3 / pms,
+                                              "tflops_effective": FLOPS_PER_STEP / (pms * 1e-3) / 1e12}
 
     workloads = None
     if not args.no_workloads:

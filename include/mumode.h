@@ -127,7 +127,24 @@ const char* mm_version(void);
  * master to the device and convert / split it into the layout the kernels
  * read.  The context owns *out.  m, n in [1, 4096]. */
 mm_status mm_op_prepare(mm_ctx ctx, const mm_matrix* master, mm_prec prec, mm_op* out);
+/* mm_op_prepare with flags:
+ *   MM_OP_IDENTITY_SPLIT  square L only: the prepared pieces hold L - I,
+ *     formed from the FP64 master, and every product adds its input entry
+ *     back in FP32 in the epilogue (after a fused prologue phase), so the
+ *     result is still T x_mu L.  For the near-identity exponentials of small
+ *     time steps the MFMA accumulation then carries only the small
+ *     departure from identity: the operator's representation error and the
+ *     rounding of the accumulation scale with |L - I| instead of |L|, which
+ *     keeps the split schemes' drift over long runs below the FP32 path's
+ *     (R15).  Costs one extra read of the input per product.  Not accepted
+ *     as a Hermite transform of ho_strang_step.
+ * MM_ERR_ARG for unknown flags, MM_ERR_SHAPE for a non-square L with
+ * MM_OP_IDENTITY_SPLIT. */
+enum { MM_OP_IDENTITY_SPLIT = 1 };
+mm_status mm_op_prepare_ex(mm_ctx ctx, const mm_matrix* master, mm_prec prec, unsigned flags, mm_op* out);
 mm_status mm_op_destroy(mm_ctx ctx, mm_op op);
+/* Flags an operator was prepared with. */
+mm_status mm_op_flags(mm_op op, unsigned* flags);
 /* Shape / type query of a prepared operator (any out pointer may be NULL). */
 mm_status mm_op_info(mm_op op, int64_t* rows, int64_t* cols, int* is_complex, mm_prec* prec);
 

@@ -20,6 +20,7 @@ from ._lib import (MM_C64, MM_C128, MM_PREC_BF16, MM_PREC_FP32, MM_PREC_FP64,  #
 
 MM_OPT_SMALL_RUN = 1
 MM_OPT_MONITOR_EVERY = 2
+MM_OP_IDENTITY_SPLIT = 1
 
 PRECISIONS = {"fp64": MM_PREC_FP64, "fp32": MM_PREC_FP32, "bf16x3": MM_PREC_SPLIT_BF16X3,
               "fp16x2": MM_PREC_SPLIT_FP16X2, "bf16": MM_PREC_BF16}
@@ -235,7 +236,9 @@ class Context:
         _check(st, where, self.handle)
 
     # ------------------------------------------------------------ ops ----
-    def mm_op_prepare(self, L: np.ndarray, prec="fp64") -> Op:
+    def mm_op_prepare(self, L: np.ndarray, prec="fp64", identity_split: bool = False) -> Op:
+        """identity_split: prepare L - I and add the input back in each product
+        (MM_OP_IDENTITY_SPLIT; square L)."""
         prec = PRECISIONS[prec] if isinstance(prec, str) else int(prec)
         L = np.asarray(L)
         cplx = np.iscomplexobj(L)
@@ -247,7 +250,8 @@ class Context:
         m.data = F.ctypes.data
         m.on_device = 0
         h = C.c_void_p()
-        self._chk(_lib.lib.mm_op_prepare(self.handle, C.byref(m), prec, C.byref(h)), "mm_op_prepare")
+        self._chk(_lib.lib.mm_op_prepare_ex(self.handle, C.byref(m), prec, MM_OP_IDENTITY_SPLIT if identity_split else 0,
+                                            C.byref(h)), "mm_op_prepare_ex")
         return Op(self, h, F.shape[0], F.shape[1], cplx, prec)
 
     # -------------------------------------------------------- products ----

@@ -30,7 +30,7 @@ EXPORTS = [
     "mm_set_workspace", "mumode_magnus_step", "mm_expm_device",
     "mm_fd2_periodic_order", "mm_fourier_d2", "mm_pipe_flow_operators", "mm_set_option", "mm_monitor_log",
     "mm_schrodinger_fd_hamiltonian", "mm_schrodinger_fd_exponential", "mm_hermite_ho_generator",
-    "gpe_strang_step_noalloc", "mm_nonuniform_neumann_d2",
+    "gpe_strang_step_noalloc", "mm_nonuniform_neumann_d2", "mm_op_prepare_ex", "mm_op_flags",
 ]
 
 
@@ -63,6 +63,8 @@ def _load():
         "mm_version": (C.c_char_p, []),
         "mm_op_prepare": (st, [P, C.POINTER(MMMatrix), C.c_int, C.POINTER(P)]),
         "mm_op_destroy": (st, [P, P]),
+        "mm_op_prepare_ex": (st, [P, C.POINTER(MMMatrix), C.c_int, C.c_uint, C.POINTER(P)]),
+        "mm_op_flags": (st, [P, C.POINTER(C.c_uint)]),
         "mm_op_info": (st, [P, C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_int), C.POINTER(C.c_int)]),
         "mumode_apply": (st, [P, C.POINTER(MMTensor), C.POINTER(MMTensor), P, C.c_int, P]),
         "mumode_expstep": (st, [P, C.POINTER(MMTensor), C.POINTER(P), C.c_int, P]),

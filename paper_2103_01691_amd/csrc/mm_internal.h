@@ -53,7 +53,10 @@ struct ModeArgs {
   uint32_t* smax_out;
   uint32_t* smax_clr;
   int a_exp;
-  int pad_;
+  // identity split: the operator pieces hold L - I (square L) and the
+  // epilogue adds the input entry at the same position back in FP32 (after
+  // the prologue phase when there is one)
+  int idadd;
 };
 
 // Per-workgroup work item of a batched launch.

@@ -757,12 +757,24 @@ __device__ __forceinline__ void mode_tile(const ModeArgs& a, int64_t tile_x, int
           w[r] = v[r];
           if constexpr (F16) w[r] = ldexpf(w[r], o_exp);
         }
+        const int64_t fg = f0 + (int64_t)nf0 * NB + f;
+        if (a.idadd) {
+          // identity part: the input entries at the same position (square
+          // operator: same layout), read by the lane that overwrites them
+          const f32x4v x = *(const f32x4v*)((const st*)a.in + fg * a.Mr + mf * 32 + 4 * b);
+          st y[4] = {x[0], x[1], x[2], x[3]};
+          if constexpr (PRO && CPLX) {
+            phase<st>(y[0], y[1], s_pre);
+            phase<st>(y[2], y[3], s_pre);
+          }
+#pragma unroll
+          for (int r = 0; r < 4; ++r) w[r] += y[r];
+        }
         if constexpr (CPLX && EPI) {
           phase<st>(w[0], w[1], s_post);
           phase<st>(w[2], w[3], s_post);
         }
         if constexpr (F16) vmax = fmaxf(vmax, fmaxf(fmaxf(fabsf(w[0]), fabsf(w[1])), fmaxf(fabsf(w[2]), fabsf(w[3]))));
-        const int64_t fg = f0 + (int64_t)nf0 * NB + f;
         *(f32x4v*)(out + fg * a.Mr + mf * 32 + 4 * b) = f32x4v{w[0], w[1], w[2], w[3]};
       }
     }
@@ -810,6 +822,17 @@ __device__ __forceinline__ void mode_tile(const ModeArgs& a, int64_t tile_x, int
             if constexpr (F16) v4[r] = ldexpf(v4[r], o_exp);
           }
           if constexpr (CPLX) {
+            if (a.idadd) {
+#pragma unroll
+              for (int h = 0; h < 2; ++h) {
+                const int u = (MB == 32) ? mf * 16 + 4 * gq + h : mf * 8 + 4 * h;
+                const st2 x = *(const st2*)((const char*)a.in + (int64_t)u * obytes + voff[j]);
+                st y0 = x[0], y1 = x[1];
+                if constexpr (PRO) phase<st>(y0, y1, s_pre);
+                v4[2 * h] += y0;
+                v4[2 * h + 1] += y1;
+              }
+            }
             if constexpr (EPI) {
               phase<st>(v4[0], v4[1], s_post);
               phase<st>(v4[2], v4[3], s_post);
@@ -825,6 +848,7 @@ __device__ __forceinline__ void mode_tile(const ModeArgs& a, int64_t tile_x, int
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
               const int u = (MB == 32) ? mf * 32 + 8 * gq + r : mf * 16 + 4 * r;
+              if (a.idadd) v4[r] += *(const st*)((const char*)a.in + (int64_t)u * obytes + voff[j]);
               if constexpr (F16) vmax = fmaxf(vmax, fabsf(v4[r]));
               char* sb = (char*)out + (int64_t)u * obytes;
               *(st*)(sb + voff[j]) = v4[r];
@@ -884,6 +908,19 @@ __device__ __forceinline__ void mode_tile(const ModeArgs& a, int64_t tile_x, int
               e0 = mf * 8 + lane / 16;
               e1 = e0 + 4;
             }
+            if (a.idadd) {
+  #pragma unroll
+              for (int h = 0; h < 2; ++h) {
+                const int ie = h ? e1 : e0;
+                if (ie < a.m) {
+                  const st* src = (const st*)a.in + obase + (int64_t)ie * ostride;
+                  st y0 = src[0], y1 = src[1];
+                  if constexpr (PRO) phase<st>(y0, y1, s_pre);
+                  v4[2 * h] += y0;
+                  v4[2 * h + 1] += y1;
+                }
+              }
+            }
             if constexpr (EPI) {
               phase<st>(v4[0], v4[1], s_post);
               phase<st>(v4[2], v4[3], s_post);
@@ -907,6 +944,7 @@ __device__ __forceinline__ void mode_tile(const ModeArgs& a, int64_t tile_x, int
             for (int r = 0; r < 4; ++r) {
               const int ie = (MB == 32) ? mf * 32 + 8 * gq + 4 * (lane / 32) + r : mf * 16 + lane / 16 + 4 * r;
               if (ie < a.m) {
+                if (a.idadd) v4[r] += ((const st*)a.in)[obase + (int64_t)ie * ostride];
                 if constexpr (F16) vmax = fmaxf(vmax, fabsf(v4[r]));
                 out[obase + (int64_t)ie * ostride] = v4[r];
               }

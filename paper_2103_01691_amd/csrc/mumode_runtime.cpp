@@ -33,6 +33,7 @@ struct mm_op_s {
   void* prep = nullptr;          // fragment-order operator (own complexity)
   int KBT = 0, MFT = 0;
   int a_exp = 0;                 // FP16X2: the pieces represent L * 2^-a_exp
+  int idsplit = 0;               // the master and pieces hold L - I; products add the input back
   void* prep_c = nullptr;        // real master promoted to complex (lazily)
   int KBT_c = 0, MFT_c = 0;
   double* dev_master_c = nullptr;
@@ -284,7 +285,7 @@ mm_status run_mode(mm_ctx ctx, const void* in, void* out, const int64_t* dims, i
   a.smax_out = nullptr;
   a.smax_clr = nullptr;
   a.a_exp = L->a_exp;
-  a.pad_ = 0;
+  a.idadd = L->idsplit;
   const bool kcontig = (P == 1) && (a.Kr % 8 == 0);
   const bool fcontig = (P % 4 == 0);
   const bool pair = !kcontig && !cplx && P == 2 && a.Kr % 8 == 0;   // as the planner decides
@@ -705,9 +706,16 @@ mm_status mm_destroy(mm_ctx ctx) {
 }
 
 mm_status mm_op_prepare(mm_ctx ctx, const mm_matrix* M, mm_prec prec, mm_op* out) {
+  return mm_op_prepare_ex(ctx, M, prec, 0u, out);
+}
+
+mm_status mm_op_prepare_ex(mm_ctx ctx, const mm_matrix* M, mm_prec prec, unsigned flags, mm_op* out) {
   if (!ctx) return MM_ERR_ARG;
   if (!M || !out || !M->data) return fail(ctx, MM_ERR_ARG, "NULL matrix or output");
   *out = nullptr;
+  if (flags & ~(unsigned)MM_OP_IDENTITY_SPLIT) return fail(ctx, MM_ERR_ARG, "unknown operator flags 0x%x", flags);
+  const bool idsplit = (flags & MM_OP_IDENTITY_SPLIT) != 0;
+  if (idsplit && M->rows != M->cols) return fail(ctx, MM_ERR_SHAPE, "identity split needs a square operator");
   if (M->dtype != MM_R64 && M->dtype != MM_C128) return fail(ctx, MM_ERR_DTYPE, "master must be MM_R64 or MM_C128");
   if (prec < MM_PREC_FP64 || prec > MM_PREC_BF16) return fail(ctx, MM_ERR_ARG, "bad precision");
   if (M->rows < 1 || M->cols < 1 || M->rows > 4096 || M->cols > 4096)
@@ -729,16 +737,18 @@ mm_status mm_op_prepare(mm_ctx ctx, const mm_matrix* M, mm_prec prec, mm_op* out
     for (int64_t j = 0; j < M->cols; ++j)
       std::memcpy(&host[(size_t)j * M->rows * comps], src + (size_t)j * M->ld * comps, sizeof(double) * M->rows * comps);
   }
-  double amax = 0.0;
-  for (double v : host) {
+  for (double v : host)
     if (!std::isfinite(v)) return fail(ctx, MM_ERR_NONFINITE, "operator holds NaN / Inf");
-    amax = std::max(amax, std::fabs(v));
-  }
+  if (idsplit)   // L - I in FP64: the products carry only the departure from identity
+    for (int64_t i = 0; i < M->rows; ++i) host[((size_t)i * M->rows + i) * comps] -= 1.0;
+  double amax = 0.0;
+  for (double v : host) amax = std::max(amax, std::fabs(v));
   mm_op op = new mm_op_s;
   op->rows = M->rows;
   op->cols = M->cols;
   op->cplx = cplx;
   op->prec = prec;
+  op->idsplit = idsplit ? 1 : 0;
   op->a_exp = prec == MM_PREC_SPLIT_FP16X2 ? mm::fp16x2_op_exp(amax) : 0;
   const int kp = kprec(prec);
   mm::op_blocks(kp, comps * M->rows, comps * M->cols, &op->KBT, &op->MFT);
@@ -754,6 +764,12 @@ mm_status mm_op_prepare(mm_ctx ctx, const mm_matrix* M, mm_prec prec, mm_op* out
                                  op->prep, op->KBT, op->MFT, 0, op->a_exp));
   HIPCHK(ctx, hipDeviceSynchronize());
   *out = op;
+  return MM_OK;
+}
+
+mm_status mm_op_flags(mm_op op, unsigned* flags) {
+  if (!op || !flags) return MM_ERR_ARG;
+  *flags = op->idsplit ? (unsigned)MM_OP_IDENTITY_SPLIT : 0u;
   return MM_OK;
 }
 
@@ -995,6 +1011,8 @@ mm_status ho_strang_step(mm_ctx ctx, mm_tensor* psi, const mm_op* Phi_fwd, const
     const mm_op F = Phi_fwd[k], B = Psi_bwd[k];
     if (!F || !B || !nodes[k]) return fail(ctx, MM_ERR_ARG, "Phi_fwd[%d] / Psi_bwd[%d] / nodes[%d] is NULL", k, k, k);
     if (F->cplx || B->cplx) return fail(ctx, MM_ERR_DTYPE, "Phi_fwd[%d] / Psi_bwd[%d] must be real", k, k);
+    if (F->idsplit || B->idsplit)
+      return fail(ctx, MM_ERR_ARG, "Phi_fwd[%d] / Psi_bwd[%d]: prepared with the identity split", k, k);
     if (F->prec != B->prec) return fail(ctx, MM_ERR_DTYPE, "Phi_fwd[%d] and Psi_bwd[%d] differ in precision", k, k);
     if (F->cols != psi->dims[k] || B->rows != psi->dims[k] || F->rows != B->cols || F->rows > F->cols)
       return fail(ctx, MM_ERR_SHAPE, "mode %d: Phi_fwd must be K x %lld and Psi_bwd %lld x K, K <= %lld", k + 1,
@@ -1228,7 +1246,7 @@ mm_status mumode_expstep_batched(mm_ctx ctx, int count, mm_tensor* const* T, con
         a.smax_out = nullptr;
         a.smax_clr = nullptr;
         a.a_exp = 0;
-        a.pad_ = 0;
+        a.idadd = L->idsplit;
         // one merged launch per (mode, precision); the item's kind selects its tile code
         const uint64_t key = (uint64_t)plan.prec;
         const int kind = plan.cplx * 100 + plan.load * 10 + plan.cls;
