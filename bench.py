@@ -41,6 +41,7 @@ SPLIT_PRODUCTS = {"bf16x3": 6, "fp16x2": 3}        # MFMA products per algorithm
 # on another build of them are not reported
 KERNEL_SOURCES = ["paper_2103_01691_amd/csrc/mode_tile.h", "paper_2103_01691_amd/csrc/mm_internal.h",
                   "paper_2103_01691_amd/csrc/kern_bf16x3.hip", "paper_2103_01691_amd/csrc/kern_fp16x2.hip",
+                  "paper_2103_01691_amd/csrc/kern_bf16x3_ida.hip", "paper_2103_01691_amd/csrc/kern_fp16x2_ida.hip",
                   "paper_2103_01691_amd/csrc/kernels_common.hip", "paper_2103_01691_amd/build.py"]
 
 
@@ -142,17 +143,37 @@ def timed(torch, fn, reps):
     return ev0.elapsed_time(ev1) * 1e-3
 
 
-def other_workloads(ctx, mm, torch):
+WORKLOADS = ("batch512", "ho128", "free256", "hkmp", "heat64")
+
+
+def other_workloads(ctx, mm, torch, only=WORKLOADS):
     """Throughput of the other scope workloads (their parity is tested in
-    tests/); not the headline metric."""
+    tests/); not the headline metric.  `only`: the subset to run (a profiler
+    run of one workload)."""
+    import synth
+    out = {}
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(5)
+    if "batch512" in only:
+        out.update(_batch_workload(ctx, mm, torch, gen))
+    if "ho128" in only:
+        out.update(_ho_workload(ctx, mm, torch, gen))
+    if "free256" in only:
+        out.update(_free_workload(ctx, mm, torch))
+    if "hkmp" in only:
+        out.update(_hkmp_workload(ctx, mm, torch, gen))
+    if "heat64" in only:
+        out.update(_heat_workload(ctx, mm, torch, gen))
+    return out
+
+
+def _batch_workload(ctx, mm, torch, gen):
     import synth
     out = {}
     # batched: 512 instances of the mixed heat / Schroedinger workload, one
     # exponential step each, FP32, one captured graph per step; operators
     # shared per (kind, n) at tau = 1e-3 (the step's cost does not depend on tau)
     mix = synth.batch_mix(512, cfg_id=5)
-    gen = torch.Generator(device="cuda")
-    gen.manual_seed(5)
     cache, tensors, ops = {}, [], []
     ideal = 0.0
     for inst in mix:
@@ -198,6 +219,14 @@ def other_workloads(ctx, mm, torch):
                             "roofline": "sum over instances of max(flops / FP32 MFMA peak, bytes / HBM peak)"}
     ctx.mm_tune_clear()
     del tensors
+    for o in cache.values():
+        o.destroy()
+    torch.cuda.empty_cache()
+    return out
+
+
+def _ho_workload(ctx, mm, torch, gen):
+    out = {}
     # harmonic oscillator, Hermite n = 128, complex64, time-dependent potential
     m = 128
     Xl, _ = mm.hermite_nodes(m)
@@ -224,6 +253,12 @@ def other_workloads(ctx, mm, torch):
         for o in (Lh, F, B):
             o.destroy()
         del psi, spec
+    return out
+
+
+def _free_workload(ctx, mm, torch):
+    import synth
+    out = {}
     # free Schroedinger, d = 3, n = 256 on [-10, 10]^3, tau = 0.01: exact in
     # time, one expstep (three mode products) per step, 100 steps per call
     x0 = synth.wavepacket_initial(256, -10.0, 10.0, 3)
@@ -242,6 +277,11 @@ def other_workloads(ctx, mm, torch):
         del psi
     out["free_schroedinger256_100steps"] = fs
     torch.cuda.empty_cache()
+    return out
+
+
+def _hkmp_workload(ctx, mm, torch, gen):
+    out = {}
     # time-dependent Schroedinger problem of Section 4.4 in nodal Hermite
     # space, exponential midpoint rule: the mode-3 exponential is formed on
     # the device every step ("exp (int)"), then the three mode products
@@ -267,6 +307,11 @@ def other_workloads(ctx, mm, torch):
                                  "n127_single": {"exp_int": 0.25, "mu_mode": 0.54},
                                  "n255_single": {"exp_int": 0.34, "mu_mode": 7.01},
                                  "source": "the paper's table for this problem (V100), context only"}
+    return out
+
+
+def _heat_workload(ctx, mm, torch, gen):
+    out = {}
     # heat, d = 2, n = 64, FP64, 20 steps per call (launch-latency bound)
     E = mm.expm(mm.fd2_matrix(64, 0.0, 1.0), 1e-3).real.copy()
     Eop = ctx.mm_op_prepare(E, "fp64")
@@ -280,8 +325,6 @@ def other_workloads(ctx, mm, torch):
     out["heat64x64_fp64_20steps"] = {"calls_per_s": K / t, "us_per_step": 1e6 * t / (20 * K),
                                      "us_per_step_one_launch_per_product": 1e6 * t_per / (20 * K),
                                      "note": "default: all 20 steps in one single-workgroup launch"}
-    for o in cache.values():
-        o.destroy()
     Eop.destroy()
     torch.cuda.empty_cache()
     return out
@@ -311,6 +354,8 @@ def main():
     ap.add_argument("--tune-file", default=None,
                     help="timed path: load the tile choice from this file if it exists, else tune and save it")
     ap.add_argument("--no-workloads", action="store_true", help="skip the batched / HO / heat side measurements")
+    ap.add_argument("--only-workload", choices=WORKLOADS, default=None,
+                    help="profiling aid: run only this side workload, print its figures and exit")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="after timing, run one plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -323,6 +368,13 @@ def main():
 
     import paper_2103_01691_amd as mm
     import synth
+
+    if args.only_workload:
+        ctx = mm.Context(0)
+        log(f"side workload {args.only_workload} alone")
+        print(json.dumps(other_workloads(ctx, mm, torch, (args.only_workload,))), flush=True)
+        ctx.close()
+        return
 
     log("building operator (host FP64 expm)")
     E = build_operator(mm)

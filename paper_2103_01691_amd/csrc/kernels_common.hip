@@ -280,23 +280,23 @@ __global__ void hermite_collapse_kernel(const double* __restrict__ Phi, const do
 
 // ---------------------------------------------------------- host side -----
 
-KernFn pick_kernel_any(int prec, int cplx, int ld, int pro, int epi, int cls, int full = 0) {
+KernFn pick_kernel_any(int prec, int cplx, int ld, int pro, int epi, int cls, int full = 0, int ida = 0) {
   switch (prec) {
-    case KP_F64: return pick_kernel_f64(cplx, ld, pro, epi, cls, full);
-    case KP_F32: return pick_kernel_f32(cplx, ld, pro, epi, cls, full);
-    case KP_BF16X3: return pick_kernel_bf16x3(cplx, ld, pro, epi, cls, full);
-    case KP_FP16X2: return pick_kernel_fp16x2(cplx, ld, pro, epi, cls, full);
-    default: return pick_kernel_bf16(cplx, ld, pro, epi, cls, full);
+    case KP_F64: return pick_kernel_f64(cplx, ld, pro, epi, cls, full, ida);
+    case KP_F32: return pick_kernel_f32(cplx, ld, pro, epi, cls, full, ida);
+    case KP_BF16X3: return pick_kernel_bf16x3(cplx, ld, pro, epi, cls, full, ida);
+    case KP_FP16X2: return pick_kernel_fp16x2(cplx, ld, pro, epi, cls, full, ida);
+    default: return pick_kernel_bf16(cplx, ld, pro, epi, cls, full, ida);
   }
 }
 
-BatchFn pick_batch_any(int prec, int cplx, int ld, int cls) {
+bool batch_kind_any(int prec, int cplx, int ld, int cls) {
   switch (prec) {
-    case KP_F64: return pick_batch_f64(cplx, ld, cls);
-    case KP_F32: return pick_batch_f32(cplx, ld, cls);
-    case KP_BF16X3: return pick_batch_bf16x3(cplx, ld, cls);
-    case KP_FP16X2: return pick_batch_fp16x2(cplx, ld, cls);
-    default: return pick_batch_bf16(cplx, ld, cls);
+    case KP_F64: return batch_kind_f64(cplx, ld, cls);
+    case KP_F32: return batch_kind_f32(cplx, ld, cls);
+    case KP_BF16X3: return batch_kind_bf16x3(cplx, ld, cls);
+    case KP_FP16X2: return batch_kind_fp16x2(cplx, ld, cls);
+    default: return batch_kind_bf16(cplx, ld, cls);
   }
 }
 
@@ -356,7 +356,7 @@ bool plan_mode(const ModeArgs& a, int prec, int cplx, bool want_pro, bool want_e
   const bool split = prec == KP_BF16X3 || prec == KP_FP16X2;
   TileShape tf;
   if (force_cls >= 0 && tile_shape(prec, force_cls, &tf) &&
-      (batch ? pick_batch_any(prec, cplx, load, force_cls) != nullptr
+      (batch ? batch_kind_any(prec, cplx, load, force_cls)
              : pick_kernel_any(prec, cplx, load, pro, epi, force_cls) != nullptr)) {
     cls = force_cls;
   } else if (!batch && split && cplx && load != KL_GENERIC && a.Mr > 2 * rw) {
@@ -387,12 +387,12 @@ bool plan_mode(const ModeArgs& a, int prec, int cplx, bool want_pro, bool want_e
                      ? 1
                      : 0;
   }
-  if (batch) return plan->grid_x > 0 && pick_batch_any(prec, cplx, load, cls) != nullptr;
+  if (batch) return plan->grid_x > 0 && batch_kind_any(prec, cplx, load, cls);
   return plan->grid_x > 0 && pick_kernel_any(prec, cplx, load, pro, epi, cls) != nullptr;
 }
 
 hipError_t launch_mode(const ModePlan& p, const ModeArgs& a, hipStream_t s, hipEvent_t start, hipEvent_t stop) {
-  KernFn fn = pick_kernel_any(p.prec, p.cplx, p.load, p.pro, p.epi, p.cls, p.full);
+  KernFn fn = pick_kernel_any(p.prec, p.cplx, p.load, p.pro, p.epi, p.cls, p.full, a.idadd ? 1 : 0);
   if (!fn) return hipErrorInvalidDeviceFunction;
   dim3 grid(p.grid_x, p.grid_y, 1);
   if (start || stop) {
@@ -405,21 +405,13 @@ hipError_t launch_mode(const ModePlan& p, const ModeArgs& a, hipStream_t s, hipE
   return hipGetLastError();
 }
 
-hipError_t launch_mode_batch(const ModePlan& p, const BatchItem* items, int count, hipStream_t s) {
-  BatchFn fn = pick_batch_any(p.prec, p.cplx, p.load, p.cls);
-  if (!fn) return hipErrorInvalidDeviceFunction;
-  if (count <= 0) return hipSuccess;
-  hipLaunchKernelGGL(fn, dim3(count), dim3(p.threads), 0, s, items);
-  return hipGetLastError();
-}
-
-hipError_t launch_mode_batch_merged(int prec, const BatchItem* items, int count, hipStream_t s) {
+hipError_t launch_mode_batch_merged(int prec, int ida, const BatchItem* items, int count, hipStream_t s) {
   BatchFn fn = nullptr;
   switch (prec) {
-    case KP_F64: fn = pick_batch_merged_f64(); break;
-    case KP_F32: fn = pick_batch_merged_f32(); break;
-    case KP_BF16X3: fn = pick_batch_merged_bf16x3(); break;
-    case KP_BF16: fn = pick_batch_merged_bf16(); break;
+    case KP_F64: fn = ida ? pick_batch_merged_f64_ida() : pick_batch_merged_f64(); break;
+    case KP_F32: fn = ida ? pick_batch_merged_f32_ida() : pick_batch_merged_f32(); break;
+    case KP_BF16X3: fn = ida ? pick_batch_merged_bf16x3_ida() : pick_batch_merged_bf16x3(); break;
+    case KP_BF16: fn = ida ? pick_batch_merged_bf16_ida() : pick_batch_merged_bf16(); break;
     default: return hipErrorInvalidDeviceFunction;
   }
   if (count <= 0) return hipSuccess;

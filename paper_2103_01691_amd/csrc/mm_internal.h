@@ -79,16 +79,16 @@ struct TileShape {
 // Kernel tables, one per precision (kern_<prec>.hip).  cls selects the tile
 // shape (0 default; 1, 2 regrouped waves for operators with at most 256 / 128
 // real rows; 3..6 alternative split shapes).  nullptr if no instance exists.
-KernFn pick_kernel_f64(int cplx, int ld, int pro, int epi, int cls, int full);
-KernFn pick_kernel_f32(int cplx, int ld, int pro, int epi, int cls, int full);
-KernFn pick_kernel_bf16x3(int cplx, int ld, int pro, int epi, int cls, int full);
-KernFn pick_kernel_fp16x2(int cplx, int ld, int pro, int epi, int cls, int full);
-KernFn pick_kernel_bf16(int cplx, int ld, int pro, int epi, int cls, int full);
-BatchFn pick_batch_f64(int cplx, int ld, int cls);
-BatchFn pick_batch_f32(int cplx, int ld, int cls);
-BatchFn pick_batch_bf16x3(int cplx, int ld, int cls);
-BatchFn pick_batch_fp16x2(int cplx, int ld, int cls);
-BatchFn pick_batch_bf16(int cplx, int ld, int cls);
+KernFn pick_kernel_f64(int cplx, int ld, int pro, int epi, int cls, int full, int ida);
+KernFn pick_kernel_f32(int cplx, int ld, int pro, int epi, int cls, int full, int ida);
+KernFn pick_kernel_bf16x3(int cplx, int ld, int pro, int epi, int cls, int full, int ida);
+KernFn pick_kernel_fp16x2(int cplx, int ld, int pro, int epi, int cls, int full, int ida);
+KernFn pick_kernel_bf16(int cplx, int ld, int pro, int epi, int cls, int full, int ida);
+bool batch_kind_f64(int cplx, int ld, int cls);
+bool batch_kind_f32(int cplx, int ld, int cls);
+bool batch_kind_bf16x3(int cplx, int ld, int cls);
+bool batch_kind_fp16x2(int cplx, int ld, int cls);
+bool batch_kind_bf16(int cplx, int ld, int cls);
 bool tile_shape_f64(int cls, TileShape* out);
 bool tile_shape_f32(int cls, TileShape* out);
 bool tile_shape_bf16x3(int cls, TileShape* out);
@@ -104,7 +104,12 @@ BatchFn pick_batch_merged_f64();
 BatchFn pick_batch_merged_f32();
 BatchFn pick_batch_merged_bf16x3();
 BatchFn pick_batch_merged_bf16();
-hipError_t launch_mode_batch_merged(int prec, const BatchItem* items, int count, hipStream_t s);
+BatchFn pick_batch_merged_f64_ida();
+BatchFn pick_batch_merged_f32_ida();
+BatchFn pick_batch_merged_bf16x3_ida();
+BatchFn pick_batch_merged_bf16_ida();
+// ida: the items' operators carry the identity split (a.idadd set on all)
+hipError_t launch_mode_batch_merged(int prec, int ida, const BatchItem* items, int count, hipStream_t s);
 
 // Per-launch plan chosen by the runtime.
 struct ModePlan {
@@ -128,9 +133,6 @@ int num_classes(int prec);
 // start / stop (optional): events recorded by the launch itself
 hipError_t launch_mode(const ModePlan& plan, const ModeArgs& a, hipStream_t s, hipEvent_t start = nullptr,
                        hipEvent_t stop = nullptr);
-// Batched launch: `count` work items (device array) that all use `plan`'s
-// kernel (same precision, complexity, load path and tile class).
-hipError_t launch_mode_batch(const ModePlan& plan, const BatchItem* items, int count, hipStream_t s);
 // Whole-run kernel for small states (kern_small.hip): one workgroup, every
 // step and mode of an expstep.  m[k].A == nullptr skips mode k; every mode
 // must be planned with tile class SMALL_RUN_CLASS covering all its rows, with

@@ -256,7 +256,7 @@ __device__ __forceinline__ int64_t fibre_base(int64_t f, int64_t P, int n, int c
 // row block tile_y.  WM x WN waves: wave (wm, wn) owns M-fragments
 // [(tile_y*WM + wm)*WMF, +WMF) and N-fragments [wn*WNF, +WNF) of the tile.
 template <int PR, bool CPLX, int LD, int WMF, int WNF, int WM, int WN, int KCH, bool PRO, bool EPI, int OCC,
-          bool FULL = false>
+          bool FULL = false, bool IDA = false>
 __device__ __forceinline__ void mode_tile(const ModeArgs& a, int64_t tile_x, int tile_y,
                                           typename Tr<PR>::pc* __restrict__ lds) {
   typedef Tr<PR> T;
@@ -758,7 +758,7 @@ __device__ __forceinline__ void mode_tile(const ModeArgs& a, int64_t tile_x, int
           if constexpr (F16) w[r] = ldexpf(w[r], o_exp);
         }
         const int64_t fg = f0 + (int64_t)nf0 * NB + f;
-        if (a.idadd) {
+        if constexpr (IDA) {
           // identity part: the input entries at the same position (square
           // operator: same layout), read by the lane that overwrites them
           const f32x4v x = *(const f32x4v*)((const st*)a.in + fg * a.Mr + mf * 32 + 4 * b);
@@ -822,7 +822,7 @@ __device__ __forceinline__ void mode_tile(const ModeArgs& a, int64_t tile_x, int
             if constexpr (F16) v4[r] = ldexpf(v4[r], o_exp);
           }
           if constexpr (CPLX) {
-            if (a.idadd) {
+            if constexpr (IDA) {
 #pragma unroll
               for (int h = 0; h < 2; ++h) {
                 const int u = (MB == 32) ? mf * 16 + 4 * gq + h : mf * 8 + 4 * h;
@@ -848,7 +848,7 @@ __device__ __forceinline__ void mode_tile(const ModeArgs& a, int64_t tile_x, int
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
               const int u = (MB == 32) ? mf * 32 + 8 * gq + r : mf * 16 + 4 * r;
-              if (a.idadd) v4[r] += *(const st*)((const char*)a.in + (int64_t)u * obytes + voff[j]);
+              if constexpr (IDA) v4[r] += *(const st*)((const char*)a.in + (int64_t)u * obytes + voff[j]);
               if constexpr (F16) vmax = fmaxf(vmax, fabsf(v4[r]));
               char* sb = (char*)out + (int64_t)u * obytes;
               *(st*)(sb + voff[j]) = v4[r];
@@ -908,7 +908,7 @@ __device__ __forceinline__ void mode_tile(const ModeArgs& a, int64_t tile_x, int
               e0 = mf * 8 + lane / 16;
               e1 = e0 + 4;
             }
-            if (a.idadd) {
+            if constexpr (IDA) {
   #pragma unroll
               for (int h = 0; h < 2; ++h) {
                 const int ie = h ? e1 : e0;
@@ -944,7 +944,7 @@ __device__ __forceinline__ void mode_tile(const ModeArgs& a, int64_t tile_x, int
             for (int r = 0; r < 4; ++r) {
               const int ie = (MB == 32) ? mf * 32 + 8 * gq + 4 * (lane / 32) + r : mf * 16 + lane / 16 + 4 * r;
               if (ie < a.m) {
-                if (a.idadd) v4[r] += ((const st*)a.in)[obase + (int64_t)ie * ostride];
+                if constexpr (IDA) v4[r] += ((const st*)a.in)[obase + (int64_t)ie * ostride];
                 if constexpr (F16) vmax = fmaxf(vmax, fabsf(v4[r]));
                 out[obase + (int64_t)ie * ostride] = v4[r];
               }
@@ -979,23 +979,13 @@ __device__ __forceinline__ void mode_tile(const ModeArgs& a, int64_t tile_x, int
 }
 
 template <int PR, bool CPLX, int LD, int WMF, int WNF, int WM, int WN, int KCH, bool PRO, bool EPI, int OCC,
-          bool FULL>
+          bool FULL, bool IDA>
 __global__ __launch_bounds__(64 * WM * WN) __attribute__((amdgpu_waves_per_eu(OCC, OCC)))
 void mode_kernel(ModeArgs a) {
   typedef typename Tr<PR>::pc pc;
   constexpr int CHUNK = KCH * WN * WNF * Tr<PR>::NPB * 64 * Tr<PR>::KPL;
   __shared__ __attribute__((aligned(16))) pc lds[2 * CHUNK];
-  mode_tile<PR, CPLX, LD, WMF, WNF, WM, WN, KCH, PRO, EPI, OCC, FULL>(a, blockIdx.x, blockIdx.y, lds);
-}
-
-template <int PR, bool CPLX, int LD, int WMF, int WNF, int WM, int WN, int KCH>
-__global__ __launch_bounds__(64 * WM * WN) void mode_batch_kernel(const BatchItem* __restrict__ items) {
-  typedef typename Tr<PR>::pc pc;
-  constexpr int CHUNK = KCH * WN * WNF * Tr<PR>::NPB * 64 * Tr<PR>::KPL;
-  __shared__ __attribute__((aligned(16))) pc lds[2 * CHUNK];
-  const BatchItem& it = items[blockIdx.x];
-  const ModeArgs a = it.a;
-  mode_tile<PR, CPLX, LD, WMF, WNF, WM, WN, KCH, false, false, 1>(a, it.tile_x, it.tile_y, lds);
+  mode_tile<PR, CPLX, LD, WMF, WNF, WM, WN, KCH, PRO, EPI, OCC, FULL, IDA>(a, blockIdx.x, blockIdx.y, lds);
 }
 
 // ------------------------------------------------------------ configs -----
@@ -1040,22 +1030,16 @@ template <int PR, int CLS> TileShape shape_of() {
   return TileShape{C::WMF, C::WNF, C::WM, C::WN, C::KCH, C::OCC};
 }
 
-template <int PR, bool CPLX, int LD, bool PRO, bool EPI, int CLS, bool FULL = false>
+template <int PR, bool CPLX, int LD, bool PRO, bool EPI, int CLS, bool FULL = false, bool IDA = false>
 KernFn kfn() {
   typedef Cfg<PR, CLS> C;
-  return &mode_kernel<PR, CPLX, LD, C::WMF, C::WNF, C::WM, C::WN, C::KCH, PRO, EPI, C::OCC, FULL>;
+  return &mode_kernel<PR, CPLX, LD, C::WMF, C::WNF, C::WM, C::WN, C::KCH, PRO, EPI, C::OCC, FULL, IDA>;
 }
 
 // Full-tile variant when the planner allows it.
-template <int PR, bool CPLX, int LD, bool PRO, bool EPI, int CLS>
+template <int PR, bool CPLX, int LD, bool PRO, bool EPI, int CLS, bool IDA>
 KernFn kfx(int full) {
-  return full ? kfn<PR, CPLX, LD, PRO, EPI, CLS, true>() : kfn<PR, CPLX, LD, PRO, EPI, CLS, false>();
-}
-
-template <int PR, bool CPLX, int LD, int CLS>
-BatchFn bfn() {
-  typedef Cfg<PR, CLS> C;
-  return &mode_batch_kernel<PR, CPLX, LD, C::WMF, C::WNF, C::WM, C::WN, C::KCH>;
+  return full ? kfn<PR, CPLX, LD, PRO, EPI, CLS, true, IDA>() : kfn<PR, CPLX, LD, PRO, EPI, CLS, false, IDA>();
 }
 
 // Kernel table of one precision.  Instances that exist: every (complex,
@@ -1064,33 +1048,35 @@ BatchFn bfn() {
 // contiguous or strided fibres.  Classes 0 and >= 3 also have a full-tile
 // variant (full != 0: no per-store bounds checks, 32-bit output offsets) for
 // contiguous and strided fibres.
-template <int PR>
+// IDA: the instances with the identity add (a separate compile unit per
+// precision and IDA keeps the builds parallel).
+template <int PR, bool IDA>
 KernFn pick_kernel(int cplx, int ld, int pro, int epi, int cls, int full) {
   if (ld == KL_PAIR) {
     // real operator on paired fibres: classes 0..2, no phases
     if (cplx || pro || epi) return nullptr;
     switch (cls) {
-      case 0: return kfx<PR, false, KL_PAIR, false, false, 0>(full);
-      case 1: return kfn<PR, false, KL_PAIR, false, false, 1>();
-      case 2: return kfn<PR, false, KL_PAIR, false, false, 2>();
+      case 0: return kfx<PR, false, KL_PAIR, false, false, 0, IDA>(full);
+      case 1: return kfn<PR, false, KL_PAIR, false, false, 1, false, IDA>();
+      case 2: return kfn<PR, false, KL_PAIR, false, false, 2, false, IDA>();
       default: return nullptr;
     }
   }
 #define MM_PH(C_, L_, K_)                                                     \
   do {                                                                        \
-    if (pro && epi) return kfx<PR, C_, L_, true, true, K_>(full);            \
-    if (pro) return kfx<PR, C_, L_, true, false, K_>(full);                  \
-    if (epi) return kfx<PR, C_, L_, false, true, K_>(full);                  \
-    return kfx<PR, C_, L_, false, false, K_>(full);                          \
+    if (pro && epi) return kfx<PR, C_, L_, true, true, K_, IDA>(full);       \
+    if (pro) return kfx<PR, C_, L_, true, false, K_, IDA>(full);             \
+    if (epi) return kfx<PR, C_, L_, false, true, K_, IDA>(full);             \
+    return kfx<PR, C_, L_, false, false, K_, IDA>(full);                     \
   } while (0)
   if (cls == 1 || cls == 2) {
     if (pro || epi || ld == KL_GENERIC) return nullptr;
     if (cls == 1) {
-      if (cplx) return ld == KL_KCONTIG ? kfn<PR, true, KL_KCONTIG, false, false, 1>() : kfn<PR, true, KL_FCONTIG, false, false, 1>();
-      return ld == KL_KCONTIG ? kfn<PR, false, KL_KCONTIG, false, false, 1>() : kfn<PR, false, KL_FCONTIG, false, false, 1>();
+      if (cplx) return ld == KL_KCONTIG ? kfn<PR, true, KL_KCONTIG, false, false, 1, false, IDA>() : kfn<PR, true, KL_FCONTIG, false, false, 1, false, IDA>();
+      return ld == KL_KCONTIG ? kfn<PR, false, KL_KCONTIG, false, false, 1, false, IDA>() : kfn<PR, false, KL_FCONTIG, false, false, 1, false, IDA>();
     }
-    if (cplx) return ld == KL_KCONTIG ? kfn<PR, true, KL_KCONTIG, false, false, 2>() : kfn<PR, true, KL_FCONTIG, false, false, 2>();
-    return ld == KL_KCONTIG ? kfn<PR, false, KL_KCONTIG, false, false, 2>() : kfn<PR, false, KL_FCONTIG, false, false, 2>();
+    if (cplx) return ld == KL_KCONTIG ? kfn<PR, true, KL_KCONTIG, false, false, 2, false, IDA>() : kfn<PR, true, KL_FCONTIG, false, false, 2, false, IDA>();
+    return ld == KL_KCONTIG ? kfn<PR, false, KL_KCONTIG, false, false, 2, false, IDA>() : kfn<PR, false, KL_FCONTIG, false, false, 2, false, IDA>();
   }
   if constexpr (NumCls<PR>::N > 3) {
     if (cls >= 3) {
@@ -1112,29 +1098,21 @@ KernFn pick_kernel(int cplx, int ld, int pro, int epi, int cls, int full) {
     }
   }
   switch (ld) {
-    case KL_KCONTIG: return kfx<PR, false, KL_KCONTIG, false, false, 0>(full);
-    case KL_FCONTIG: return kfx<PR, false, KL_FCONTIG, false, false, 0>(full);
-    default: return kfn<PR, false, KL_GENERIC, false, false, 0>();
+    case KL_KCONTIG: return kfx<PR, false, KL_KCONTIG, false, false, 0, IDA>(full);
+    case KL_FCONTIG: return kfx<PR, false, KL_FCONTIG, false, false, 0, IDA>(full);
+    default: return kfn<PR, false, KL_GENERIC, false, false, 0, false, IDA>();
   }
 #undef MM_PH
 }
 
+// Whether the merged batched kernel of a precision has the tile code of a
+// work item kind (FP16X2 needs a state bound per instance: no batched
+// kernels).
 template <int PR>
-BatchFn pick_batch(int cplx, int ld, int cls) {
-  // FP16X2 needs a state bound per instance: no batched instances
-  if constexpr (PR == KP_FP16X2) return nullptr;
-  if (ld == KL_GENERIC || ld == KL_PAIR || cls > 2) return nullptr;
-#define MM_B(K_)                                                                      \
-  do {                                                                                \
-    if (cplx) return ld == KL_KCONTIG ? bfn<PR, true, KL_KCONTIG, K_>() : bfn<PR, true, KL_FCONTIG, K_>(); \
-    return ld == KL_KCONTIG ? bfn<PR, false, KL_KCONTIG, K_>() : bfn<PR, false, KL_FCONTIG, K_>();       \
-  } while (0)
-  switch (cls) {
-    case 0: MM_B(0);
-    case 1: MM_B(1);
-    default: MM_B(2);
-  }
-#undef MM_B
+bool batch_kind(int cplx, int ld, int cls) {
+  (void)cplx;
+  if constexpr (PR == KP_FP16X2) return false;
+  return (ld == KL_KCONTIG || ld == KL_FCONTIG) && cls >= 0 && cls <= 2;
 }
 
 template <int PR>
@@ -1172,7 +1150,7 @@ constexpr int merged_lds_scalars() {
   return a > b ? (a > c ? a : c) : (b > c ? b : c);
 }
 
-template <int PR>
+template <int PR, bool IDA>
 __global__ __launch_bounds__(256) void mode_batch_merged_kernel(const BatchItem* __restrict__ items) {
   typedef typename Tr<PR>::pc pc;
   __shared__ __attribute__((aligned(16))) pc lds[merged_lds_scalars<PR>()];
@@ -1182,7 +1160,7 @@ __global__ __launch_bounds__(256) void mode_batch_merged_kernel(const BatchItem*
   case (C_ ? 100 : 0) + L_ * 10 + K_: {                                                                    \
     typedef Cfg<PR, K_> CF;                                                                                \
     static_assert(CF::WM * CF::WN == 4, "merged batch classes use 4 waves");                               \
-    mode_tile<PR, C_, L_, CF::WMF, CF::WNF, CF::WM, CF::WN, CF::KCH, false, false, 1>(a, it.tile_x, it.tile_y, lds); \
+    mode_tile<PR, C_, L_, CF::WMF, CF::WNF, CF::WM, CF::WN, CF::KCH, false, false, 1, false, IDA>(a, it.tile_x, it.tile_y, lds); \
     break;                                                                                                 \
   }
   switch (it.kind) {
@@ -1203,9 +1181,11 @@ __global__ __launch_bounds__(256) void mode_batch_merged_kernel(const BatchItem*
 #undef MM_MK
 }
 
-template <int PR>
+// IDA: work items whose operators carry the identity split (a launch of
+// their own, so the plain merged kernel keeps its register allocation).
+template <int PR, bool IDA>
 BatchFn pick_batch_merged() {
-  return &mode_batch_merged_kernel<PR>;
+  return &mode_batch_merged_kernel<PR, IDA>;
 }
 
 }  // namespace mm

@@ -100,7 +100,7 @@ struct mm_ctx_s {
   std::vector<double> x2_nodes[MM_MAXD];   // nodes of the last upload, per mode
   // batched integrator: work items of the last batch signature, its
   // launch groups and the captured per-step graph
-  struct BatchGroup { mm::ModePlan plan; int offset, count; };
+  struct BatchGroup { mm::ModePlan plan; int ida, offset, count; };
   mm::BatchItem* bitems = nullptr;
   size_t bitems_cap = 0;
   std::vector<BatchGroup> bgroups;
@@ -557,6 +557,7 @@ mm_status small_expstep(mm_ctx ctx, mm_tensor* T, const mm_op* E, int nsteps, hi
     const int p = kprec(E[k]->prec);
     if ((p != mm::KP_F64 && p != mm::KP_F32) || (kp >= 0 && p != kp)) return MM_OK;
     if (cplx && !E[k]->cplx) return MM_OK;   // real operator on complex planes: one launch per product
+    if (E[k]->idsplit) return MM_OK;         // identity split: one launch per product
     kp = p;
     mm::ModePlan plan;
     mm::ModeArgs a;
@@ -1247,8 +1248,9 @@ mm_status mumode_expstep_batched(mm_ctx ctx, int count, mm_tensor* const* T, con
         a.smax_clr = nullptr;
         a.a_exp = 0;
         a.idadd = L->idsplit;
-        // one merged launch per (mode, precision); the item's kind selects its tile code
-        const uint64_t key = (uint64_t)plan.prec;
+        // one merged launch per (mode, precision, identity split); the item's
+        // kind selects its tile code
+        const uint64_t key = (uint64_t)plan.prec * 2 + (L->idsplit ? 1 : 0);
         const int kind = plan.cplx * 100 + plan.load * 10 + plan.cls;
         size_t g = 0;
         while (g < byk.size() && byk[g].first != key) ++g;
@@ -1266,7 +1268,7 @@ mm_status mumode_expstep_batched(mm_ctx ctx, int count, mm_tensor* const* T, con
                          [](const mm::BatchItem& x, const mm::BatchItem& y) {
                            return (int64_t)x.a.Kr * x.a.Mr > (int64_t)y.a.Kr * y.a.Mr;
                          });
-        groups.push_back({plans[g], (int)items.size(), (int)byk[g].second.size()});
+        groups.push_back({plans[g], (int)(byk[g].first & 1), (int)items.size(), (int)byk[g].second.size()});
         items.insert(items.end(), byk[g].second.begin(), byk[g].second.end());
       }
     }
@@ -1298,7 +1300,7 @@ mm_status mumode_expstep_batched(mm_ctx ctx, int count, mm_tensor* const* T, con
     HIPCHK(ctx, hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal));
     hipError_t le = hipSuccess;
     for (const auto& g : ctx->bgroups) {
-      le = mm::launch_mode_batch_merged(g.plan.prec, ctx->bitems + g.offset, g.count, ctx->cap_stream);
+      le = mm::launch_mode_batch_merged(g.plan.prec, g.ida, ctx->bitems + g.offset, g.count, ctx->cap_stream);
       if (le != hipSuccess) break;
     }
     hipGraph_t graph = nullptr;
