@@ -304,6 +304,23 @@ mm_status mm_norm2(mm_ctx ctx, const mm_tensor* T, double cell, double* host_out
  * along the modes of an expstep, a Strang step or a batch all have the shape
  * tuned here when called with the same T and E. */
 mm_status mm_autotune(mm_ctx ctx, const mm_tensor* T, const mm_op* E, int budget_ms, mm_stream stream);
+/* Autotuner of the batched step (mumode_expstep_batched with the same
+ * count, T and E): for each mode and each of real / complex instances, the
+ * tile class of that group's products in the merged launches (0..2, or the
+ * planner's own choice) is chosen by timing whole batched steps, one group
+ * at a time with the others held (coordinate descent).  Tiles that are
+ * fastest for an instance alone need not be fastest inside the merged
+ * launch, where every instance's tiles share the GPU, so the choice is made
+ * on the batch itself.  Runs the step in place on T several times (the
+ * tensors' contents afterwards are those of an unspecified number of
+ * steps).  The choice is kept by the context for later batched steps and
+ * cleared by mm_tune_clear.  budget_ms bounds the timed replays per
+ * candidate (at least two).  Synchronises `stream`. */
+mm_status mm_autotune_batched(mm_ctx ctx, int count, mm_tensor* const* T, const mm_op* const* E, int budget_ms,
+                              mm_stream stream);
+/* The class chosen for mode `mode` (1-based) of real (is_complex = 0) or
+ * complex instances; -1 when the planner's choice is kept. */
+mm_status mm_autotune_batched_get(mm_ctx ctx, int mode, int is_complex, int* cls);
 /* Number of recorded tune entries, and entry `index` (0-based):
  * key6 = {precision, complex, load path (0 contiguous fibres, 1 strided,
  * 2 gather), real rows, real columns, fibres}, the tile class and its time in

@@ -383,6 +383,26 @@ class Context:
         self._chk(_lib.lib.mm_autotune(self.handle, C.byref(t), _op_array(E), int(budget_ms), _stream(stream)),
                   "mm_autotune")
 
+    def mm_autotune_batched(self, tensors, ops, budget_ms: int = 200, stream=None):
+        """Choose the batched step's tile class per (mode, real / complex) by
+        timing the batch itself (runs steps in place on the tensors)."""
+        n = len(tensors)
+        mts = [as_mm_tensor(t) for t in tensors]
+        tarr = (C.POINTER(_lib.MMTensor) * n)(*[C.pointer(m) for m in mts])
+        oarrs = [_op_array(o) for o in ops]
+        earr = (C.POINTER(C.c_void_p) * n)(*[C.cast(o, C.POINTER(C.c_void_p)) for o in oarrs])
+        self._chk(_lib.lib.mm_autotune_batched(self.handle, n, tarr, earr, int(budget_ms), _stream(stream)),
+                  "mm_autotune_batched")
+        out = {}
+        for mode in range(1, _lib.MM_MAXD + 1):
+            for cplx in (0, 1):
+                c = C.c_int()
+                self._chk(_lib.lib.mm_autotune_batched_get(self.handle, mode, cplx, C.byref(c)),
+                          "mm_autotune_batched_get")
+                if c.value >= 0:
+                    out[(mode, bool(cplx))] = c.value
+        return out
+
     def mm_tune_entries(self):
         """List of (key6 tuple, tile class, microseconds) of the recorded entries."""
         n = C.c_int()

@@ -31,6 +31,7 @@ EXPORTS = [
     "mm_fd2_periodic_order", "mm_fourier_d2", "mm_pipe_flow_operators", "mm_set_option", "mm_monitor_log",
     "mm_schrodinger_fd_hamiltonian", "mm_schrodinger_fd_exponential", "mm_hermite_ho_generator",
     "gpe_strang_step_noalloc", "mm_nonuniform_neumann_d2", "mm_op_prepare_ex", "mm_op_flags",
+    "mm_autotune_batched", "mm_autotune_batched_get",
 ]
 
 
@@ -85,6 +86,8 @@ def _load():
         "mm_hermite_matrices": (st, [C.c_int, C.POINTER(d), C.POINTER(d)]),
         "mm_autotune": (st, [P, C.POINTER(MMTensor), C.POINTER(P), C.c_int, P]),
         "mm_tune_count": (st, [P, C.POINTER(C.c_int)]),
+        "mm_autotune_batched": (st, [P, C.c_int, C.POINTER(C.POINTER(MMTensor)), C.POINTER(C.POINTER(P)), C.c_int, P]),
+        "mm_autotune_batched_get": (st, [P, C.c_int, C.c_int, C.POINTER(C.c_int)]),
         "mm_tune_get": (st, [P, C.c_int, C.POINTER(C.c_int64), C.POINTER(C.c_int), C.POINTER(d)]),
         "mm_tune_clear": (st, [P]),
         "mm_tune_save": (st, [P, C.c_char_p]),

@@ -107,6 +107,9 @@ struct mm_ctx_s {
   std::vector<uint64_t> bsig;
   hipGraph_t bgraph = nullptr;
   hipGraphExec_t bexec = nullptr;
+  // tile class of the batched step's products per (mode, complex), chosen by
+  // mm_autotune_batched (-1: the planner's choice)
+  int batch_cls[MM_MAXD][2] = {{-1, -1}, {-1, -1}, {-1, -1}, {-1, -1}, {-1, -1}, {-1, -1}};
   hipStream_t cap_stream = nullptr;
   // optional per-launch timing (mm_profile_begin / mm_profile_end)
   bool profiling = false;
@@ -1214,8 +1217,12 @@ mm_status mumode_expstep_batched(mm_ctx ctx, int count, mm_tensor* const* T, con
         if (k >= T[i]->d || !E[i][k]) continue;
         mm_op L = E[i][k];
         mm::ModePlan plan;
+        const int forced = ctx->batch_cls[k][is_complex(T[i]->dtype) ? 1 : 0];
+        const int keep_force = ctx->force_cls;
+        if (forced >= 0) ctx->force_cls = forced;
         st = run_mode(ctx, T[i]->data, T[i]->data, T[i]->dims, T[i]->d, T[i]->dtype, L, k + 1, 0, 0, s, &plan, true,
                       nullptr, true);
+        ctx->force_cls = keep_force;
         if (st != MM_OK) return st;
         if (!plan.covers_all_rows || plan.load == mm::KL_GENERIC)
           return fail(ctx, MM_ERR_UNSUPPORTED, "batched step needs n_mu <= 256 (complex) / 512 (real) and "
@@ -1526,6 +1533,89 @@ mm_status mm_autotune(mm_ctx ctx, const mm_tensor* T, const mm_op* E, int budget
   return MM_OK;
 }
 
+mm_status mm_autotune_batched(mm_ctx ctx, int count, mm_tensor* const* T, const mm_op* const* E, int budget_ms,
+                              mm_stream stream) {
+  if (!ctx) return MM_ERR_ARG;
+  if (count <= 0) return MM_OK;
+  hipStream_t s = (hipStream_t)stream;
+  // the (mode, complex) groups present in the batch
+  bool present[MM_MAXD][2] = {};
+  for (int i = 0; i < count; ++i) {
+    if (!T || !T[i] || !E || !E[i]) return fail(ctx, MM_ERR_ARG, "T / E entry %d is NULL", i);
+    for (int k = 0; k < T[i]->d && k < MM_MAXD; ++k)
+      if (E[i][k]) present[k][is_complex(T[i]->dtype) ? 1 : 0] = true;
+  }
+  for (int k = 0; k < MM_MAXD; ++k) ctx->batch_cls[k][0] = ctx->batch_cls[k][1] = -1;
+  batch_invalidate(ctx);
+  hipEvent_t e0, e1;
+  HIPCHK(ctx, hipEventCreate(&e0));
+  HIPCHK(ctx, hipEventCreate(&e1));
+  struct Ev {
+    hipEvent_t a, b;
+    ~Ev() { hipEventDestroy(a); hipEventDestroy(b); }
+  } guard{e0, e1};
+  // one captured step per candidate: a warm-up replay, then reps timed replays
+  auto time_step = [&](double* ms) -> mm_status {
+    mm_status st = mumode_expstep_batched(ctx, count, T, E, 1, stream);
+    if (st != MM_OK) return st;
+    HIPCHK(ctx, hipEventRecord(e0, s));
+    st = mumode_expstep_batched(ctx, count, T, E, 1, stream);
+    if (st != MM_OK) return st;
+    HIPCHK(ctx, hipEventRecord(e1, s));
+    HIPCHK(ctx, hipEventSynchronize(e1));
+    float t1 = 0.f;
+    HIPCHK(ctx, hipEventElapsedTime(&t1, e0, e1));
+    const int reps = (int)std::min(10.0, std::max(2.0, (double)budget_ms / 24.0 / std::max(1e-3, (double)t1)));
+    HIPCHK(ctx, hipEventRecord(e0, s));
+    st = mumode_expstep_batched(ctx, count, T, E, reps, stream);
+    if (st != MM_OK) return st;
+    HIPCHK(ctx, hipEventRecord(e1, s));
+    HIPCHK(ctx, hipEventSynchronize(e1));
+    float tr = 0.f;
+    HIPCHK(ctx, hipEventElapsedTime(&tr, e0, e1));
+    *ms = (double)tr / reps;
+    return MM_OK;
+  };
+  double best_ms = 0.0;
+  mm_status st = time_step(&best_ms);
+  if (st != MM_OK) return st;
+  // coordinate descent over the groups: each group's class in turn, the
+  // others held at their current choice
+  for (int k = 0; k < MM_MAXD; ++k)
+    for (int c = 0; c < 2; ++c) {
+      if (!present[k][c]) continue;
+      int best = -1;
+      for (int cls = 0; cls <= 2; ++cls) {
+        ctx->batch_cls[k][c] = cls;
+        batch_invalidate(ctx);
+        double ms = 0.0;
+        st = time_step(&ms);
+        if (st == MM_ERR_UNSUPPORTED) {
+          ctx->err.clear();
+          continue;
+        }
+        if (st != MM_OK) {
+          ctx->batch_cls[k][c] = best;
+          batch_invalidate(ctx);
+          return st;
+        }
+        if (ms < best_ms) {
+          best_ms = ms;
+          best = cls;
+        }
+      }
+      ctx->batch_cls[k][c] = best;
+      batch_invalidate(ctx);
+    }
+  return MM_OK;
+}
+
+mm_status mm_autotune_batched_get(mm_ctx ctx, int mode, int is_complex_, int* cls) {
+  if (!ctx || !cls || mode < 1 || mode > MM_MAXD || is_complex_ < 0 || is_complex_ > 1) return MM_ERR_ARG;
+  *cls = ctx->batch_cls[mode - 1][is_complex_];
+  return MM_OK;
+}
+
 mm_status mm_tune_count(mm_ctx ctx, int* count) {
   if (!ctx || !count) return MM_ERR_ARG;
   *count = (int)ctx->tune.size();
@@ -1547,6 +1637,7 @@ mm_status mm_tune_clear(mm_ctx ctx) {
   if (!ctx) return MM_ERR_ARG;
   batch_invalidate(ctx);
   ctx->tune.clear();
+  for (int k = 0; k < MM_MAXD; ++k) ctx->batch_cls[k][0] = ctx->batch_cls[k][1] = -1;
   return MM_OK;
 }
 

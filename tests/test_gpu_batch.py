@@ -79,3 +79,37 @@ def test_batched_rejects_fp16x2(ctx):
     with pytest.raises(mm.MumodeError) as e:
         ctx.mumode_expstep_batched([t], [[L, L]], 1)
     assert e.value.status == 7
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+def test_batch_autotuner_then_parity(ctx, prec):
+    # the batch autotuner times whole batched steps per (mode, real/complex)
+    # tile class; the step with the chosen classes must still match the oracle
+    import paper_2103_01691_amd as mm
+    mix = synth.batch_mix(40, cfg_id=5, sizes=(32, 48, 64, 96))
+    tensors, ops, inputs, refs = [], [], [], []
+    opcache = {}
+    for inst in mix:
+        cplx = inst["kind"] == "schrodinger"
+        g = synth.rng(5, 2000 + inst["index"])
+        U = cast(synth.random_tensor(inst["dims"], cplx, g), prec, cplx)
+        Eo = [_oracle_exponential(inst["kind"], n, inst["tau"]) for n in inst["dims"]]
+        refs.append(om.expstep(U, Eo, 1))
+        inputs.append((U, cplx))
+        ol = []
+        for n in inst["dims"]:
+            key = (inst["kind"], n, inst["tau"])
+            if key not in opcache:
+                opcache[key] = ctx.mm_op_prepare(_lib_exponential(mm, inst["kind"], n, inst["tau"]), prec)
+            ol.append(opcache[key])
+        ops.append(ol)
+        tensors.append(to_gpu(U, prec, cplx))
+    chosen = ctx.mm_autotune_batched(tensors, ops, 20)
+    note(f"batch autotuner {prec}: {chosen}")
+    assert all(0 <= c <= 2 for c in chosen.values())
+    for t, (U, cplx) in zip(tensors, inputs):
+        t.copy_(to_gpu(U, prec, cplx))
+    ctx.mumode_expstep_batched(tensors, ops, 1)
+    for inst, t, ref in zip(mix, tensors, refs):
+        assert rel(from_gpu(t), ref) < REL_TOL[prec], inst
+    ctx.mm_tune_clear()
