@@ -57,9 +57,10 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def counter_traffic(summary):
-    """Scaled FETCH_SIZE + WRITE_SIZE bytes per product launch from a committed
-    rocprofv3 summary, or None when it was taken on other kernel sources."""
+def counter_traffic(summary, field="traffic_bytes_per_launch"):
+    """A figure of a committed rocprofv3 summary (default: scaled FETCH_SIZE +
+    WRITE_SIZE bytes per product launch), or None when it was taken on other
+    kernel sources."""
     path = os.path.join(ROOT, "profiles", summary)
     if not os.path.exists(path):
         return None
@@ -72,7 +73,7 @@ def counter_traffic(summary):
     if fields.get("kernel_source_sha256_16") != kernel_source_hash():
         return None
     try:
-        return float(fields["traffic_bytes_per_launch"])
+        return float(fields[field])
     except (KeyError, ValueError):
         return None
 
@@ -402,6 +403,10 @@ def main():
                 prec, (SPLIT_PRODUCTS.get(prec, 1), PEAK["bf16"]))
             side[prec] = {"ms_per_step": pms, "steps_per_s": 1e3 / pms, "tflops_effective": eff,
                           "executed_mfma_frac_per_step": mult * eff * 1e12 / peak}
+            if prec in SPLIT_PRODUCTS:
+                summ = f"mode_kernel_{prec}_gpe3d_n256.md"
+                side[prec]["traffic_bytes_per_launch"] = counter_traffic(summ)
+                side[prec]["mfma_busy_frac_counters"] = counter_traffic(summ, "mfma_busy_frac")
         # trajectory-accurate variants: operators prepared as L - I (identity
         # split), each product adding its input back in the epilogue
         for prec in SPLIT_PRODUCTS:
@@ -470,6 +475,7 @@ def main():
             "kernel": f"mode_kernel (split {split}, complex 256x256 operator, one mu-mode product per launch)",
             "avg_launch_ms": avg_launch_ms, "launches": len(prod_ms), "per_kind_ms": per_kind,
             "executed_mfma_frac": (SPLIT_PRODUCTS[split] * achieved / PEAK["bf16"]) if achieved else None,
+            "mfma_busy_frac_counters": counter_traffic(f"mode_kernel_{split}_gpe3d_n256.md", "mfma_busy_frac"),
         },
         "tuned_tiles": tuned,
         "paths": side,
