@@ -145,6 +145,12 @@ struct SmallRun {
   int d, nsteps;
 };
 hipError_t launch_small_run(int prec, int cplx, const SmallRun& r, int* threads_out, hipStream_t s);
+// Whole run of a 2-D real FP64 integrator (n1, n2 <= 64) in one workgroup
+// with the state and the operators resident in LDS (kern_small.hip): U
+// (n1 x n2, column-major) <- E1 U E2^T nsteps times; E1 / E2 are FP64
+// masters (ld = rows), NULL leaves that mode unchanged.
+hipError_t launch_small_lds(double* U, int n1, int n2, const double* E1, const double* E2, int nsteps,
+                            hipStream_t s);
 
 // Optional diagonal phase scaling of a complex master before conversion:
 // L'[i,j] = exp(-i rc rx2[i]) L[i,j] exp(-i cc cx2[j]); rx2 / cx2 are device

@@ -547,6 +547,30 @@ mm_status monitor_end(mm_ctx ctx, hipStream_t s) {
 // *used = false (and nothing launched) when the problem does not qualify.
 mm_status small_expstep(mm_ctx ctx, mm_tensor* T, const mm_op* E, int nsteps, hipStream_t s, bool* used) {
   *used = false;
+  // 2-D real FP64 with both modes at most 64 long: state and operators stay
+  // in one workgroup's LDS for the whole run
+  if (T->d == 2 && T->dtype == MM_R64 && T->dims[0] <= 64 && T->dims[1] <= 64) {
+    bool ok = E[0] || E[1];
+    for (int k = 0; k < 2; ++k)
+      if (E[k]) ok = ok && E[k]->prec == MM_PREC_FP64 && !E[k]->cplx && !E[k]->idsplit;
+    if (ok) {
+      hipEvent_t e0 = nullptr, e1 = nullptr;
+      if (ctx->profiling) {
+        HIPCHK(ctx, hipEventCreate(&e0));
+        HIPCHK(ctx, hipEventCreate(&e1));
+        HIPCHK(ctx, hipEventRecord(e0, s));
+      }
+      HIPCHK(ctx, mm::launch_small_lds((double*)T->data, (int)T->dims[0], (int)T->dims[1],
+                                       E[0] ? E[0]->dev_master : nullptr, E[1] ? E[1]->dev_master : nullptr, nsteps,
+                                       s));
+      if (ctx->profiling) {
+        HIPCHK(ctx, hipEventRecord(e1, s));
+        ctx->recs.push_back({mm::KP_F64 * 1000 + 91, e0, e1});
+      }
+      *used = true;
+      return MM_OK;
+    }
+  }
   const size_t bytes = (size_t)numel(T) * dsize(T->dtype);
   if (bytes > ((size_t)2 << 20) || T->d > 6) return MM_OK;
   const bool cplx = is_complex(T->dtype);
