@@ -804,7 +804,9 @@ __device__ __forceinline__ void mode_tile(const ModeArgs& a, int64_t tile_x, int
       }
       voff[j] = (ob + (uint32_t)lp * (uint32_t)ostride) * (uint32_t)sizeof(st);
     }
-    const int64_t obytes = ostride * (int64_t)sizeof(st);
+    // every output byte offset fits in 32 bits (checked by the planner): a
+    // uniform base plus one 32-bit per-lane offset per store
+    const uint32_t obytes = (uint32_t)ostride * (uint32_t)sizeof(st);
     typedef float f32x2 __attribute__((ext_vector_type(2)));
     typedef typename std::conditional<sizeof(st) == 4, f32x2, f64x2>::type st2;
 #pragma unroll
@@ -826,7 +828,7 @@ __device__ __forceinline__ void mode_tile(const ModeArgs& a, int64_t tile_x, int
 #pragma unroll
               for (int h = 0; h < 2; ++h) {
                 const int u = (MB == 32) ? mf * 16 + 4 * gq + h : mf * 8 + 4 * h;
-                const st2 x = *(const st2*)((const char*)a.in + (int64_t)u * obytes + voff[j]);
+                const st2 x = *(const st2*)((const char*)a.in + ((uint32_t)u * obytes + voff[j]));
                 st y0 = x[0], y1 = x[1];
                 if constexpr (PRO) phase<st>(y0, y1, s_pre);
                 v4[2 * h] += y0;
@@ -840,18 +842,16 @@ __device__ __forceinline__ void mode_tile(const ModeArgs& a, int64_t tile_x, int
 #pragma unroll
             for (int h = 0; h < 2; ++h) {
               const int u = (MB == 32) ? mf * 16 + 4 * gq + h : mf * 8 + 4 * h;
-              if constexpr (F16) vmax = fmaxf(vmax, fmaxf(fabsf(v4[2 * h]), fabsf(v4[2 * h + 1])));
-              char* sb = (char*)out + (int64_t)u * obytes;
-              *(st2*)(sb + voff[j]) = st2{v4[2 * h], v4[2 * h + 1]};
+              if constexpr (F16) vmax = fmaxf(fmaxf(vmax, fabsf(v4[2 * h])), fabsf(v4[2 * h + 1]));
+              *(st2*)((char*)out + ((uint32_t)u * obytes + voff[j])) = st2{v4[2 * h], v4[2 * h + 1]};
             }
           } else {
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
               const int u = (MB == 32) ? mf * 32 + 8 * gq + r : mf * 16 + 4 * r;
-              if constexpr (IDA) v4[r] += *(const st*)((const char*)a.in + (int64_t)u * obytes + voff[j]);
+              if constexpr (IDA) v4[r] += *(const st*)((const char*)a.in + ((uint32_t)u * obytes + voff[j]));
               if constexpr (F16) vmax = fmaxf(vmax, fabsf(v4[r]));
-              char* sb = (char*)out + (int64_t)u * obytes;
-              *(st*)(sb + voff[j]) = v4[r];
+              *(st*)((char*)out + ((uint32_t)u * obytes + voff[j])) = v4[r];
             }
           }
         }
