@@ -407,6 +407,23 @@ def main():
                 summ = f"mode_kernel_{prec}_gpe3d_n256.md"
                 side[prec]["traffic_bytes_per_launch"] = counter_traffic(summ)
                 side[prec]["mfma_busy_frac_counters"] = counter_traffic(summ, "mfma_busy_frac")
+        # one step per call (a serving-style loop): every FP16x2 call starts
+        # with a max-abs pass over the state, unless consecutive calls on the
+        # tensor continue the running bound (MM_OPT_FP16X2_CHAIN)
+        import synth
+        psi = torch.from_numpy(synth.to_device_layout(psi0.astype(np.complex64))).cuda()
+        op1 = ctx.mm_op_prepare(E, "fp16x2")
+        percall = {}
+        for chain in (0, 1):
+            ctx.mm_set_option(mm.MM_OPT_FP16X2_CHAIN, chain)
+            ctx.gpe_strang_step(psi, [op1] * D, TAU, BETA, 1)
+            k = 50
+            t = timed(torch, lambda r: [ctx.gpe_strang_step(psi, [op1] * D, TAU, BETA, 1) for _ in range(r)], k)
+            percall["chained_bound" if chain else "max_abs_pass_each_call"] = 1e3 * t / k
+        ctx.mm_set_option(mm.MM_OPT_FP16X2_CHAIN, 0)
+        side["fp16x2_one_step_per_call_ms"] = percall
+        op1.destroy()
+        del psi
         # trajectory-accurate variants: operators prepared as L - I (identity
         # split), each product adding its input back in the epilogue
         for prec in SPLIT_PRODUCTS:

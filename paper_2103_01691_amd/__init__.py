@@ -20,6 +20,7 @@ from ._lib import (MM_C64, MM_C128, MM_PREC_BF16, MM_PREC_FP32, MM_PREC_FP64,  #
 
 MM_OPT_SMALL_RUN = 1
 MM_OPT_MONITOR_EVERY = 2
+MM_OPT_FP16X2_CHAIN = 3
 MM_OP_IDENTITY_SPLIT = 1
 
 PRECISIONS = {"fp64": MM_PREC_FP64, "fp32": MM_PREC_FP32, "bf16x3": MM_PREC_SPLIT_BF16X3,

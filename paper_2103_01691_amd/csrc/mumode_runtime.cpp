@@ -55,6 +55,9 @@ struct mm_ctx_s {
   // in-call monitor (MM_OPT_MONITOR_EVERY): sum |T|^2 every mon_every steps
   // of mumode_expstep / gpe_strang_step, kept on the device until the call ends
   int mon_every = 0;
+  // MM_OPT_FP16X2_CHAIN: an expstep / GPE call on the tensor the previous
+  // such call ended with continues its FP16X2 running bound
+  bool keep_chain = false;
   double* mon_dev = nullptr;
   size_t mon_cap = 0;
   std::vector<int> mon_steps;
@@ -849,7 +852,7 @@ mm_status mumode_expstep(mm_ctx ctx, mm_tensor* T, const mm_op* E, int nsteps, m
     if (st != MM_OK) return st;
   }
   HIPCHK(ctx, hipSetDevice(ctx->device));
-  ctx->chain_end = nullptr;
+  if (!ctx->keep_chain || T->data != ctx->chain_end) ctx->chain_end = nullptr;
   if (ctx->small_run && nsteps >= 2 && ctx->mon_every <= 0) {
     bool used = false;
     st = small_expstep(ctx, T, E, nsteps, (hipStream_t)stream, &used);
@@ -957,7 +960,7 @@ mm_status gpe_strang_impl(mm_ctx ctx, mm_tensor* psi, const mm_op* E, double tau
       return fail(ctx, MM_ERR_UNSUPPORTED, "E[%d] is real: the allocation-free step takes complex operators", k);
   }
   HIPCHK(ctx, hipSetDevice(ctx->device));
-  ctx->chain_end = nullptr;
+  if (noalloc || !ctx->keep_chain || psi->data != ctx->chain_end) ctx->chain_end = nullptr;
   const double half = 0.5 * tau * beta, full = tau * beta;
   if (noalloc) {
     // every product must run in place (no workspace), i.e. its plan must
@@ -1896,6 +1899,11 @@ mm_status mm_set_option(mm_ctx ctx, int option, int64_t value) {
     case MM_OPT_MONITOR_EVERY:
       if (value < 0 || value > (1 << 30)) return fail(ctx, MM_ERR_ARG, "monitor interval %lld", (long long)value);
       ctx->mon_every = (int)value;
+      return MM_OK;
+    case MM_OPT_FP16X2_CHAIN:
+      if (value != 0 && value != 1) return fail(ctx, MM_ERR_ARG, "MM_OPT_FP16X2_CHAIN takes 0 or 1");
+      ctx->keep_chain = value != 0;
+      ctx->chain_end = nullptr;
       return MM_OK;
     default:
       return fail(ctx, MM_ERR_ARG, "unknown option %d", option);

@@ -327,3 +327,32 @@ def test_fp16x2_state_changed_between_calls(ctx):
     err = rel(from_gpu(T), om.expstep(mid, E, 1))
     note(f"fp16x2 rescaled between calls rel err {err:.3e}")
     assert err < REL_TOL["fp16x2"]
+
+
+def test_fp16x2_chain_across_calls(ctx):
+    # MM_OPT_FP16X2_CHAIN: consecutive GPE calls on one tensor continue the
+    # running bound the previous call's last product wrote (the exact maximum
+    # of its output), so the results equal those of calls that each start
+    # with a max-abs pass, bit for bit; a call on another tensor starts a
+    # chain of its own
+    import paper_2103_01691_amd as mm
+    n, a, b, beta, tau = 48, -8.0, 8.0, 100.0, 1e-3
+    psi0 = cast(synth.thomas_fermi_initial(n, a, b, 3, beta, cfg_id=4), "fp16x2", True)
+    E = ctx.mm_op_prepare(mm.schrodinger_fd_exponential(n, a, b, 1.0, tau), "fp16x2")
+    other0 = cast(synth.wavepacket_initial(n, -10.0, 10.0, 3, cfg_id=2), "fp16x2", True)
+    runs = {}
+    for chain in (0, 1):
+        ctx.mm_set_option(mm.MM_OPT_FP16X2_CHAIN, chain)
+        psi = to_gpu(psi0, "fp16x2", True)
+        other = to_gpu(other0, "fp16x2", True)
+        for it in range(4):
+            ctx.gpe_strang_step(psi, [E] * 3, tau, beta, 1)
+            if it == 1:
+                ctx.gpe_strang_step(other, [E] * 3, tau, beta, 1)
+        runs[chain] = (from_gpu(psi), from_gpu(other))
+    ctx.mm_set_option(mm.MM_OPT_FP16X2_CHAIN, 0)
+    E.destroy()
+    assert np.array_equal(runs[0][0], runs[1][0]) and np.array_equal(runs[0][1], runs[1][1])
+    Eo = op.ho_exponential(n, a, b, tau)
+    assert rel(runs[1][0], sc.gpe_strang(psi0, [Eo] * 3, tau, beta, 4)) < 4 * REL_TOL["fp16x2"]
+    assert rel(runs[1][1], sc.gpe_strang(other0, [Eo] * 3, tau, beta, 1)) < REL_TOL["fp16x2"]
