@@ -338,7 +338,7 @@ size_t prepared_bytes(int prec, int KBT, int MFT) {
 }
 
 int num_classes(int prec) {
-  return (prec == KP_BF16X3 || prec == KP_FP16X2) ? 7 : 3;
+  return (prec == KP_BF16X3 || prec == KP_FP16X2) ? 8 : 3;
 }
 
 bool plan_mode(const ModeArgs& a, int prec, int cplx, bool want_pro, bool want_epi, bool fcontig_ok,

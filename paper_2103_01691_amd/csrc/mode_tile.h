@@ -995,7 +995,9 @@ void mode_kernel(ModeArgs a) {
 // operators with at most 256 / 128 real rows, classes 3 and 4 are alternative
 // shapes of the split complex kernels (4 x 128 rows, 128 fibres, with 4 or 2
 // K-blocks per LDS chunk), classes 5 and 6 split shapes with 64 fibres sized
-// for two workgroups per CU (OCC = 2).
+// for two workgroups per CU (OCC = 2), class 7 a small split tile (4 x 64
+// rows, 32 fibres, two workgroups per CU) for modes of at most 128 complex
+// entries, where larger tiles leave too few workgroups to cover latency.
 template <int PR, int CLS> struct Cfg;
 template <> struct Cfg<KP_F64, 0> { static constexpr int WMF = 8, WNF = 2, WM = 4, WN = 1, KCH = 8; static constexpr int OCC = 1; };
 template <> struct Cfg<KP_F64, 1> { static constexpr int WMF = 8, WNF = 1, WM = 2, WN = 2, KCH = 8; static constexpr int OCC = 1; };
@@ -1010,6 +1012,7 @@ template <> struct Cfg<KP_BF16X3, 3> { static constexpr int WMF = 4, WNF = 4, WM
 template <> struct Cfg<KP_BF16X3, 4> { static constexpr int WMF = 4, WNF = 4, WM = 4, WN = 1, KCH = 2; static constexpr int OCC = 1; };
 template <> struct Cfg<KP_BF16X3, 5> { static constexpr int WMF = 4, WNF = 2, WM = 4, WN = 1, KCH = 4; static constexpr int OCC = 2; };
 template <> struct Cfg<KP_BF16X3, 6> { static constexpr int WMF = 4, WNF = 2, WM = 4, WN = 1, KCH = 2; static constexpr int OCC = 2; };
+template <> struct Cfg<KP_BF16X3, 7> { static constexpr int WMF = 2, WNF = 1, WM = 4, WN = 1, KCH = 4; static constexpr int OCC = 2; };
 template <> struct Cfg<KP_FP16X2, 0> { static constexpr int WMF = 4, WNF = 2, WM = 4, WN = 1, KCH = 4; static constexpr int OCC = 1; };
 template <> struct Cfg<KP_FP16X2, 1> { static constexpr int WMF = 4, WNF = 1, WM = 2, WN = 2, KCH = 4; static constexpr int OCC = 1; };
 template <> struct Cfg<KP_FP16X2, 2> { static constexpr int WMF = 4, WNF = 1, WM = 1, WN = 4, KCH = 4; static constexpr int OCC = 1; };
@@ -1017,13 +1020,14 @@ template <> struct Cfg<KP_FP16X2, 3> { static constexpr int WMF = 4, WNF = 4, WM
 template <> struct Cfg<KP_FP16X2, 4> { static constexpr int WMF = 4, WNF = 4, WM = 4, WN = 1, KCH = 2; static constexpr int OCC = 1; };
 template <> struct Cfg<KP_FP16X2, 5> { static constexpr int WMF = 4, WNF = 2, WM = 4, WN = 1, KCH = 4; static constexpr int OCC = 2; };
 template <> struct Cfg<KP_FP16X2, 6> { static constexpr int WMF = 4, WNF = 2, WM = 4, WN = 1, KCH = 2; static constexpr int OCC = 2; };
+template <> struct Cfg<KP_FP16X2, 7> { static constexpr int WMF = 2, WNF = 1, WM = 4, WN = 1, KCH = 4; static constexpr int OCC = 2; };
 template <> struct Cfg<KP_BF16, 0> { static constexpr int WMF = 4, WNF = 2, WM = 4, WN = 1, KCH = 4; static constexpr int OCC = 1; };
 template <> struct Cfg<KP_BF16, 1> { static constexpr int WMF = 4, WNF = 1, WM = 2, WN = 2, KCH = 4; static constexpr int OCC = 1; };
 template <> struct Cfg<KP_BF16, 2> { static constexpr int WMF = 4, WNF = 1, WM = 1, WN = 4, KCH = 4; static constexpr int OCC = 1; };
 
 template <int PR> struct NumCls { static constexpr int N = 3; };
-template <> struct NumCls<KP_BF16X3> { static constexpr int N = 7; };
-template <> struct NumCls<KP_FP16X2> { static constexpr int N = 7; };
+template <> struct NumCls<KP_BF16X3> { static constexpr int N = 8; };
+template <> struct NumCls<KP_FP16X2> { static constexpr int N = 8; };
 
 template <int PR, int CLS> TileShape shape_of() {
   typedef Cfg<PR, CLS> C;
@@ -1085,7 +1089,9 @@ KernFn pick_kernel(int cplx, int ld, int pro, int epi, int cls, int full) {
         case 3: if (ld == KL_KCONTIG) MM_PH(true, KL_KCONTIG, 3); else MM_PH(true, KL_FCONTIG, 3);
         case 4: if (ld == KL_KCONTIG) MM_PH(true, KL_KCONTIG, 4); else MM_PH(true, KL_FCONTIG, 4);
         case 5: if (ld == KL_KCONTIG) MM_PH(true, KL_KCONTIG, 5); else MM_PH(true, KL_FCONTIG, 5);
-        default: if (ld == KL_KCONTIG) MM_PH(true, KL_KCONTIG, 6); else MM_PH(true, KL_FCONTIG, 6);
+        case 6: if (ld == KL_KCONTIG) MM_PH(true, KL_KCONTIG, 6); else MM_PH(true, KL_FCONTIG, 6);
+        case 7: if (ld == KL_KCONTIG) MM_PH(true, KL_KCONTIG, 7); else MM_PH(true, KL_FCONTIG, 7);
+        default: return nullptr;
       }
     }
   }
@@ -1129,6 +1135,7 @@ bool shape_table(int cls, TileShape* out) {
       case 4: *out = shape_of<PR, 4>(); return true;
       case 5: *out = shape_of<PR, 5>(); return true;
       case 6: *out = shape_of<PR, 6>(); return true;
+      case 7: *out = shape_of<PR, 7>(); return true;
       default: break;
     }
   }
