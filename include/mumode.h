@@ -109,8 +109,13 @@ typedef struct {
 /* ------------------------------------------------------------ context ---- */
 
 /* Create a context on HIP device `device` (checks it is gfx950).
- * Returns MM_ERR_NODEVICE if there is none; *out is NULL on failure. */
-mm_status mm_create(mm_ctx* out, int device);
+ * tune_cache_path (nullable): a tune file (mm_tune_save format) that the
+ * context reads at creation when it exists, and to which mm_autotune writes
+ * the context's entries after every tuning run, so tile choices persist
+ * across processes; a missing file is not an error, a malformed one is
+ * (MM_ERR_ARG, no context).  Returns MM_ERR_NODEVICE if there is no usable
+ * device; *out is NULL on failure. */
+mm_status mm_create(mm_ctx* out, int device, const char* tune_cache_path);
 /* Free every operator and buffer the context owns.  NULL is accepted. */
 mm_status mm_destroy(mm_ctx ctx);
 /* Static description of a status code. */

@@ -208,9 +208,9 @@ def _op_array(ops):
 class Context:
     """mm_create / mm_destroy around one device."""
 
-    def __init__(self, device: int = 0):
+    def __init__(self, device: int = 0, tune_cache_path=None):
         h = C.c_void_p()
-        st = _lib.lib.mm_create(C.byref(h), device)
+        st = _lib.lib.mm_create(C.byref(h), device, None if tune_cache_path is None else str(tune_cache_path).encode())
         if st != 0:
             raise MumodeError(st, "mm_create", _lib.lib.mm_last_error(None).decode())
         self.handle = h

@@ -57,7 +57,7 @@ def _load():
     P = C.c_void_p
     d = C.c_double
     sig = {
-        "mm_create": (st, [C.POINTER(P), C.c_int]),
+        "mm_create": (st, [C.POINTER(P), C.c_int, C.c_char_p]),
         "mm_destroy": (st, [P]),
         "mm_status_string": (C.c_char_p, [st]),
         "mm_last_error": (C.c_char_p, [P]),

@@ -50,6 +50,7 @@ struct mm_ctx_s {
   // path, real rows Mr, real columns Kr, fibres F) -> (class, microseconds)
   std::map<std::array<int64_t, 6>, std::pair<int, double>> tune;
   int force_cls = -1;            // set while the autotuner times a class
+  std::string tune_path;         // tune cache file (mm_create), "" if none
   std::array<int64_t, 6> last_key{};   // tune key of the last planned product
   bool small_run = true;         // whole-run single-workgroup kernel for small expsteps
   // in-call monitor (MM_OPT_MONITOR_EVERY): sum |T|^2 every mon_every steps
@@ -654,7 +655,7 @@ const char* mm_status_string(mm_status s) {
 
 const char* mm_last_error(mm_ctx ctx) { return ctx ? ctx->err.c_str() : g_create_err.c_str(); }
 
-mm_status mm_create(mm_ctx* out, int device) {
+mm_status mm_create(mm_ctx* out, int device, const char* tune_cache_path) {
   if (!out) return fail(nullptr, MM_ERR_ARG, "out is NULL");
   *out = nullptr;
   int count = 0;
@@ -680,6 +681,17 @@ mm_status mm_create(mm_ctx* out, int device) {
     if (e != hipSuccess) {
       mm_destroy(c);
       return fail(nullptr, MM_ERR_HIP, "hipGetSymbolAddress(scratch) failed: %s", hipGetErrorString(e));
+    }
+  }
+  if (tune_cache_path) {
+    c->tune_path = tune_cache_path;
+    if (FILE* f = std::fopen(tune_cache_path, "r")) {
+      std::fclose(f);
+      if (mm_tune_load(c, tune_cache_path) != MM_OK) {
+        const std::string why = c->err;
+        mm_destroy(c);
+        return fail(nullptr, MM_ERR_ARG, "tune cache: %s", why.c_str());
+      }
     }
   }
   *out = c;
@@ -1557,6 +1569,7 @@ mm_status mm_autotune(mm_ctx ctx, const mm_tensor* T, const mm_op* E, int budget
   }
   batch_invalidate(ctx);
   ctx->chain_end = nullptr;
+  if (!ctx->tune_path.empty()) return mm_tune_save(ctx, ctx->tune_path.c_str());
   return MM_OK;
 }
 

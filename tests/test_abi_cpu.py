@@ -51,7 +51,7 @@ def test_create_without_gpu_reports_nodevice():
         pytest.skip("a GPU is present")
     lib = _lib().lib
     h = C.c_void_p()
-    assert lib.mm_create(C.byref(h), 0) == _lib().MM_ERR_NODEVICE
+    assert lib.mm_create(C.byref(h), 0, None) == _lib().MM_ERR_NODEVICE
     assert h.value is None
     assert b"device" in lib.mm_last_error(None)
     assert lib.mm_destroy(None) == 0

@@ -122,3 +122,24 @@ def test_caller_workspace(ctx):
     ctx.mumode_transform(out, to_gpu(U, "fp64", True), ops)
     assert rel(from_gpu(out), om.tucker(U, Phi)) < 1e-12
     del small, big
+
+
+def test_tune_cache_path_persists_across_contexts(tmp_path):
+    # mm_create's tune cache: read at creation when present, written by every
+    # autotuner run; a malformed file refuses the context
+    import paper_2103_01691_amd as mm
+    path = tmp_path / "cache.txt"
+    U, E = _problem("fp32")
+    with mm.Context(0, tune_cache_path=path) as c1:
+        assert c1.mm_tune_entries() == []
+        ops = [c1.mm_op_prepare(e, "fp32") for e in E]
+        c1.mm_autotune(to_gpu(U, "fp32", True), ops, 100)
+        ent = [(k, c) for k, c, _ in c1.mm_tune_entries()]
+    assert path.exists() and len(ent) == len(DIMS)
+    with mm.Context(0, tune_cache_path=path) as c2:
+        assert [(k, c) for k, c, _ in c2.mm_tune_entries()] == ent
+    bad = tmp_path / "bad.txt"
+    bad.write_text("not a tune file\n")
+    with pytest.raises(mm.MumodeError) as e:
+        mm.Context(0, tune_cache_path=bad)
+    assert e.value.status == 1
