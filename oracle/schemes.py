@@ -15,6 +15,11 @@ Pins (tests/test_oracle_schemes.py):
                     keeps |psi|).
   monitors       -- mass of a normalised state is 1; energy of a 1-D HO
                     eigenvector of the FD Hamiltonian equals its eigenvalue.
+  vortex_strang  -- the nonlinear subflow of the Section 4.5 vortex problem
+                    against its ODE (central differences in time) and |v|
+                    constant; the background u = 1 (v = W^(1/2) 1) is an
+                    exact steady state of the whole step; the W-weighted mass
+                    is conserved; second order in tau.
   magnus_midpoint -- g = 0 equals the exact harmonic-oscillator propagation
                     in Hermite space; a constant g is exact in time (one step
                     of tau equals k steps of tau/k); second order against a
@@ -59,6 +64,27 @@ def gpe_strang_merged(psi: np.ndarray, E, tau: float, beta: float, nsteps: int =
 
 
 # --------------------------------------- harmonic oscillator (Hermite) -----
+
+def vortex_nonlinear(v: np.ndarray, s: float, winv: np.ndarray) -> np.ndarray:
+    """Exact flow over time s of the nonlinear part of the Section 4.5
+    vortex problem in the symmetrised variable v = W^(1/2) u,
+    v_t = (i/2)(1 - W^-1 |v|^2) v: |v| is constant along it, so
+    v <- exp((i s / 2)(1 - W^-1 |v|^2)) v.  winv: the tensor of W^-1 (the
+    product over the modes of the inverse dual-cell widths)."""
+    return np.exp(0.5j * s * (1.0 - winv * np.abs(v) ** 2)) * v
+
+
+def vortex_strang(v: np.ndarray, E, winv: np.ndarray, tau: float, nsteps: int = 1) -> np.ndarray:
+    """Strang splitting of v_t = (i/2) M_W v + (i/2)(1 - W^-1 |v|^2) v
+    (Section 4.5): N(tau/2) L(tau) N(tau/2) per step, L the mu-mode integrator
+    with E_mu = exp(i tau/2 M_mu) (M_W is the Kronecker sum of the modes'
+    M_mu), N the exact nonlinear flow."""
+    for _ in range(nsteps):
+        v = vortex_nonlinear(v, 0.5 * tau, winv)
+        v = tucker(v, E)
+        v = vortex_nonlinear(v, 0.5 * tau, winv)
+    return v
+
 
 def ho_potential_flow(psi: np.ndarray, nodes, a: float, b: float, eps: float) -> np.ndarray:
     """Exact flow from time a to b of i psi_t = (eps/2) sin(t) |x|^2 psi:

@@ -73,6 +73,21 @@ def graded_nodes(n: int, a: float, b: float, alpha: float = 2.0) -> np.ndarray:
     return c + r * np.sinh(alpha * xi) / np.sinh(alpha)
 
 
+def vortex_pair_initial(nodes, d: float = 2.0, cfg_id: int = 6, instance_id: int = 0) -> np.ndarray:
+    """A vortex and an anti-vortex, straight lines along x_3 through
+    (x_1, x_2) = (+d, 0) and (-d, 0), in a background of density 1:
+    u = prod_s ((x_1 - s d) + i s x_2) / sqrt((x_1 - s d)^2 + x_2^2 + 1),
+    s = +1, -1, plus 1e-3 seeded complex noise (3-D; nodes: three 1-D node
+    arrays).  |u| -> 1 away from the lines."""
+    x1, x2 = nodes[0][:, None, None], nodes[1][None, :, None]
+    u = np.ones((nodes[0].size, nodes[1].size, nodes[2].size), dtype=np.complex128)
+    for sgn in (1.0, -1.0):
+        z = (x1 - sgn * d) + 1j * sgn * x2
+        u = u * (z / np.sqrt(np.abs(z) ** 2 + 1.0))
+    g = rng(cfg_id, instance_id)
+    return u + 1e-3 * complex_noise(u.shape, g)
+
+
 def random_tensor(dims, complex_: bool, g: np.random.Generator, dist: str = "normal") -> np.ndarray:
     dims = tuple(int(x) for x in dims)
     if dist == "uniform":

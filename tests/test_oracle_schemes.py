@@ -214,3 +214,51 @@ def test_magnus_product_state_is_product_of_mode_steps():
         w.append(sc.magnus_midpoint(u, Bs, ds, lambda nu, t, mu=mu: gf(mu, t) if nu == 0 else 0.0,
                                     tau, 3, t0=0.1).reshape(m))
     assert _rel(got, np.einsum("i,j,k->ijk", *w)) < 1e-12
+
+
+# ------------------------------------------ vortex problem (Section 4.5) ----
+
+def _vortex_setup(dims=(14, 12, 10), alpha=1.5):
+    xs = [synth.graded_nodes(n, -20.0, 20.0, alpha) for n in dims]
+    Ms, ws = zip(*[op.nonuniform_neumann_d2(x) for x in xs])
+    winv = 1.0 / (ws[0][:, None, None] * ws[1][None, :, None] * ws[2][None, None, :])
+    return xs, Ms, ws, winv
+
+
+def test_vortex_nonlinear_flow_solves_its_ode():
+    xs, _, ws, winv = _vortex_setup()
+    W = 1.0 / winv
+    v = np.sqrt(W) * synth.vortex_pair_initial(xs)
+    s, dt = 0.3, 1e-4
+    vs = sc.vortex_nonlinear(v, s, winv)
+    assert np.allclose(np.abs(vs), np.abs(v), rtol=1e-14, atol=0)
+    deriv = (sc.vortex_nonlinear(v, s + dt, winv) - sc.vortex_nonlinear(v, s - dt, winv)) / (2 * dt)
+    rhs = 0.5j * (1.0 - winv * np.abs(vs) ** 2) * vs
+    assert np.max(np.abs(deriv - rhs)) < 1e-7 * np.max(np.abs(rhs))
+
+
+def test_vortex_background_is_a_steady_state():
+    # u = 1 everywhere: the Neumann Laplacian annihilates constants and the
+    # nonlinearity (1 - |u|^2) vanishes, so the whole step leaves it unchanged
+    xs, Ms, ws, winv = _vortex_setup()
+    E = [op.exp_symmetric(M, 0.5j * 0.1) for M in Ms]
+    v = np.sqrt(ws[0][:, None, None] * ws[1][None, :, None] * ws[2][None, None, :]).astype(np.complex128)
+    out = sc.vortex_strang(v, E, winv, 0.1, 5)
+    assert np.max(np.abs(out - v)) < 1e-12 * np.max(np.abs(v))
+
+
+def test_vortex_step_keeps_weighted_mass_and_is_second_order():
+    xs, Ms, ws, winv = _vortex_setup()
+    v0 = np.sqrt(1.0 / winv) * synth.vortex_pair_initial(xs)
+    T = 0.4
+
+    def run(k):
+        tau = T / k
+        E = [op.exp_symmetric(M, 0.5j * tau) for M in Ms]
+        return sc.vortex_strang(v0, E, winv, tau, k)
+
+    r1, r2, r4 = run(4), run(8), run(16)
+    assert abs(np.sum(np.abs(r4) ** 2) / np.sum(np.abs(v0) ** 2) - 1.0) < 1e-12
+    e1 = np.linalg.norm(r1 - r2)
+    e2 = np.linalg.norm(r2 - r4)
+    assert 3.5 < e1 / e2 < 4.5
