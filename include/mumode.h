@@ -228,6 +228,21 @@ mm_status ho_strang_step(mm_ctx ctx, mm_tensor* psi, const mm_op* Phi_fwd, const
                          const double* const* nodes, double t0, double tau, double eps, int nsteps,
                          mm_stream stream);
 
+/* Strang splitting for the vortex-reconnection problem of Section 4.5 in
+ * its symmetrised form, v_t = (i/2) M_W v + (i/2)(1 - W^-1 |v|^2) v, where
+ * v = W^(1/2) u, M_W is the Kronecker sum of the modes' symmetrised
+ * non-uniform Neumann operators (mm_nonuniform_neumann_d2) and W the
+ * Kronecker product of their dual-cell widths.  One step is N(tau/2) L(tau)
+ * N(tau/2) with L(tau) = x_1 E[0] ... x_d E[d-1], E[k] = exp(i tau/2 M_k),
+ * and N(s) v = exp((i s/2)(1 - W^-1 |v|^2)) v, the exact nonlinear flow
+ * (|v| is constant along it).  Adjacent half steps of N are merged; each N
+ * is one pass over the state (its coefficient varies with the position).
+ *   w[k]: host array of the n_{k+1} dual-cell widths of mode k+1 (the w of
+ *         mm_nonuniform_neumann_d2), uploaded when they change.
+ * v is complex, updated in place. */
+mm_status vortex_strang_step(mm_ctx ctx, mm_tensor* v, const mm_op* E, const double* const* w, double tau,
+                             int nsteps, mm_stream stream);
+
 /* Batched integrator: count independent instances, each
  * T[i] <- T[i] x_1 E[i][0] ... x_{d_i} E[i][d_i - 1], nsteps times, in place.
  * Instances may differ in d, dims, dtype (real / complex) and precision.  One

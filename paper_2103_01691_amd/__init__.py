@@ -309,6 +309,15 @@ class Context:
                   "ho_strang_step")
         return psi
 
+    def vortex_strang_step(self, v, E, w, tau: float, nsteps: int = 1, stream=None):
+        """E: per-mode exp(i tau/2 M_k) operators; w: per-mode dual-cell widths."""
+        t = as_mm_tensor(v)
+        keep = [np.ascontiguousarray(np.asarray(x, dtype=np.float64)) for x in w]
+        arr = (C.POINTER(C.c_double) * len(keep))(*[k.ctypes.data_as(C.POINTER(C.c_double)) for k in keep])
+        self._chk(_lib.lib.vortex_strang_step(self.handle, C.byref(t), _op_array(E), arr, float(tau), nsteps,
+                                              _stream(stream)), "vortex_strang_step")
+        return v
+
     def mm_energy_gpe(self, psi, H, beta: float, cell: float, stream=None) -> float:
         t = as_mm_tensor(psi)
         out = C.c_double()

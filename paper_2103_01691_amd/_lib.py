@@ -31,7 +31,7 @@ EXPORTS = [
     "mm_fd2_periodic_order", "mm_fourier_d2", "mm_pipe_flow_operators", "mm_set_option", "mm_monitor_log",
     "mm_schrodinger_fd_hamiltonian", "mm_schrodinger_fd_exponential", "mm_hermite_ho_generator",
     "gpe_strang_step_noalloc", "mm_nonuniform_neumann_d2", "mm_op_prepare_ex", "mm_op_flags",
-    "mm_autotune_batched", "mm_autotune_batched_get",
+    "mm_autotune_batched", "mm_autotune_batched_get", "vortex_strang_step",
 ]
 
 
@@ -72,6 +72,7 @@ def _load():
         "mumode_transform": (st, [P, C.POINTER(MMTensor), C.POINTER(MMTensor), C.POINTER(P), P]),
         "gpe_strang_step": (st, [P, C.POINTER(MMTensor), C.POINTER(P), d, d, C.c_int, P]),
         "gpe_strang_step_noalloc": (st, [P, C.POINTER(MMTensor), C.POINTER(P), d, d, C.c_int, P]),
+        "vortex_strang_step": (st, [P, C.POINTER(MMTensor), C.POINTER(P), C.POINTER(C.POINTER(d)), d, C.c_int, P]),
         "mm_norm2": (st, [P, C.POINTER(MMTensor), d, C.POINTER(d), P]),
         "mm_profile_begin": (st, [P]),
         "ho_strang_step": (st, [P, C.POINTER(MMTensor), C.POINTER(P), C.POINTER(P), C.POINTER(C.POINTER(d)), d, d, d,

@@ -278,6 +278,37 @@ __global__ void hermite_collapse_kernel(const double* __restrict__ Phi, const do
   out[2 * e + 1] = im;
 }
 
+// Exact flow over time s of the nonlinear part of the Section 4.5 vortex
+// problem in the symmetrised variable v = W^(1/2) u:
+// v <- exp((i s / 2)(1 - W^-1 |v|^2)) v, W^-1 the product over the modes of
+// the inverse dual-cell widths winv[k * 4096 + i_k].  |v| is constant along
+// the flow.  One thread per entry (grid-stride); FP32 states take the angle
+// and its sine / cosine in FP32 (the library's own reduction and series),
+// FP64 states in FP64.
+struct Dims6 {
+  int64_t n[6];
+};
+template <typename T>
+__global__ __launch_bounds__(256) void vortex_phase_kernel(T* __restrict__ v, int64_t count, int d, Dims6 dims,
+                                                           const double* __restrict__ winv, double s) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < count; e += (int64_t)gridDim.x * blockDim.x) {
+    int64_t r = e;
+    double wi = 1.0;
+    for (int k = 0; k < d; ++k) {
+      const int64_t i = r % dims.n[k];
+      r /= dims.n[k];
+      wi *= winv[(int64_t)k * 4096 + i];
+    }
+    T re = v[2 * e], im = v[2 * e + 1];
+    const T th = (T)(0.5 * s) * ((T)1 - (T)wi * (re * re + im * im));
+    T sn, cs;
+    if constexpr (sizeof(T) == 8) sincos(th, &sn, &cs);
+    else sincos_f32<false>(th, &sn, &cs);
+    v[2 * e] = re * cs - im * sn;
+    v[2 * e + 1] = im * cs + re * sn;
+  }
+}
+
 // ---------------------------------------------------------- host side -----
 
 KernFn pick_kernel_any(int prec, int cplx, int ld, int pro, int epi, int cls, int full = 0, int ida = 0) {
@@ -508,6 +539,22 @@ hipError_t launch_hermite_collapse(const double* Phi, const double* Psi, int m, 
   const int64_t n = (int64_t)m * m;
   hipLaunchKernelGGL(hermite_collapse_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, Phi, Psi, m, K, tau,
                      out);
+  return hipGetLastError();
+}
+
+hipError_t launch_vortex_phase(void* v, int is_f64, int d, const int64_t* dims, const double* winv, double s,
+                               hipStream_t st) {
+  Dims6 D;
+  int64_t count = 1;
+  for (int k = 0; k < 6; ++k) D.n[k] = k < d ? dims[k] : 1;
+  for (int k = 0; k < d; ++k) count *= dims[k];
+  const int64_t blocks = std::min<int64_t>((count + 255) / 256, 8192);
+  if (is_f64)
+    hipLaunchKernelGGL(vortex_phase_kernel<double>, dim3((unsigned)blocks), dim3(256), 0, st, (double*)v, count, d, D,
+                       winv, s);
+  else
+    hipLaunchKernelGGL(vortex_phase_kernel<float>, dim3((unsigned)blocks), dim3(256), 0, st, (float*)v, count, d, D,
+                       winv, s);
   return hipGetLastError();
 }
 

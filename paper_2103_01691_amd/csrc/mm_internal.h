@@ -202,6 +202,11 @@ hipError_t launch_expm_ps(double* P, const double* W, const double* X, const dou
 // FP64 device masters with ld = rows; out: m x m complex FP64 interleaved).
 hipError_t launch_hermite_collapse(const double* Phi, const double* Psi, int m, int K, double tau, double* out,
                                    hipStream_t s);
+// Exact nonlinear flow of the Section 4.5 vortex problem over time s on a
+// complex state (interleaved, d modes, column-major): v <- exp((i s/2)(1 -
+// W^-1 |v|^2)) v with W^-1 = prod_k winv[k * 4096 + i_k] (device array).
+hipError_t launch_vortex_phase(void* v, int is_f64, int d, const int64_t* dims, const double* winv, double s,
+                               hipStream_t st);
 // FP16X2 chain start: slots[0] = float bits of max |x_k| over `count` floats,
 // slots[1] = slots[2] = 0.  partial: >= norm_partials() words.
 hipError_t launch_maxabs(const float* x, int64_t count, uint32_t* partial, uint32_t* slots, hipStream_t s);

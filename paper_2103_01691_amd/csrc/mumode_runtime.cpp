@@ -102,6 +102,12 @@ struct mm_ctx_s {
   double* x2_stage = nullptr;    // pinned staging of x2
   hipEvent_t x2_ev = nullptr;    // the last upload from x2_stage
   std::vector<double> x2_nodes[MM_MAXD];   // nodes of the last upload, per mode
+  // vortex_strang_step: inverse dual-cell widths per mode (device, MM_MAXD *
+  // 4096 doubles), uploaded from pinned staging when the weights change
+  double* winv = nullptr;
+  double* winv_stage = nullptr;
+  hipEvent_t winv_ev = nullptr;
+  std::vector<double> winv_w[MM_MAXD];
   // batched integrator: work items of the last batch signature, its
   // launch groups and the captured per-step graph
   struct BatchGroup { mm::ModePlan plan; int ida, offset, count; };
@@ -731,6 +737,9 @@ mm_status mm_destroy(mm_ctx ctx) {
   if (ctx->x2) hipFree(ctx->x2);
   if (ctx->x2_stage) hipHostFree(ctx->x2_stage);
   if (ctx->x2_ev) hipEventDestroy(ctx->x2_ev);
+  if (ctx->winv) hipFree(ctx->winv);
+  if (ctx->winv_stage) hipHostFree(ctx->winv_stage);
+  if (ctx->winv_ev) hipEventDestroy(ctx->winv_ev);
   for (int k = 0; k < MM_MAXD; ++k)
     if (ctx->ho[k].master) hipFree(ctx->ho[k].master);
   if (ctx->bexec) hipGraphExecDestroy(ctx->bexec);
@@ -1197,6 +1206,66 @@ mm_status ho_strang_step(mm_ctx ctx, mm_tensor* psi, const mm_op* Phi_fwd, const
       if (ctx->chain_end == cur) ctx->chain_end = psi->data;
     }
   }
+  return MM_OK;
+}
+
+mm_status vortex_strang_step(mm_ctx ctx, mm_tensor* v, const mm_op* E, const double* const* w, double tau, int nsteps,
+                             mm_stream stream) {
+  if (!ctx) return MM_ERR_ARG;
+  mm_status st = check_tensor(ctx, v, "v");
+  if (st != MM_OK) return st;
+  if (!is_complex(v->dtype)) return fail(ctx, MM_ERR_DTYPE, "v must be complex");
+  if (!E || !w) return fail(ctx, MM_ERR_ARG, "E / w is NULL");
+  if (nsteps < 0) return fail(ctx, MM_ERR_ARG, "nsteps < 0");
+  if (!std::isfinite(tau)) return fail(ctx, MM_ERR_ARG, "tau not finite");
+  for (int k = 0; k < v->d; ++k) {
+    if (!E[k] || !w[k]) return fail(ctx, MM_ERR_ARG, "E[%d] / w[%d] is NULL", k, k);
+    if (E[k]->rows != E[k]->cols || E[k]->cols != v->dims[k])
+      return fail(ctx, MM_ERR_SHAPE, "E[%d] must be %lld x %lld", k, (long long)v->dims[k], (long long)v->dims[k]);
+    if (v->dims[k] > 4096) return fail(ctx, MM_ERR_SHAPE, "n_%d > 4096", k + 1);
+    st = check_op_dtype(ctx, E[k], v->dtype);
+    if (st != MM_OK) return st;
+    for (int64_t i = 0; i < v->dims[k]; ++i)
+      if (!(w[k][i] > 0.0) || !std::isfinite(w[k][i])) return fail(ctx, MM_ERR_ARG, "w[%d][%lld] not a positive width", k, (long long)i);
+  }
+  HIPCHK(ctx, hipSetDevice(ctx->device));
+  ctx->chain_end = nullptr;
+  hipStream_t s = (hipStream_t)stream;
+  if (nsteps == 0) return MM_OK;
+  if (!ctx->winv) {
+    if (hipMalloc((void**)&ctx->winv, sizeof(double) * MM_MAXD * 4096) != hipSuccess)
+      return fail(ctx, MM_ERR_NOMEM, "weight buffer");
+    if (hipHostMalloc((void**)&ctx->winv_stage, sizeof(double) * MM_MAXD * 4096, hipHostMallocDefault) != hipSuccess)
+      return fail(ctx, MM_ERR_NOMEM, "weight staging");
+    HIPCHK(ctx, hipEventCreateWithFlags(&ctx->winv_ev, hipEventDisableTiming));
+  }
+  bool changed = false;
+  for (int k = 0; k < v->d && !changed; ++k)
+    changed = ctx->winv_w[k].size() != (size_t)v->dims[k] ||
+              std::memcmp(ctx->winv_w[k].data(), w[k], sizeof(double) * v->dims[k]) != 0;
+  if (changed) {
+    HIPCHK(ctx, hipEventSynchronize(ctx->winv_ev));
+    for (int k = 0; k < MM_MAXD; ++k) ctx->winv_w[k].clear();
+    for (int k = 0; k < v->d; ++k) {
+      ctx->winv_w[k].assign(w[k], w[k] + v->dims[k]);
+      for (int64_t i = 0; i < v->dims[k]; ++i) ctx->winv_stage[(size_t)k * 4096 + i] = 1.0 / w[k][i];
+    }
+    HIPCHK(ctx, hipMemcpyAsync(ctx->winv, ctx->winv_stage, sizeof(double) * v->d * 4096, hipMemcpyHostToDevice, s));
+    HIPCHK(ctx, hipEventRecord(ctx->winv_ev, s));
+  }
+  const int f64 = is_f64(v->dtype) ? 1 : 0;
+  // merged steps N(tau/2) [L N(tau)]^(nsteps-1) L N(tau/2): N keeps |v|, so
+  // adjacent half steps compose; each N is one pass over the state (its
+  // coefficient depends on the position through W^-1), after which an FP16X2
+  // product starts a new running bound (a rotation can raise a component)
+  HIPCHK(ctx, mm::launch_vortex_phase(v->data, f64, v->d, v->dims, ctx->winv, 0.5 * tau, s));
+  for (int it = 0; it < nsteps; ++it) {
+    ctx->chain_end = nullptr;
+    st = sweep(ctx, v, E, 0.0, 0.0, s);
+    if (st != MM_OK) return st;
+    HIPCHK(ctx, mm::launch_vortex_phase(v->data, f64, v->d, v->dims, ctx->winv, it + 1 < nsteps ? tau : 0.5 * tau, s));
+  }
+  ctx->chain_end = nullptr;
   return MM_OK;
 }
 

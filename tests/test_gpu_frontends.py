@@ -118,3 +118,75 @@ def test_nonuniform_neumann_schroedinger_flow(ctx, prec):
     assert abs(mass / mass0 - 1.0) < (1e-12 if prec == "fp64" else 1e-5)
     for o in ops:
         o.destroy()
+
+
+def _vortex_problem(dims, alpha=2.0):
+    import synth
+    import paper_2103_01691_amd as mm
+    xs = [synth.graded_nodes(n, -20.0, 20.0, alpha) for n in dims]
+    Ml, Mo, ws = [], [], []
+    for x in xs:
+        m, _ = mm.nonuniform_neumann_d2(x)
+        mo, wo = op.nonuniform_neumann_d2(x)
+        Ml.append(m)
+        Mo.append(mo)
+        ws.append(wo)
+    W = ws[0][:, None, None] * ws[1][None, :, None] * ws[2][None, None, :]
+    return xs, Ml, Mo, ws, W
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3", "fp16x2"])
+def test_vortex_strang_step(ctx, prec):
+    # the Section 4.5 vortex pair on graded non-uniform nodes (a different
+    # count per mode, none a multiple of the tile edge), symmetrised variable
+    # v = W^(1/2) u: three Strang steps, nonlinear half steps merged
+    import synth
+    import paper_2103_01691_amd as mm
+    from oracle import schemes as sc
+    dims, tau, steps = (40, 36, 30), 0.1, 3
+    xs, Ml, Mo, ws, W = _vortex_problem(dims)
+    Eo = [op.exp_symmetric(m, 0.5j * tau) for m in Mo]
+    v0 = cast(np.sqrt(W) * synth.vortex_pair_initial(xs), prec, True)
+    note(f"vortex {prec}: oracle, {steps} steps")
+    ref = sc.vortex_strang(v0, Eo, 1.0 / W, tau, steps)
+    ops = [ctx.mm_op_prepare(mm.expm(m, 0.5j * tau), prec) for m in Ml]
+    v = to_gpu(v0, prec, True)
+    ctx.vortex_strang_step(v, ops, ws, tau, steps)
+    got = from_gpu(v)
+    err = rel(got, ref)
+    mass0 = float(np.sum(np.abs(v0) ** 2))
+    mass = ctx.mm_norm2(v, 1.0)
+    note(f"vortex {prec}: rel L2 {err:.3e}, weighted mass drift {abs(mass / mass0 - 1):.2e}")
+    assert err < 2 * steps * REL_TOL[prec]
+    # both parts of the splitting are unitary in v
+    assert abs(mass / mass0 - 1.0) < (1e-12 if prec == "fp64" else 1e-5)
+    for o in ops:
+        o.destroy()
+
+
+def test_vortex_background_steady_and_weights_reuploaded(ctx):
+    # u = 1: the Neumann Laplacian annihilates constants and the nonlinearity
+    # vanishes at |u| = 1, so steps leave v = W^(1/2) unchanged; then the same
+    # context with other nodes (other weights, same sizes) must use the new
+    # weights
+    import synth
+    import paper_2103_01691_amd as mm
+    from oracle import schemes as sc
+    dims, tau = (24, 20, 16), 0.1
+    for alpha in (2.0, 1.0):
+        xs, Ml, Mo, ws, W = _vortex_problem(dims, alpha)
+        ops = [ctx.mm_op_prepare(mm.expm(m, 0.5j * tau), "fp64") for m in Ml]
+        v0 = np.sqrt(W).astype(np.complex128)
+        v = to_gpu(v0, "fp64", True)
+        ctx.vortex_strang_step(v, ops, ws, tau, 4)
+        dev = np.max(np.abs(from_gpu(v) - v0)) / np.max(np.abs(v0))
+        u1 = np.sqrt(W) * synth.vortex_pair_initial(xs)
+        ref = sc.vortex_strang(u1, [op.exp_symmetric(m, 0.5j * tau) for m in Mo], 1.0 / W, tau, 2)
+        v = to_gpu(u1, "fp64", True)
+        ctx.vortex_strang_step(v, ops, ws, tau, 2)
+        err = rel(from_gpu(v), ref)
+        note(f"vortex alpha={alpha}: background deviation {dev:.2e}, vortex pair rel err {err:.3e}")
+        assert dev < 1e-12
+        assert err < 1e-12
+        for o in ops:
+            o.destroy()
