@@ -42,7 +42,9 @@ SPLIT_PRODUCTS = {"bf16x3": 6, "fp16x2": 3}        # MFMA products per algorithm
 KERNEL_SOURCES = ["paper_2103_01691_amd/csrc/mode_tile.h", "paper_2103_01691_amd/csrc/mm_internal.h",
                   "paper_2103_01691_amd/csrc/kern_bf16x3.hip", "paper_2103_01691_amd/csrc/kern_fp16x2.hip",
                   "paper_2103_01691_amd/csrc/kern_bf16x3_ida.hip", "paper_2103_01691_amd/csrc/kern_fp16x2_ida.hip",
-                  "paper_2103_01691_amd/csrc/kernels_common.hip", "paper_2103_01691_amd/build.py"]
+                  "paper_2103_01691_amd/csrc/kernels_common.hip", "paper_2103_01691_amd/build.py",
+                  "paper_2103_01691_amd/csrc/mode_gauss.h", "paper_2103_01691_amd/csrc/kern_bf16x3_g.hip",
+                  "paper_2103_01691_amd/csrc/kern_fp16x2_g.hip"]
 
 
 def kernel_source_hash():

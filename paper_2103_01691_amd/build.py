@@ -16,7 +16,7 @@ OBJ = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libmumode.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["kern_bf16x3.hip", "kern_fp16x2.hip", "kern_bf16x3_ida.hip", "kern_fp16x2_ida.hip", "kern_f32.hip",
+SOURCES = ["kern_bf16x3.hip", "kern_fp16x2.hip", "kern_bf16x3_g.hip", "kern_fp16x2_g.hip", "kern_bf16x3_ida.hip", "kern_fp16x2_ida.hip", "kern_f32.hip",
            "kern_f64.hip", "kern_bf16.hip", "kern_f32_ida.hip", "kern_f64_ida.hip", "kern_bf16_ida.hip", "kern_small.hip",
            "kernels_common.hip", "mumode_runtime.cpp", "host_math.cpp"]
 COMMON = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

@@ -16,6 +16,36 @@ namespace {
 
 // -------------------------------------------------------- preparation -----
 
+// The stored pieces of one operator value x at out[base] (piece p at
+// base + p * 64 * KPL).
+template <int PR>
+__device__ __forceinline__ void put_pieces(typename Tr<PR>::pc* __restrict__ out, int64_t base, double x,
+                                           int a_exp) {
+  constexpr int KPL = Tr<PR>::KPL, NPC = Tr<PR>::NPS;
+  if constexpr (PR == KP_F64) {
+    out[base] = x;
+  } else if constexpr (PR == KP_F32) {
+    out[base] = (float)x;
+  } else if constexpr (PR == KP_FP16X2) {
+    // stored pieces (h 2^11, l) of x 2^-a_exp = h + 2^-11 l; the residual
+    // is exact in FP64.  h 2^11 multiplies both state pieces, l the high
+    // one.
+    const double xs = ldexp(x, -a_exp);
+    const _Float16 h = (_Float16)(float)xs;
+    const _Float16 l = (_Float16)(float)((xs - (double)h) * 2048.0);
+    out[base] = (_Float16)((float)h * 2048.0f);
+    out[base + (int64_t)64 * KPL] = l;
+  } else {
+    double r = x;
+#pragma unroll
+    for (int p = 0; p < NPC; ++p) {
+      __bf16 h = (__bf16)(float)r;
+      out[base + (int64_t)p * 64 * KPL] = h;
+      r = r - (double)(float)h;
+    }
+  }
+}
+
 // One fragment slot s = (kb, mf, lane) of the prepared operator.
 template <int PR>
 __device__ __forceinline__ void prepare_slot(int64_t s, const double* __restrict__ master, int64_t rows,
@@ -64,28 +94,36 @@ __device__ __forceinline__ void prepare_slot(int64_t s, const double* __restrict
       }
     }
     const int64_t base = (((int64_t)kb * MFT + mf) * NPC) * 64 * KPL + lane * KPL + e;
-    if constexpr (PR == KP_F64) {
-      out[base] = x;
-    } else if constexpr (PR == KP_F32) {
-      out[base] = (float)x;
-    } else if constexpr (PR == KP_FP16X2) {
-      // stored pieces (h 2^11, l) of x 2^-a_exp = h + 2^-11 l; the residual
-      // is exact in FP64.  h 2^11 multiplies both state pieces, l the high
-      // one.
-      const double xs = ldexp(x, -a_exp);
-      const _Float16 h = (_Float16)(float)xs;
-      const _Float16 l = (_Float16)(float)((xs - (double)h) * 2048.0);
-      out[base] = (_Float16)((float)h * 2048.0f);
-      out[base + (int64_t)64 * KPL] = l;
-    } else {
-      double r = x;
-#pragma unroll
-      for (int p = 0; p < NPC; ++p) {
-        __bf16 h = (__bf16)(float)r;
-        out[base + (int64_t)p * 64 * KPL] = h;
-        r = r - (double)(float)h;
-      }
+    put_pieces<PR>(out, base, x, a_exp);
+  }
+}
+
+// Three-product (Gauss) preparation: slot ((jb * 3 + t) * MFT + mf, lane)
+// holds 8 columns of complex row mf * 32 + lane % 32 of Re L (t = 0), Im L
+// (t = 1) or Re L + Im L (t = 2), formed in FP64.
+template <int PR>
+__global__ void prepare_gauss_kernel(const double* __restrict__ master, int64_t rows, int64_t cols, int64_t ld,
+                                     void* __restrict__ outv, int JBT, int MFT, int a_exp) {
+  typedef typename Tr<PR>::pc pc;
+  constexpr int NPC = Tr<PR>::NPS;
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= (int64_t)JBT * 3 * MFT * 64) return;
+  const int lane = (int)(s % 64);
+  const int64_t t = s / 64;
+  const int mf = (int)(t % MFT);
+  const int64_t kbg = t / MFT;
+  const int ty = (int)(kbg % 3);
+  const int64_t jb = kbg / 3;
+  const int64_t i = (int64_t)mf * 32 + lane % 32;
+  pc* out = (pc*)outv;
+  for (int e = 0; e < 8; ++e) {
+    const int64_t j = jb * 16 + 8 * (lane / 32) + e;
+    double x = 0.0;
+    if (i < rows && j < cols) {
+      const double re = master[2 * (i + j * ld)], im = master[2 * (i + j * ld) + 1];
+      x = ty == 0 ? re : (ty == 1 ? im : re + im);
     }
+    put_pieces<PR>(out, ((kbg * MFT + mf) * NPC) * 64 * 8 + lane * 8 + e, x, a_exp);
   }
 }
 
@@ -369,11 +407,36 @@ size_t prepared_bytes(int prec, int KBT, int MFT) {
 }
 
 int num_classes(int prec) {
-  return (prec == KP_BF16X3 || prec == KP_FP16X2) ? 8 : 3;
+  return (prec == KP_BF16X3 || prec == KP_FP16X2) ? 10 : 3;
+}
+
+void gauss_blocks(int64_t rows, int64_t cols, int* JBT, int* MFT) {
+  *JBT = (int)(((cols + 15) / 16 + 3) / 4 * 4);
+  *MFT = (int)(((rows + 31) / 32 + 7) / 8 * 8);
+}
+
+size_t gauss_prepared_bytes(int prec, int JBT, int MFT) {
+  const int npc = prec == KP_BF16X3 ? 3 : 2;
+  return (size_t)JBT * 3 * MFT * npc * 64 * 8 * 2;
+}
+
+hipError_t launch_prepare_gauss(int prec, const double* master, int64_t rows, int64_t cols, int64_t ld, void* out,
+                                int JBT, int MFT, int a_exp, hipStream_t s) {
+  const int64_t slots = (int64_t)JBT * 3 * MFT * 64;
+  const dim3 grid((unsigned)((slots + 255) / 256));
+  if (prec == KP_FP16X2)
+    hipLaunchKernelGGL(prepare_gauss_kernel<KP_FP16X2>, grid, dim3(256), 0, s, master, rows, cols, ld, out, JBT, MFT,
+                       a_exp);
+  else if (prec == KP_BF16X3)
+    hipLaunchKernelGGL(prepare_gauss_kernel<KP_BF16X3>, grid, dim3(256), 0, s, master, rows, cols, ld, out, JBT, MFT,
+                       a_exp);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
 }
 
 bool plan_mode(const ModeArgs& a, int prec, int cplx, bool want_pro, bool want_epi, bool fcontig_ok,
-               bool kcontig_ok, ModePlan* plan, bool batch, int force_cls) {
+               bool kcontig_ok, ModePlan* plan, bool batch, int force_cls, bool gauss_ok) {
   FragGeom g = frag_geom(prec);
   // two interleaved real fibres (P == 2), 16-byte aligned runs of 8 rows
   const bool pair_ok = !kcontig_ok && !cplx && a.P == 2 && a.Kr % 8 == 0;
@@ -386,6 +449,10 @@ bool plan_mode(const ModeArgs& a, int prec, int cplx, bool want_pro, bool want_e
   const int rw = t0.WMF * g.MB;                      // rows per wave
   const bool split = prec == KP_BF16X3 || prec == KP_FP16X2;
   TileShape tf;
+  // three-product classes only where the caller has the operator's Gauss
+  // preparation (complex operator and state, no batch, no identity split)
+  if (force_cls >= GAUSS_CLS0 && !(gauss_ok && cplx && !batch && (load == KL_KCONTIG || load == KL_FCONTIG)))
+    force_cls = -1;
   if (force_cls >= 0 && tile_shape(prec, force_cls, &tf) &&
       (batch ? batch_kind_any(prec, cplx, load, force_cls)
              : pick_kernel_any(prec, cplx, load, pro, epi, force_cls) != nullptr)) {
@@ -404,6 +471,7 @@ bool plan_mode(const ModeArgs& a, int prec, int cplx, bool want_pro, bool want_e
   plan->pro = pro;
   plan->epi = epi;
   plan->cls = cls;
+  plan->gauss = cls >= GAUSS_CLS0 ? 1 : 0;
   plan->nt = t.WN * t.WNF * g.NB;
   plan->threads = 64 * t.WM * t.WN;
   plan->mt_rows = t.WM * t.WMF * g.MB;

@@ -97,6 +97,22 @@ bool tile_shape_bf16(int cls, TileShape* out);
 
 bool tile_shape(int prec, int cls, TileShape* out);
 
+// Three-product (Gauss) complex split kernels (kern_<prec>_g.hip), tile
+// classes 8 and 9 of BF16X3 and FP16X2: complex operator and state,
+// contiguous or strided fibres, operator prepared by launch_prepare_gauss.
+KernFn pick_gauss_bf16x3(int ld, int pro, int epi, int cls, int full);
+KernFn pick_gauss_fp16x2(int ld, int pro, int epi, int cls, int full);
+bool gauss_shape_bf16x3(int cls, TileShape* out);
+bool gauss_shape_fp16x2(int cls, TileShape* out);
+constexpr int GAUSS_CLS0 = 8;
+// Padded complex K-blocks (16 columns, a multiple of 4) and complex-row
+// fragments (32 rows, a multiple of 8) of a three-product operator.
+void gauss_blocks(int64_t rows, int64_t cols, int* JBT, int* MFT);
+size_t gauss_prepared_bytes(int prec, int JBT, int MFT);
+// master: complex FP64, column-major with leading dimension ld.
+hipError_t launch_prepare_gauss(int prec, const double* master, int64_t rows, int64_t cols, int64_t ld, void* out,
+                                int JBT, int MFT, int a_exp, hipStream_t s);
+
 // Merged batched launch: one kernel per precision runs work items of every
 // kind (complex / real, contiguous / strided fibres, tile class 0..2; all
 // 256 threads), so every instance tile of one mode goes in a single launch.
@@ -120,6 +136,7 @@ struct ModePlan {
   int mt_rows;         // real rows covered by one workgroup (multiple of MB)
   bool covers_all_rows;
   int full;            // every tile complete and output offsets fit 32 bits
+  int gauss;           // three-product kernel: the operator's Gauss preparation
 };
 
 // Fill `plan` for the given problem; returns false if no kernel fits.
@@ -127,7 +144,8 @@ struct ModePlan {
 // force_cls >= 0: use that tile class if an instance exists for the problem
 // (the autotuner's choice), else fall back to the built-in choice.
 bool plan_mode(const ModeArgs& a, int prec, int cplx, bool want_pro, bool want_epi,
-               bool fcontig_ok, bool kcontig_ok, ModePlan* plan, bool batch = false, int force_cls = -1);
+               bool fcontig_ok, bool kcontig_ok, ModePlan* plan, bool batch = false, int force_cls = -1,
+               bool gauss_ok = false);
 // Number of tile classes of a precision (classes 0 .. n-1).
 int num_classes(int prec);
 // start / stop (optional): events recorded by the launch itself

@@ -37,6 +37,11 @@ struct mm_op_s {
   void* prep_c = nullptr;        // real master promoted to complex (lazily)
   int KBT_c = 0, MFT_c = 0;
   double* dev_master_c = nullptr;
+  // three-product (Gauss) preparation of a complex split operator: Re L, Im L
+  // and Re L + Im L (none for real operators or the identity split)
+  void* prep_g = nullptr;
+  int JBT_g = 0, MFT_g = 0;
+  int a_exp_g = 0;               // FP16X2: scale chosen from max(|Re|, |Im|, |Re + Im|)
 };
 
 struct mm_ctx_s {
@@ -264,25 +269,13 @@ mm_status run_mode(mm_ctx ctx, const void* in, void* out, const int64_t* dims, i
   // promoted copy of the operator).
   const bool rview = !L->cplx && is_complex(dt) && !batch && s_pre == 0.0 && s_post == 0.0 && !prep_override;
   const bool cplx = is_complex(dt) && !rview;
-  void* prep = nullptr;
-  int KBT = 0, MFT = 0;
-  if (prep_override) {
-    prep = (void*)prep_override;
-    KBT = L->KBT;
-    MFT = L->MFT;
-  } else if (!dry) {
-    mm_status st = ensure_prepared(ctx, L, cplx, s, &prep, &KBT, &MFT);
-    if (st != MM_OK) return st;
-  } else {
-    mm::op_blocks(kprec(L->prec), (cplx ? 2 : 1) * L->rows, (cplx ? 2 : 1) * L->cols, &KBT, &MFT);
-  }
   mm::ModeArgs a;
   int64_t P = rview ? 2 : 1, Q = 1;
   for (int k = 0; k < mu - 1; ++k) P *= dims[k];
   for (int k = mu; k < d; ++k) Q *= dims[k];
   a.in = in;
   a.out = out;
-  a.A = prep;
+  a.A = nullptr;
   a.P = P;
   a.Q = Q;
   a.F = P * Q;
@@ -290,8 +283,6 @@ mm_status run_mode(mm_ctx ctx, const void* in, void* out, const int64_t* dims, i
   a.m = (int)L->rows;
   a.Kr = (cplx ? 2 : 1) * a.n;
   a.Mr = (cplx ? 2 : 1) * a.m;
-  a.KBT = KBT;
-  a.MFT = MFT;
   a.s_pre = s_pre;
   a.s_post = s_post;
   a.smax_in = nullptr;
@@ -309,9 +300,12 @@ mm_status run_mode(mm_ctx ctx, const void* in, void* out, const int64_t* dims, i
     auto it = ctx->tune.find(ctx->last_key);
     if (it != ctx->tune.end()) force = it->second.first;
   }
+  // three-product kernels: complex operator with its Gauss preparation,
+  // single-tensor products, whole staging tiles of 8 entries
+  const bool gauss_ok = L->prep_g && cplx && !batch && !prep_override && !args_out && a.n % 8 == 0;
   mm::ModePlan plan;
   if (!mm::plan_mode(a, kprec(L->prec), cplx ? 1 : 0, s_pre != 0.0, s_post != 0.0, fcontig, kcontig, &plan, batch,
-                     force))
+                     force, gauss_ok))
     return fail(ctx, MM_ERR_UNSUPPORTED, "no kernel plan for this shape");
   // batched work items run in place, so each must own all rows of its
   // fibres: a tuned class that splits the rows gives way to the built-in one
@@ -319,6 +313,26 @@ mm_status run_mode(mm_ctx ctx, const void* in, void* out, const int64_t* dims, i
       !mm::plan_mode(a, kprec(L->prec), cplx ? 1 : 0, s_pre != 0.0, s_post != 0.0, fcontig, kcontig, &plan, batch,
                      -1))
     return fail(ctx, MM_ERR_UNSUPPORTED, "no kernel plan for this shape");
+  if (plan.gauss) {
+    a.A = L->prep_g;
+    a.KBT = L->JBT_g;
+    a.MFT = L->MFT_g;
+    a.a_exp = L->a_exp_g;
+  } else if (prep_override) {
+    a.A = prep_override;
+    a.KBT = L->KBT;
+    a.MFT = L->MFT;
+  } else if (!dry) {
+    void* prep = nullptr;
+    int KBT = 0, MFT = 0;
+    mm_status st = ensure_prepared(ctx, L, cplx, s, &prep, &KBT, &MFT);
+    if (st != MM_OK) return st;
+    a.A = prep;
+    a.KBT = KBT;
+    a.MFT = MFT;
+  } else {
+    mm::op_blocks(kprec(L->prec), a.Mr, a.Kr, &a.KBT, &a.MFT);
+  }
   if (plan_out) *plan_out = plan;
   if (args_out) *args_out = a;
   if (dry) return MM_OK;
@@ -717,6 +731,7 @@ mm_status mm_op_destroy(mm_ctx ctx, mm_op op) {
   if (op->dev_master) hipFree(op->dev_master);
   if (op->prep) hipFree(op->prep);
   if (op->prep_c) hipFree(op->prep_c);
+  if (op->prep_g) hipFree(op->prep_g);
   if (op->dev_master_c) hipFree(op->dev_master_c);
   delete op;
   return MM_OK;
@@ -814,6 +829,19 @@ mm_status mm_op_prepare_ex(mm_ctx ctx, const mm_matrix* M, mm_prec prec, unsigne
   HIPCHK(ctx, hipMemcpy(op->dev_master, host.data(), host.size() * sizeof(double), hipMemcpyHostToDevice));
   HIPCHK(ctx, mm::launch_prepare(kp, cplx, op->dev_master, op->rows, op->cols, op->rows, mm::PhaseScale(),
                                  op->prep, op->KBT, op->MFT, 0, op->a_exp));
+  if (cplx && !idsplit && (kp == mm::KP_FP16X2 || kp == mm::KP_BF16X3)) {
+    // the three-product form, prepared with the operator so that no product
+    // call allocates
+    double gmax = 0.0;
+    for (size_t e = 0; e + 1 < host.size(); e += 2)
+      gmax = std::max(gmax, std::max(std::fabs(host[e]), std::max(std::fabs(host[e + 1]), std::fabs(host[e] + host[e + 1]))));
+    op->a_exp_g = kp == mm::KP_FP16X2 ? mm::fp16x2_op_exp(gmax) : 0;
+    mm::gauss_blocks(op->rows, op->cols, &op->JBT_g, &op->MFT_g);
+    if (hipMalloc(&op->prep_g, mm::gauss_prepared_bytes(kp, op->JBT_g, op->MFT_g)) != hipSuccess)
+      return fail(ctx, MM_ERR_NOMEM, "operator buffers");
+    HIPCHK(ctx, mm::launch_prepare_gauss(kp, op->dev_master, op->rows, op->cols, op->rows, op->prep_g, op->JBT_g,
+                                         op->MFT_g, op->a_exp_g, 0));
+  }
   HIPCHK(ctx, hipDeviceSynchronize());
   *out = op;
   return MM_OK;

@@ -1,8 +1,9 @@
 """GPU parity of the kernel instances the benchmark times.
 
 The 3-D GPE Strang step at n = 256 runs every split tile class the
-autotuner may choose (0, 3, 4, 5, 6, 7; classes 1 and 2 have no fused-phase
-instances; class 7 covers half the rows, so its products run out of place)
+autotuner may choose (0, 3, 4, 5, 6, 7 and the three-product classes 8, 9;
+classes 1 and 2 have no fused-phase instances; class 7 covers half the rows,
+so its products run out of place)
 with the nonlinear phase fused into the prologue of each step's
 first product and the epilogue of the last, and with the full-tile epilogue
 (every tile complete at n = 256).  Two steps, so that the prologue runs with
@@ -53,7 +54,7 @@ def _tune_file(path, prec, cls):
 
 
 @pytest.mark.parametrize("prec", ["fp16x2", "bf16x3"])
-@pytest.mark.parametrize("cls", [0, 3, 4, 5, 6, 7])
+@pytest.mark.parametrize("cls", [0, 3, 4, 5, 6, 7, 8, 9])
 def test_gpe_256_every_phase_class(ctx, problem, tmp_path, prec, cls):
     import paper_2103_01691_amd as mm
     psi0, ref = problem

@@ -43,7 +43,7 @@ def _problem(prec):
 
 
 @pytest.mark.parametrize("prec", ["bf16x3", "fp16x2"])
-@pytest.mark.parametrize("cls", list(range(8)))
+@pytest.mark.parametrize("cls", list(range(10)))
 def test_every_split_class_matches_oracle(ctx, tmp_path, prec, cls):
     U, E = _problem(prec)
     f = tmp_path / "t.txt"
@@ -57,6 +57,40 @@ def test_every_split_class_matches_oracle(ctx, tmp_path, prec, cls):
     ctx.mm_tune_clear()
     note(f"forced class {cls} {prec} rel err {err:.3e}")
     assert err < REL_TOL[prec]
+
+
+@pytest.mark.parametrize("prec", ["bf16x3", "fp16x2"])
+@pytest.mark.parametrize("cls", [8, 9])
+@pytest.mark.parametrize("dims", [(200, 136), (40, 48, 24), (8, 16)])
+def test_three_product_classes_ragged(ctx, tmp_path, prec, cls, dims):
+    # the three-product (Gauss) classes on fibre counts that leave a partial
+    # fibre tile, row counts below / not a multiple of the 256-row tile, and
+    # mode lengths that end inside an LDS chunk; each product once with the
+    # fused phases (prologue on mode 1, epilogue on the last mode) through
+    # one GPE step, once without through an expstep
+    from oracle import schemes as sc
+    g = synth.rng(1102, PREC_CODE[prec] * 10 + cls)
+    U = cast(synth.random_tensor(dims, True, g), prec, True)
+    E = [synth.random_matrix(n, n, True, g) for n in dims]
+    f = tmp_path / "t.txt"
+    f.write_text("mumode-tune 1\n" + "".join(" ".join(map(str, k)) + f" {cls} 0.0\n" for k in _keys(prec, dims)))
+    ctx.mm_tune_clear()
+    ctx.mm_tune_load(f)
+    ops = [ctx.mm_op_prepare(e, prec) for e in E]
+    T = to_gpu(U, prec, True)
+    ctx.mumode_expstep(T, ops, 1)
+    err = rel(from_gpu(T), om.expstep(U, E, 1))
+    T = to_gpu(U, prec, True)
+    ctx.mm_profile_begin()
+    ctx.gpe_strang_step(T, ops, 0.01, 3.0, 1)
+    kinds = [k for k, _ in ctx.mm_profile_end()]
+    err_ph = rel(from_gpu(T), sc.gpe_strang(U, E, 0.01, 3.0, 1))
+    ctx.mm_tune_clear()
+    note(f"three-product class {cls} {prec} dims {dims}: rel err {err:.3e}, with phases {err_ph:.3e}, kinds {kinds}")
+    assert err < REL_TOL[prec]
+    assert err_ph < REL_TOL[prec]
+    # first product with the prologue phase, last with the epilogue
+    assert kinds[0] % 10 == 2 and kinds[-1] % 10 == 1
 
 
 @pytest.mark.parametrize("prec", ["fp32", "fp16x2"])
@@ -93,7 +127,7 @@ def test_tune_load_rejects_malformed(ctx, tmp_path):
     f.write_text("something else\n")
     with pytest.raises(mm.MumodeError):
         ctx.mm_tune_load(f)
-    f.write_text("mumode-tune 1\n2 1 0 512 512 100 9 1.0\n")   # class out of range
+    f.write_text("mumode-tune 1\n2 1 0 512 512 100 99 1.0\n")   # class out of range
     with pytest.raises(mm.MumodeError):
         ctx.mm_tune_load(f)
     assert ctx.mm_tune_entries() == []
