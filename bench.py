@@ -491,7 +491,9 @@ def main():
             "unit": "TFLOP/s", "frac": (achieved / PEAK["bf16"]) if achieved else None, "traffic": traffic,
             "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE x2 + WRITE_SIZE x1, copy-calibrated)",
             "algorithmic_bytes_per_launch": BYTES_PER_PRODUCT,
-            "kernel": f"mode_kernel (split {split}, complex 256x256 operator, one mu-mode product per launch)",
+            "kernel": ("mode_kernel" + (" and gauss_kernel (three-product classes)"
+                                        if any(t["class"] >= 8 for t in tuned) else "")
+                       + f" (split {split}, complex 256x256 operator, one mu-mode product per launch)"),
             "avg_launch_ms": avg_launch_ms, "launches": len(prod_ms), "per_kind_ms": per_kind,
             "executed_mfma_frac": (SPLIT_PRODUCTS[split] * achieved / PEAK["bf16"]) if achieved else None,
             "mfma_busy_frac_counters": counter_traffic(f"mode_kernel_{split}_gpe3d_n256.md", "mfma_busy_frac"),
