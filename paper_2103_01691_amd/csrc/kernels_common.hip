@@ -407,7 +407,7 @@ size_t prepared_bytes(int prec, int KBT, int MFT) {
 }
 
 int num_classes(int prec) {
-  return (prec == KP_BF16X3 || prec == KP_FP16X2) ? 10 : 3;
+  return (prec == KP_BF16X3 || prec == KP_FP16X2) ? 11 : 3;
 }
 
 void gauss_blocks(int64_t rows, int64_t cols, int* JBT, int* MFT) {
@@ -451,9 +451,13 @@ bool plan_mode(const ModeArgs& a, int prec, int cplx, bool want_pro, bool want_e
   TileShape tf;
   // three-product classes only where the caller has the operator's Gauss
   // preparation (complex operator and state, no batch, no identity split)
-  if (force_cls >= GAUSS_CLS0 && !(gauss_ok && cplx && !batch && (load == KL_KCONTIG || load == KL_FCONTIG)))
+  if (is_gauss_class(force_cls) && !(gauss_ok && cplx && !batch && (load == KL_KCONTIG || load == KL_FCONTIG)))
     force_cls = -1;
-  if (force_cls >= 0 && tile_shape(prec, force_cls, &tf) &&
+  // the prepared operator's K-blocks must make whole LDS chunks of the class
+  // (three-product classes: their own padding, a multiple of every chunk)
+  int kbt = 0, mft = 0;
+  op_blocks(prec, a.Mr, a.Kr, &kbt, &mft);
+  if (force_cls >= 0 && tile_shape(prec, force_cls, &tf) && (is_gauss_class(force_cls) || kbt % tf.KCH == 0) &&
       (batch ? batch_kind_any(prec, cplx, load, force_cls)
              : pick_kernel_any(prec, cplx, load, pro, epi, force_cls) != nullptr)) {
     cls = force_cls;
@@ -471,7 +475,7 @@ bool plan_mode(const ModeArgs& a, int prec, int cplx, bool want_pro, bool want_e
   plan->pro = pro;
   plan->epi = epi;
   plan->cls = cls;
-  plan->gauss = cls >= GAUSS_CLS0 ? 1 : 0;
+  plan->gauss = is_gauss_class(cls) ? 1 : 0;
   plan->nt = t.WN * t.WNF * g.NB;
   plan->threads = 64 * t.WM * t.WN;
   plan->mt_rows = t.WM * t.WMF * g.MB;

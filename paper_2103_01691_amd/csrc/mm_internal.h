@@ -104,7 +104,7 @@ KernFn pick_gauss_bf16x3(int ld, int pro, int epi, int cls, int full);
 KernFn pick_gauss_fp16x2(int ld, int pro, int epi, int cls, int full);
 bool gauss_shape_bf16x3(int cls, TileShape* out);
 bool gauss_shape_fp16x2(int cls, TileShape* out);
-constexpr int GAUSS_CLS0 = 8;
+inline bool is_gauss_class(int cls) { return cls == 8 || cls == 9; }
 // Padded complex K-blocks (16 columns, a multiple of 4) and complex-row
 // fragments (32 rows, a multiple of 8) of a three-product operator.
 void gauss_blocks(int64_t rows, int64_t cols, int* JBT, int* MFT);

@@ -997,7 +997,11 @@ void mode_kernel(ModeArgs a) {
 // K-blocks per LDS chunk), classes 5 and 6 split shapes with 64 fibres sized
 // for two workgroups per CU (OCC = 2), class 7 a small split tile (4 x 64
 // rows, 32 fibres, two workgroups per CU) for modes of at most 128 complex
-// entries, where larger tiles leave too few workgroups to cover latency.
+// entries, where larger tiles leave too few workgroups to cover latency;
+// class 10 the same tile with the whole K range of a 128-entry complex mode
+// in one LDS chunk (FP16X2; BF16X3: half of it), so a tile waits for one HBM
+// round trip instead of one per chunk.  (Classes 8 and 9 are the
+// three-product kernels of mode_gauss.h.)
 template <int PR, int CLS> struct Cfg;
 template <> struct Cfg<KP_F64, 0> { static constexpr int WMF = 8, WNF = 2, WM = 4, WN = 1, KCH = 8; static constexpr int OCC = 1; };
 template <> struct Cfg<KP_F64, 1> { static constexpr int WMF = 8, WNF = 1, WM = 2, WN = 2, KCH = 8; static constexpr int OCC = 1; };
@@ -1013,6 +1017,7 @@ template <> struct Cfg<KP_BF16X3, 4> { static constexpr int WMF = 4, WNF = 4, WM
 template <> struct Cfg<KP_BF16X3, 5> { static constexpr int WMF = 4, WNF = 2, WM = 4, WN = 1, KCH = 4; static constexpr int OCC = 2; };
 template <> struct Cfg<KP_BF16X3, 6> { static constexpr int WMF = 4, WNF = 2, WM = 4, WN = 1, KCH = 2; static constexpr int OCC = 2; };
 template <> struct Cfg<KP_BF16X3, 7> { static constexpr int WMF = 2, WNF = 1, WM = 4, WN = 1, KCH = 4; static constexpr int OCC = 2; };
+template <> struct Cfg<KP_BF16X3, 10> { static constexpr int WMF = 2, WNF = 1, WM = 4, WN = 1, KCH = 8; static constexpr int OCC = 2; };
 template <> struct Cfg<KP_FP16X2, 0> { static constexpr int WMF = 4, WNF = 2, WM = 4, WN = 1, KCH = 4; static constexpr int OCC = 1; };
 template <> struct Cfg<KP_FP16X2, 1> { static constexpr int WMF = 4, WNF = 1, WM = 2, WN = 2, KCH = 4; static constexpr int OCC = 1; };
 template <> struct Cfg<KP_FP16X2, 2> { static constexpr int WMF = 4, WNF = 1, WM = 1, WN = 4, KCH = 4; static constexpr int OCC = 1; };
@@ -1021,13 +1026,14 @@ template <> struct Cfg<KP_FP16X2, 4> { static constexpr int WMF = 4, WNF = 4, WM
 template <> struct Cfg<KP_FP16X2, 5> { static constexpr int WMF = 4, WNF = 2, WM = 4, WN = 1, KCH = 4; static constexpr int OCC = 2; };
 template <> struct Cfg<KP_FP16X2, 6> { static constexpr int WMF = 4, WNF = 2, WM = 4, WN = 1, KCH = 2; static constexpr int OCC = 2; };
 template <> struct Cfg<KP_FP16X2, 7> { static constexpr int WMF = 2, WNF = 1, WM = 4, WN = 1, KCH = 4; static constexpr int OCC = 2; };
+template <> struct Cfg<KP_FP16X2, 10> { static constexpr int WMF = 2, WNF = 1, WM = 4, WN = 1, KCH = 16; static constexpr int OCC = 2; };
 template <> struct Cfg<KP_BF16, 0> { static constexpr int WMF = 4, WNF = 2, WM = 4, WN = 1, KCH = 4; static constexpr int OCC = 1; };
 template <> struct Cfg<KP_BF16, 1> { static constexpr int WMF = 4, WNF = 1, WM = 2, WN = 2, KCH = 4; static constexpr int OCC = 1; };
 template <> struct Cfg<KP_BF16, 2> { static constexpr int WMF = 4, WNF = 1, WM = 1, WN = 4, KCH = 4; static constexpr int OCC = 1; };
 
 template <int PR> struct NumCls { static constexpr int N = 3; };
-template <> struct NumCls<KP_BF16X3> { static constexpr int N = 8; };
-template <> struct NumCls<KP_FP16X2> { static constexpr int N = 8; };
+template <> struct NumCls<KP_BF16X3> { static constexpr int N = 11; };
+template <> struct NumCls<KP_FP16X2> { static constexpr int N = 11; };
 
 template <int PR, int CLS> TileShape shape_of() {
   typedef Cfg<PR, CLS> C;
@@ -1091,6 +1097,7 @@ KernFn pick_kernel(int cplx, int ld, int pro, int epi, int cls, int full) {
         case 5: if (ld == KL_KCONTIG) MM_PH(true, KL_KCONTIG, 5); else MM_PH(true, KL_FCONTIG, 5);
         case 6: if (ld == KL_KCONTIG) MM_PH(true, KL_KCONTIG, 6); else MM_PH(true, KL_FCONTIG, 6);
         case 7: if (ld == KL_KCONTIG) MM_PH(true, KL_KCONTIG, 7); else MM_PH(true, KL_FCONTIG, 7);
+        case 10: if (ld == KL_KCONTIG) MM_PH(true, KL_KCONTIG, 10); else MM_PH(true, KL_FCONTIG, 10);
         default: return nullptr;
       }
     }
@@ -1136,6 +1143,7 @@ bool shape_table(int cls, TileShape* out) {
       case 5: *out = shape_of<PR, 5>(); return true;
       case 6: *out = shape_of<PR, 6>(); return true;
       case 7: *out = shape_of<PR, 7>(); return true;
+      case 10: *out = shape_of<PR, 10>(); return true;
       default: break;
     }
   }

@@ -54,7 +54,7 @@ def _tune_file(path, prec, cls):
 
 
 @pytest.mark.parametrize("prec", ["fp16x2", "bf16x3"])
-@pytest.mark.parametrize("cls", [0, 3, 4, 5, 6, 7, 8, 9])
+@pytest.mark.parametrize("cls", [0, 3, 4, 5, 6, 7, 8, 9, 10])
 def test_gpe_256_every_phase_class(ctx, problem, tmp_path, prec, cls):
     import paper_2103_01691_amd as mm
     psi0, ref = problem
