@@ -144,6 +144,24 @@ __global__ void prepare_multi_kernel(PrepJobs jobs) {
                    p.out, p.KBT, p.MFT, p.a_exp);
 }
 
+// Per-step operators of the time-dependent harmonic-oscillator splitting
+// (blockIdx.y = step * modes + entry).
+template <int PR>
+__global__ void prepare_steps_kernel(StepPrep p) {
+  const int e = (int)(blockIdx.y % p.modes);
+  const int st = (int)(blockIdx.y / p.modes);
+  const StepPrepMode& m = p.m[e];
+  const double t = p.t0 + st * p.tau;
+  const double th = t + 0.5 * p.tau;
+  PhaseScale ph;
+  ph.rx2 = m.x2;
+  ph.cx2 = m.x2;
+  ph.cc = 0.5 * p.eps * (cos(t) - cos(th));           // first half step: columns
+  ph.rc = 0.5 * p.eps * (cos(th) - cos(t + p.tau));   // second half step: rows
+  prepare_slot<PR>((int64_t)blockIdx.x * blockDim.x + threadIdx.x, m.master, m.n, m.n, m.n, 1, ph,
+                   m.out + (size_t)st * m.stride, m.KBT, m.MFT, m.a_exp);
+}
+
 // ------------------------------------------------------------- norm2 ------
 
 constexpr int NORM_BLOCKS = 1024;
@@ -534,6 +552,21 @@ hipError_t launch_prepare_multi(int prec, const PrepJobs& jobs, hipStream_t s) {
     case KP_BF16X3: hipLaunchKernelGGL(prepare_multi_kernel<KP_BF16X3>, grid, dim3(threads), 0, s, jobs); break;
     case KP_FP16X2: hipLaunchKernelGGL(prepare_multi_kernel<KP_FP16X2>, grid, dim3(threads), 0, s, jobs); break;
     default: hipLaunchKernelGGL(prepare_multi_kernel<KP_BF16>, grid, dim3(threads), 0, s, jobs); break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_prepare_steps(int prec, const StepPrep& p, hipStream_t s) {
+  if (p.modes < 1 || p.modes > MAX_STEP_MODES || p.steps < 1) return hipErrorInvalidValue;
+  int64_t slots = 0;
+  for (int k = 0; k < p.modes; ++k) slots = std::max(slots, (int64_t)p.m[k].KBT * p.m[k].MFT * 64);
+  const dim3 grid((unsigned)((slots + 255) / 256), (unsigned)(p.modes * p.steps));
+  switch (prec) {
+    case KP_F64: hipLaunchKernelGGL(prepare_steps_kernel<KP_F64>, grid, dim3(256), 0, s, p); break;
+    case KP_F32: hipLaunchKernelGGL(prepare_steps_kernel<KP_F32>, grid, dim3(256), 0, s, p); break;
+    case KP_BF16X3: hipLaunchKernelGGL(prepare_steps_kernel<KP_BF16X3>, grid, dim3(256), 0, s, p); break;
+    case KP_FP16X2: hipLaunchKernelGGL(prepare_steps_kernel<KP_FP16X2>, grid, dim3(256), 0, s, p); break;
+    default: hipLaunchKernelGGL(prepare_steps_kernel<KP_BF16>, grid, dim3(256), 0, s, p); break;
   }
   return hipGetLastError();
 }

@@ -197,6 +197,29 @@ struct PrepJobs {
 // Up to MAX_PREP_JOBS preparations of one precision in one launch.
 hipError_t launch_prepare_multi(int prec, const PrepJobs& jobs, hipStream_t s);
 
+// The collapsed harmonic-oscillator propagators of `steps` consecutive steps
+// of the time-dependent splitting, for up to 6 modes of one precision, in
+// one launch: step s, entry e gets the diagonal phase factors
+// exp(-i ca x_i^2) on its rows and exp(-i cb x_j^2) on its columns, where
+// cb and ca are the potential's flows over the step's two halves,
+// (eps/2)(cos t - cos(t + tau/2)) and (eps/2)(cos(t + tau/2) - cos(t + tau))
+// with t = t0 + s tau, formed on the device.
+constexpr int MAX_STEP_MODES = 6;
+struct StepPrepMode {
+  const double* master = nullptr;   // complex FP64, n x n, ld = n
+  int64_t n = 0;
+  const double* x2 = nullptr;       // squared nodes of the mode
+  char* out = nullptr;              // step s at out + s * stride
+  size_t stride = 0;
+  int KBT = 0, MFT = 0, a_exp = 0;
+};
+struct StepPrep {
+  StepPrepMode m[MAX_STEP_MODES];
+  int modes = 0, steps = 0;
+  double t0 = 0.0, tau = 0.0, eps = 0.0;
+};
+hipError_t launch_prepare_steps(int prec, const StepPrep& p, hipStream_t s);
+
 // Convert an FP64 master (device, column-major, ld) into fragment order.
 // a_exp (FP16X2 only): the pieces represent master * 2^-a_exp.
 hipError_t launch_prepare(int prec, int cplx, const double* master, int64_t rows, int64_t cols,

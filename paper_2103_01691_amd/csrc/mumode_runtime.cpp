@@ -1105,8 +1105,6 @@ mm_status ho_strang_step(mm_ctx ctx, mm_tensor* psi, const mm_op* Phi_fwd, const
   HIPCHK(ctx, hipSetDevice(ctx->device));
   ctx->chain_end = nullptr;
   hipStream_t s = (hipStream_t)stream;
-  bool one_prec = psi->d <= mm::MAX_PREP_JOBS;
-  for (int k = 1; k < psi->d; ++k) one_prec = one_prec && Phi_fwd[k]->prec == Phi_fwd[0]->prec;
   // the collapsed propagators of this tau, formed on the device once per
   // (operators, tau, precision)
   for (int k = 0; k < psi->d; ++k) {
@@ -1156,65 +1154,74 @@ mm_status ho_strang_step(mm_ctx ctx, mm_tensor* psi, const mm_op* Phi_fwd, const
     HIPCHK(ctx, hipMemcpyAsync(ctx->x2, ctx->x2_stage, sizeof(double) * psi->d * 4096, hipMemcpyHostToDevice, s));
     HIPCHK(ctx, hipEventRecord(ctx->x2_ev, s));
   }
+  // per-step operators, prepared for blocks of up to 32 steps (and at most
+  // 64 MiB) in one launch per precision, so no preparation sits between the
+  // products of a step; without the time-dependent potential (eps = 0) they
+  // are the same every step and are prepared once
+  size_t need[MM_MAXD];
+  size_t per_step = 0;
   for (int k = 0; k < psi->d; ++k) {
     const mm_op_s& L = ctx->ho[k].op;
-    const size_t need = mm::prepared_bytes(kprec(L.prec), L.KBT, L.MFT);
-    if (ctx->step_prep_bytes[k] < need) {
+    need[k] = (mm::prepared_bytes(kprec(L.prec), L.KBT, L.MFT) + 255) / 256 * 256;
+    per_step += need[k];
+  }
+  int blk = eps != 0.0 ? std::min(nsteps, 32) : 1;
+  while (blk > 1 && per_step * blk > ((size_t)64 << 20)) blk /= 2;
+  blk = std::max(blk, 1);
+  for (int k = 0; k < psi->d; ++k) {
+    const size_t want = need[k] * blk;
+    if (ctx->step_prep_bytes[k] < want) {
       if (ctx->step_prep[k]) {
         HIPCHK(ctx, hipDeviceSynchronize());
         HIPCHK(ctx, hipFree(ctx->step_prep[k]));
         ctx->step_prep[k] = nullptr;
         ctx->step_prep_bytes[k] = 0;
       }
-      if (hipMalloc(&ctx->step_prep[k], need) != hipSuccess) return fail(ctx, MM_ERR_NOMEM, "step operator");
-      ctx->step_prep_bytes[k] = need;
+      if (hipMalloc(&ctx->step_prep[k], want) != hipSuccess) return fail(ctx, MM_ERR_NOMEM, "step operators");
+      ctx->step_prep_bytes[k] = want;
     }
   }
-  const size_t bytes = (size_t)numel(psi) * dsize(psi->dtype);
-  for (int it = 0; it < nsteps; ++it) {
-    // exact flow of the potential part over [a, b]: exp(-i (eps/2) |x|^2 (cos a - cos b)),
-    // separable over the modes, folded into the operators as diagonal factors
-    const double t = t0 + it * tau;
-    const double cb = 0.5 * eps * (std::cos(t) - std::cos(t + 0.5 * tau));
-    const double ca = 0.5 * eps * (std::cos(t + 0.5 * tau) - std::cos(t + tau));
-    void* cur = psi->data;
-    auto phase_of = [&](int k) {
-      mm::PhaseScale ph;
-      ph.rx2 = ctx->x2 + (size_t)k * 4096;
-      ph.rc = ca;
-      ph.cx2 = ph.rx2;
-      ph.cc = cb;
-      return ph;
-    };
-    // the step's operators, all modes in one launch when they share a
-    // precision (each buffer is read only by its own mode's product below);
-    // without the time-dependent potential (eps = 0) they are the same every
-    // step and are prepared once
-    const bool prep = it == 0 || eps != 0.0;
-    if (prep && one_prec) {
-      mm::PrepJobs jobs;
-      jobs.n = psi->d;
-      for (int k = 0; k < psi->d; ++k) {
+  auto prepare_block = [&](int it0, int steps) -> mm_status {
+    // one launch per precision group of modes
+    bool done[MM_MAXD] = {false};
+    for (int k0 = 0; k0 < psi->d; ++k0) {
+      if (done[k0]) continue;
+      mm::StepPrep p;
+      p.steps = steps;
+      p.t0 = t0 + it0 * tau;
+      p.tau = tau;
+      p.eps = eps;
+      for (int k = k0; k < psi->d && p.modes < mm::MAX_STEP_MODES; ++k) {
+        if (done[k] || ctx->ho[k].op.prec != ctx->ho[k0].op.prec) continue;
         const mm_op_s& L = ctx->ho[k].op;
-        mm::PrepJob& j = jobs.j[k];
-        j.master = L.dev_master;
-        j.rows = L.rows;
-        j.cols = L.cols;
-        j.ld = L.rows;
-        j.cplx = 1;
-        j.ph = phase_of(k);
-        j.out = ctx->step_prep[k];
-        j.KBT = L.KBT;
-        j.MFT = L.MFT;
-        j.a_exp = L.a_exp;
+        mm::StepPrepMode& m = p.m[p.modes++];
+        m.master = L.dev_master;
+        m.n = L.rows;
+        m.x2 = ctx->x2 + (size_t)k * 4096;
+        m.out = (char*)ctx->step_prep[k];
+        m.stride = need[k];
+        m.KBT = L.KBT;
+        m.MFT = L.MFT;
+        m.a_exp = L.a_exp;
+        done[k] = true;
       }
-      HIPCHK(ctx, mm::launch_prepare_multi(kprec(Phi_fwd[0]->prec), jobs, s));
+      HIPCHK(ctx, mm::launch_prepare_steps(kprec(ctx->ho[k0].op.prec), p, s));
     }
+    return MM_OK;
+  };
+  const size_t bytes = (size_t)numel(psi) * dsize(psi->dtype);
+  int blk0 = 0;   // first step of the prepared block
+  for (int it = 0; it < nsteps; ++it) {
+    if (it == 0 || (eps != 0.0 && it - blk0 >= blk)) {
+      blk0 = it;
+      st = prepare_block(it, eps != 0.0 ? std::min(blk, nsteps - it) : 1);
+      if (st != MM_OK) return st;
+    }
+    const size_t sidx = eps != 0.0 ? (size_t)(it - blk0) : 0;
+    void* cur = psi->data;
     for (int k = 0; k < psi->d; ++k) {
       mm_op_s* L = &ctx->ho[k].op;
-      if (prep && !one_prec)
-        HIPCHK(ctx, mm::launch_prepare(kprec(L->prec), 1, L->dev_master, L->rows, L->cols, L->rows, phase_of(k), ctx->step_prep[k],
-                                       L->KBT, L->MFT, s, L->a_exp));
+      const void* prep = (const char*)ctx->step_prep[k] + sidx * need[k];
       mm::ModePlan plan;
       st = run_mode(ctx, cur, cur, psi->dims, psi->d, psi->dtype, L, k + 1, 0, 0, s, &plan, true);
       if (st != MM_OK) return st;
@@ -1224,8 +1231,7 @@ mm_status ho_strang_step(mm_ctx ctx, mm_tensor* psi, const mm_op* Phi_fwd, const
         if (st != MM_OK) return st;
         dst = (cur == psi->data) ? ctx->ws : psi->data;
       }
-      st = run_mode(ctx, cur, dst, psi->dims, psi->d, psi->dtype, L, k + 1, 0, 0, s, nullptr, false,
-                    ctx->step_prep[k]);
+      st = run_mode(ctx, cur, dst, psi->dims, psi->d, psi->dtype, L, k + 1, 0, 0, s, nullptr, false, prep);
       if (st != MM_OK) return st;
       cur = dst;
     }
