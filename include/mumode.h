@@ -317,9 +317,13 @@ mm_status mm_norm2(mm_ctx ctx, const mm_tensor* T, double cell, double* host_out
  * for the product T x_{k+1} E[k], out of place into the context workspace
  * (T is read, not modified), and records the fastest for that problem shape
  * (precision, real / complex, fibre load path, rows, columns, number of
- * fibres).  Later launches of the same shape on this context use the
- * recorded shape, with or without the fused phases; shapes never tuned use
- * the built-in choice.  budget_ms bounds the timing loop (at least two
+ * fibres).  A complex product with a complex operator is timed a second
+ * time with the fused prologue phase (the first product of a
+ * Gross-Pitaevskii step), whose staging work can change the fastest shape,
+ * and that choice is recorded under its own key (load path + 8).  Later
+ * launches of the same shape on this context use the recorded shape (a
+ * product with the prologue phase its own entry if there is one, else the
+ * plain one); shapes never tuned use the built-in choice.  budget_ms bounds the timing loop (at least two
  * timed repetitions per candidate).  Synchronises `stream`.  The products
  * along the modes of an expstep, a Strang step or a batch all have the shape
  * tuned here when called with the same T and E. */
@@ -343,7 +347,8 @@ mm_status mm_autotune_batched(mm_ctx ctx, int count, mm_tensor* const* T, const 
 mm_status mm_autotune_batched_get(mm_ctx ctx, int mode, int is_complex, int* cls);
 /* Number of recorded tune entries, and entry `index` (0-based):
  * key6 = {precision, complex, load path (0 contiguous fibres, 1 strided,
- * 2 gather), real rows, real columns, fibres}, the tile class and its time in
+ * 2 gather, 3 paired real fibres; + 8 for a product with the fused prologue
+ * phase), real rows, real columns, fibres}, the tile class and its time in
  * microseconds (any out pointer may be NULL). */
 mm_status mm_tune_count(mm_ctx ctx, int* count);
 mm_status mm_tune_get(mm_ctx ctx, int index, int64_t* key6, int* cls, double* us);

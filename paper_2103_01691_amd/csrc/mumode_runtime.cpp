@@ -294,10 +294,19 @@ mm_status run_mode(mm_ctx ctx, const void* in, void* out, const int64_t* dims, i
   const bool fcontig = (P % 4 == 0);
   const bool pair = !kcontig && !cplx && P == 2 && a.Kr % 8 == 0;   // as the planner decides
   const int load = kcontig ? mm::KL_KCONTIG : (pair ? mm::KL_PAIR : (fcontig ? mm::KL_FCONTIG : mm::KL_GENERIC));
-  ctx->last_key = {(int64_t)kprec(L->prec), cplx ? 1 : 0, load, a.Mr, a.Kr, a.F};
+  // tune key: (precision, complex, load path, rows, columns, fibres); a
+  // complex product with the fused prologue phase has its own entry (load
+  // path + 8) and falls back to the plain one
+  const bool pro_key = cplx && s_pre != 0.0;
+  ctx->last_key = {(int64_t)kprec(L->prec), cplx ? 1 : 0, load + (pro_key ? 8 : 0), a.Mr, a.Kr, a.F};
   int force = ctx->force_cls;
   if (force < 0 && !ctx->tune.empty()) {
     auto it = ctx->tune.find(ctx->last_key);
+    if (it == ctx->tune.end() && pro_key) {
+      std::array<int64_t, 6> plain = ctx->last_key;
+      plain[2] = load;
+      it = ctx->tune.find(plain);
+    }
     if (it != ctx->tune.end()) force = it->second.first;
   }
   // three-product kernels: complex operator with its Gauss preparation,
@@ -1624,51 +1633,68 @@ mm_status mm_autotune(mm_ctx ctx, const mm_tensor* T, const mm_op* E, int budget
       if (st == MM_OK && plan.cls == c) cands.push_back(c);
     }
     if (cands.empty()) continue;
-    const double per_cand_ms = per_mode_ms / cands.size();
-    int best = -1;
-    double best_ms = 0.0;
-    std::array<int64_t, 6> key{};
-    for (int c : cands) {
-      ctx->force_cls = c;
-      mm::ModePlan plan;
-      // first launch: warm-up (and, for FP16X2, the bound of T in slot 0)
-      ctx->chain_end = nullptr;
-      st = run_mode(ctx, T->data, ctx->ws, T->dims, T->d, T->dtype, L, k + 1, 0, 0, s, &plan, false);
-      if (st == MM_OK) {
-        key = ctx->last_key;
+    // complex products with a complex operator are timed a second time with
+    // the fused prologue phase (the first product of a Gross-Pitaevskii
+    // step): the phase adds VALU work to the staging, which changes which
+    // tile shape is fastest, so that choice is recorded under its own key
+    const bool with_pro = cplx && L->cplx;
+    const double per_cand_ms = per_mode_ms / cands.size() / (with_pro ? 2 : 1);
+    for (int pass = 0; pass < (with_pro ? 2 : 1); ++pass) {
+      const double s_pre = pass ? 1e-3 : 0.0;
+      int best = -1;
+      double best_ms = 0.0;
+      std::array<int64_t, 6> key{};
+      for (int c : cands) {
+        ctx->force_cls = c;
+        mm::ModePlan plan;
+        if (pass) {   // classes without instances that carry the phase
+          st = run_mode(ctx, T->data, ctx->ws, T->dims, T->d, T->dtype, L, k + 1, s_pre, 0, s, &plan, true);
+          if (st != MM_OK || plan.cls != c) {
+            ctx->err.clear();
+            ctx->force_cls = -1;
+            st = MM_OK;
+            continue;
+          }
+        }
+        // first launch: warm-up (and, for FP16X2, the bound of T in slot 0)
+        ctx->chain_end = nullptr;
+        st = run_mode(ctx, T->data, ctx->ws, T->dims, T->d, T->dtype, L, k + 1, s_pre, 0, s, &plan, false);
+        if (st == MM_OK) {
+          key = ctx->last_key;
+          HIPCHK(ctx, hipEventRecord(e0, s));
+          ctx->chain_end = T->data;
+          ctx->sidx = 0;
+          st = run_mode(ctx, T->data, ctx->ws, T->dims, T->d, T->dtype, L, k + 1, s_pre, 0, s, nullptr, false);
+          HIPCHK(ctx, hipEventRecord(e1, s));
+        }
+        if (st != MM_OK) {
+          ctx->force_cls = -1;
+          return st;
+        }
+        HIPCHK(ctx, hipEventSynchronize(e1));
+        float t1 = 0.f;
+        HIPCHK(ctx, hipEventElapsedTime(&t1, e0, e1));
+        int reps = (int)std::min(20.0, std::max(2.0, per_cand_ms / std::max(1e-3, (double)t1)));
         HIPCHK(ctx, hipEventRecord(e0, s));
-        ctx->chain_end = T->data;
-        ctx->sidx = 0;
-        st = run_mode(ctx, T->data, ctx->ws, T->dims, T->d, T->dtype, L, k + 1, 0, 0, s, nullptr, false);
+        for (int r = 0; r < reps && st == MM_OK; ++r) {
+          ctx->chain_end = T->data;   // every repetition reads the bound of T (slot 0)
+          ctx->sidx = 0;
+          st = run_mode(ctx, T->data, ctx->ws, T->dims, T->d, T->dtype, L, k + 1, s_pre, 0, s, nullptr, false);
+        }
         HIPCHK(ctx, hipEventRecord(e1, s));
-      }
-      if (st != MM_OK) {
         ctx->force_cls = -1;
-        return st;
+        if (st != MM_OK) return st;
+        HIPCHK(ctx, hipEventSynchronize(e1));
+        float tr = 0.f;
+        HIPCHK(ctx, hipEventElapsedTime(&tr, e0, e1));
+        const double avg = (double)tr / reps;
+        if (best < 0 || avg < best_ms) {
+          best = c;
+          best_ms = avg;
+        }
       }
-      HIPCHK(ctx, hipEventSynchronize(e1));
-      float t1 = 0.f;
-      HIPCHK(ctx, hipEventElapsedTime(&t1, e0, e1));
-      int reps = (int)std::min(20.0, std::max(2.0, per_cand_ms / std::max(1e-3, (double)t1)));
-      HIPCHK(ctx, hipEventRecord(e0, s));
-      for (int r = 0; r < reps && st == MM_OK; ++r) {
-        ctx->chain_end = T->data;   // every repetition reads the bound of T (slot 0)
-        ctx->sidx = 0;
-        st = run_mode(ctx, T->data, ctx->ws, T->dims, T->d, T->dtype, L, k + 1, 0, 0, s, nullptr, false);
-      }
-      HIPCHK(ctx, hipEventRecord(e1, s));
-      ctx->force_cls = -1;
-      if (st != MM_OK) return st;
-      HIPCHK(ctx, hipEventSynchronize(e1));
-      float tr = 0.f;
-      HIPCHK(ctx, hipEventElapsedTime(&tr, e0, e1));
-      const double avg = (double)tr / reps;
-      if (best < 0 || avg < best_ms) {
-        best = c;
-        best_ms = avg;
-      }
+      if (best >= 0) ctx->tune[key] = {best, best_ms * 1e3};
     }
-    ctx->tune[key] = {best, best_ms * 1e3};
   }
   batch_invalidate(ctx);
   ctx->chain_end = nullptr;
