@@ -85,6 +85,36 @@ def test_gpe_identity_split(ctx, prec, n, nsteps):
     assert err < nsteps * REL_TOL[prec]
 
 
+@pytest.mark.parametrize("prec", ["bf16x3", "fp16x2"])
+@pytest.mark.parametrize("cls", [8, 9])
+def test_identity_split_ignores_three_product_class(ctx, tmp_path, prec, cls):
+    # the three-product kernels have no identity-add form: a tune entry that
+    # names one for the shape of an identity-split product must give way to
+    # a four-product class (same result as untuned)
+    import paper_2103_01691_amd as mm
+    code = {"bf16x3": 2, "fp16x2": 3}[prec]
+    n, a, b, beta, tau = 64, -8.0, 8.0, 100.0, 1e-3
+    psi0 = cast(synth.thomas_fermi_initial(n, a, b, 3, beta, cfg_id=4), prec, True)
+    lines = [f"{code} 1 {ld} {2 * n} {2 * n} {n * n} {cls} 0.0\n" for ld in (0, 1, 8, 9)]
+    f = tmp_path / "t.txt"
+    f.write_text("mumode-tune 1\n" + "".join(lines))
+    E = ctx.mm_op_prepare(mm.schrodinger_fd_exponential(n, a, b, 1.0, tau), prec, identity_split=True)
+    ref = sc.gpe_strang(psi0, [op.ho_exponential(n, a, b, tau)] * 3, tau, beta, 2)
+    outs = []
+    for tuned in (False, True):
+        ctx.mm_tune_clear()
+        if tuned:
+            ctx.mm_tune_load(f)
+        psi = to_gpu(psi0, prec, True)
+        ctx.gpe_strang_step(psi, [E] * 3, tau, beta, 2)
+        outs.append(from_gpu(psi))
+    ctx.mm_tune_clear()
+    E.destroy()
+    note(f"identity split, class {cls} in the tune table, {prec}: rel err {rel(outs[1], ref):.3e}")
+    assert np.array_equal(outs[0], outs[1])
+    assert rel(outs[1], ref) < 2 * REL_TOL[prec]
+
+
 @pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
 def test_batched_identity_split(ctx, prec):
     g = synth.rng(1503, 0)
