@@ -425,7 +425,7 @@ size_t prepared_bytes(int prec, int KBT, int MFT) {
 }
 
 int num_classes(int prec) {
-  return (prec == KP_BF16X3 || prec == KP_FP16X2) ? 11 : 3;
+  return (prec == KP_BF16X3 || prec == KP_FP16X2) ? 11 : (prec == KP_F64 ? 4 : 3);
 }
 
 void gauss_blocks(int64_t rows, int64_t cols, int* JBT, int* MFT) {

@@ -1006,6 +1006,12 @@ template <int PR, int CLS> struct Cfg;
 template <> struct Cfg<KP_F64, 0> { static constexpr int WMF = 8, WNF = 2, WM = 4, WN = 1, KCH = 8; static constexpr int OCC = 1; };
 template <> struct Cfg<KP_F64, 1> { static constexpr int WMF = 8, WNF = 1, WM = 2, WN = 2, KCH = 8; static constexpr int OCC = 1; };
 template <> struct Cfg<KP_F64, 2> { static constexpr int WMF = 8, WNF = 1, WM = 1, WN = 4, KCH = 8; static constexpr int OCC = 1; };
+// FP64 class 3: one wave, 32 real rows x 16 fibres, four waves per SIMD, for
+// products with few fibres (the 2-D matrix products of the device
+// exponential: a 256 x 256 complex product has 256 fibres, 8 workgroups of
+// class 0 but 256 of this class); it splits the rows over workgroups, so its
+// products run out of place
+template <> struct Cfg<KP_F64, 3> { static constexpr int WMF = 2, WNF = 1, WM = 1, WN = 1, KCH = 8; static constexpr int OCC = 4; };
 template <> struct Cfg<KP_F32, 0> { static constexpr int WMF = 4, WNF = 2, WM = 4, WN = 1, KCH = 32; static constexpr int OCC = 1; };
 template <> struct Cfg<KP_F32, 1> { static constexpr int WMF = 4, WNF = 1, WM = 2, WN = 2, KCH = 32; static constexpr int OCC = 1; };
 template <> struct Cfg<KP_F32, 2> { static constexpr int WMF = 4, WNF = 1, WM = 1, WN = 4, KCH = 32; static constexpr int OCC = 1; };
@@ -1079,6 +1085,16 @@ KernFn pick_kernel(int cplx, int ld, int pro, int epi, int cls, int full) {
     if (epi) return kfx<PR, C_, L_, false, true, K_, IDA>(full);             \
     return kfx<PR, C_, L_, false, false, K_, IDA>(full);                     \
   } while (0)
+  if constexpr (PR == KP_F64) {
+    if (cls == 3) {
+      if (pro || epi || (ld != KL_KCONTIG && ld != KL_FCONTIG)) return nullptr;
+      if (cplx)
+        return ld == KL_KCONTIG ? kfx<PR, true, KL_KCONTIG, false, false, 3, IDA>(full)
+                                : kfx<PR, true, KL_FCONTIG, false, false, 3, IDA>(full);
+      return ld == KL_KCONTIG ? kfx<PR, false, KL_KCONTIG, false, false, 3, IDA>(full)
+                              : kfx<PR, false, KL_FCONTIG, false, false, 3, IDA>(full);
+    }
+  }
   if (cls == 1 || cls == 2) {
     if (pro || epi || ld == KL_GENERIC) return nullptr;
     if (cls == 1) {
@@ -1135,6 +1151,12 @@ bool shape_table(int cls, TileShape* out) {
     case 1: *out = shape_of<PR, 1>(); return true;
     case 2: *out = shape_of<PR, 2>(); return true;
     default: break;
+  }
+  if constexpr (PR == KP_F64) {
+    if (cls == 3) {
+      *out = shape_of<PR, 3>();
+      return true;
+    }
   }
   if constexpr (NumCls<PR>::N > 3) {
     switch (cls) {

@@ -503,8 +503,16 @@ mm_status expm_device(mm_ctx ctx, int n, const double* A, const double* d, doubl
   if (q > 1000) return fail(ctx, MM_ERR_ARG, "exponent argument too large (norm %g)", fa);
   const double sc = std::ldexp(1.0, -q);
   const int64_t dims[2] = {n, n};
+  // a product of two n x n matrices has only n fibres: where the default
+  // FP64 tile would leave most CUs idle (fewer than 128 workgroups), the
+  // one-wave tile of class 3 (32 real rows x 16 fibres) runs it
+  const bool few = (int64_t)((n + 31) / 32) * ((2 * (int64_t)n + 511) / 512) < 128;
   auto mul = [&](const void* prep, const double* in, double* o) {
-    return run_mode(ctx, in, o, dims, 2, MM_C128, &op, 1, 0, 0, s, nullptr, false, prep);
+    const int keep = ctx->force_cls;
+    if (few) ctx->force_cls = 3;
+    mm_status r = run_mode(ctx, in, o, dims, 2, MM_C128, &op, 1, 0, 0, s, nullptr, false, prep);
+    ctx->force_cls = keep;
+    return r;
   };
   HIPCHK(ctx, mm::launch_expm_generator(A, n, d, gr, gi, fr * sc, fi * sc, X, s));
   HIPCHK(ctx, mm::launch_prepare(mm::KP_F64, 1, X, n, n, n, mm::PhaseScale(), prepX, op.KBT, op.MFT, s));

@@ -59,6 +59,29 @@ def test_every_split_class_matches_oracle(ctx, tmp_path, prec, cls):
     assert err < REL_TOL[prec]
 
 
+@pytest.mark.parametrize("cplx", [True, False])
+@pytest.mark.parametrize("cls", [0, 1, 2, 3])
+def test_every_fp64_class_matches_oracle(ctx, tmp_path, cplx, cls):
+    # FP64 classes, including the one-wave class 3 that the device
+    # exponential uses for its few-fibre matrix products (rows split over
+    # workgroups, so every product here runs out of place)
+    g = synth.rng(1103, int(cplx) * 10 + cls)
+    U = synth.random_tensor(DIMS, cplx, g)
+    E = [synth.random_matrix(n, n, cplx, g) for n in DIMS]
+    f = tmp_path / "t.txt"
+    f.write_text("mumode-tune 1\n" + "".join(" ".join(map(str, k)) + f" {cls} 0.0\n"
+                                             for k in _keys("fp64", DIMS, cplx)))
+    ctx.mm_tune_clear()
+    ctx.mm_tune_load(f)
+    ops = [ctx.mm_op_prepare(e, "fp64") for e in E]
+    T = to_gpu(U, "fp64", cplx)
+    ctx.mumode_expstep(T, ops, 1)
+    err = rel(from_gpu(T), om.expstep(U, E, 1))
+    ctx.mm_tune_clear()
+    note(f"forced FP64 class {cls} complex={cplx}: rel err {err:.3e}")
+    assert err < REL_TOL["fp64"]
+
+
 @pytest.mark.parametrize("prec", ["bf16x3", "fp16x2"])
 @pytest.mark.parametrize("cls", [8, 9])
 @pytest.mark.parametrize("dims", [(200, 136), (40, 48, 24), (8, 16)])
