@@ -204,3 +204,30 @@ def test_tune_cache_path_persists_across_contexts(tmp_path):
     with pytest.raises(mm.MumodeError) as e:
         mm.Context(0, tune_cache_path=bad)
     assert e.value.status == 1
+
+
+@pytest.mark.parametrize("cls", [8, 9])
+@pytest.mark.parametrize("state,op,growth", [(1e-9, 1.0, 1.0), (1e7, 1.0, 1.0), (1.0, 1e-6, 1.0), (1.0, 1e4, 1.0),
+                                             (1.0, 1.0, 40.0), (1.0, 1.0, 1.0 / 40.0)])
+def test_three_product_fp16x2_range(ctx, tmp_path, cls, state, op, growth):
+    # the three-product FP16x2 form keeps one more bit of headroom for x + y
+    # and Re L + Im L: its error must not depend on the magnitudes of the
+    # state or the operator, nor on a bound that moves by growth^9 over a
+    # chain of nine products
+    dims = (64, 40, 24)
+    g = synth.rng(1104, cls)
+    U = cast(synth.random_tensor(dims, True, g) * state, "fp16x2", True)
+    E = [synth.random_matrix(n, n, True, g) * op * growth for n in dims]
+    steps = 3 if growth != 1.0 else 1
+    ref = om.expstep(U, E, steps)
+    f = tmp_path / "t.txt"
+    f.write_text("mumode-tune 1\n" + "".join(" ".join(map(str, k)) + f" {cls} 0.0\n" for k in _keys("fp16x2", dims)))
+    ctx.mm_tune_clear()
+    ctx.mm_tune_load(f)
+    ops = [ctx.mm_op_prepare(e, "fp16x2") for e in E]
+    T = to_gpu(U, "fp16x2", True)
+    ctx.mumode_expstep(T, ops, steps)
+    err = rel(from_gpu(T), ref)
+    ctx.mm_tune_clear()
+    note(f"three-product class {cls} state x{state:g} operator x{op:g} growth {growth:g}: rel err {err:.3e}")
+    assert err < steps * REL_TOL["fp16x2"]
