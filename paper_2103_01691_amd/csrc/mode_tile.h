@@ -732,9 +732,26 @@ __device__ __forceinline__ void mode_tile(const ModeArgs& a, int64_t tile_x, int
     float* reg = (float*)lds + (size_t)wave * WNF * 32 * 32;
     st* __restrict__ out = (st*)a.out;
     const st s_post = (st)a.s_post;
+    // identity part: the input entries of a row block are loaded together,
+    // one block ahead of its stores, so their latency is paid once per block
+    // and no load waits behind the stores before it (one counter, in order)
+    constexpr int NSB = WNF * 32 / 8;
+    f32x4v xin[IDA ? 2 : 1][IDA ? NSB : 1];
+    auto load_in = [&](int i, f32x4v (&dst)[IDA ? NSB : 1]) {
+#pragma unroll
+      for (int sblk = 0; sblk < NSB; ++sblk) {
+        const int f = 8 * sblk + lane / 8;
+        const int64_t fg = f0 + (int64_t)nf0 * NB + f;
+        dst[sblk] = *(const f32x4v*)((const st*)a.in + fg * a.Mr + (mf0 + i) * 32 + 4 * (lane % 8));
+      }
+    };
+    if constexpr (IDA) load_in(0, xin[0]);
 #pragma unroll
     for (int i = 0; i < WMF; ++i) {
       const int mf = mf0 + i;
+      if constexpr (IDA) {
+        if (i + 1 < WMF) load_in(i + 1, xin[(i + 1) & 1]);
+      }
 #pragma unroll
       for (int j = 0; j < WNF; ++j)
 #pragma unroll
@@ -761,7 +778,7 @@ __device__ __forceinline__ void mode_tile(const ModeArgs& a, int64_t tile_x, int
         if constexpr (IDA) {
           // identity part: the input entries at the same position (square
           // operator: same layout), read by the lane that overwrites them
-          const f32x4v x = *(const f32x4v*)((const st*)a.in + fg * a.Mr + mf * 32 + 4 * b);
+          const f32x4v x = xin[i & 1][sblk];
           st y[4] = {x[0], x[1], x[2], x[3]};
           if constexpr (PRO && CPLX) {
             phase<st>(y[0], y[1], s_pre);
@@ -809,12 +826,41 @@ __device__ __forceinline__ void mode_tile(const ModeArgs& a, int64_t tile_x, int
     const uint32_t obytes = (uint32_t)ostride * (uint32_t)sizeof(st);
     typedef float f32x2 __attribute__((ext_vector_type(2)));
     typedef typename std::conditional<sizeof(st) == 4, f32x2, f64x2>::type st2;
+    constexpr int GROUPS = T::NACC / 4;
+    // identity part: the input entries of a row block are loaded together
+    // at the start of the block (complex: (re, im) pairs; real: scalars), so
+    // their latency is paid once per block; one block ahead would need a
+    // second buffer, which spills here
+    constexpr int NIN = IDA ? WNF * GROUPS * (CPLX ? 2 : 4) : 1;
+    typedef typename std::conditional<CPLX, st2, st>::type inT;
+    inT yin[1][NIN];
+    auto load_in = [&](int i, inT (&dst)[NIN]) {
+      const int mf = mf0 + i;
+#pragma unroll
+      for (int j = 0; j < WNF; ++j)
+#pragma unroll
+        for (int gq = 0; gq < GROUPS; ++gq) {
+          if constexpr (CPLX) {
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+              const int u = (MB == 32) ? mf * 16 + 4 * gq + h : mf * 8 + 4 * h;
+              dst[(j * GROUPS + gq) * 2 + h] = *(const st2*)((const char*)a.in + ((uint32_t)u * obytes + voff[j]));
+            }
+          } else {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+              const int u = (MB == 32) ? mf * 32 + 8 * gq + r : mf * 16 + 4 * r;
+              dst[(j * GROUPS + gq) * 4 + r] = *(const st*)((const char*)a.in + ((uint32_t)u * obytes + voff[j]));
+            }
+          }
+        }
+    };
 #pragma unroll
     for (int i = 0; i < WMF; ++i) {
       const int mf = mf0 + i;
+      if constexpr (IDA) load_in(i, yin[0]);
 #pragma unroll
       for (int j = 0; j < WNF; ++j) {
-        constexpr int GROUPS = T::NACC / 4;
 #pragma unroll
         for (int gq = 0; gq < GROUPS; ++gq) {
           st v4[4];
@@ -827,8 +873,7 @@ __device__ __forceinline__ void mode_tile(const ModeArgs& a, int64_t tile_x, int
             if constexpr (IDA) {
 #pragma unroll
               for (int h = 0; h < 2; ++h) {
-                const int u = (MB == 32) ? mf * 16 + 4 * gq + h : mf * 8 + 4 * h;
-                const st2 x = *(const st2*)((const char*)a.in + ((uint32_t)u * obytes + voff[j]));
+                const st2 x = yin[0][(j * GROUPS + gq) * 2 + h];
                 st y0 = x[0], y1 = x[1];
                 if constexpr (PRO) phase<st>(y0, y1, s_pre);
                 v4[2 * h] += y0;
@@ -849,7 +894,7 @@ __device__ __forceinline__ void mode_tile(const ModeArgs& a, int64_t tile_x, int
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
               const int u = (MB == 32) ? mf * 32 + 8 * gq + r : mf * 16 + 4 * r;
-              if constexpr (IDA) v4[r] += *(const st*)((const char*)a.in + ((uint32_t)u * obytes + voff[j]));
+              if constexpr (IDA) v4[r] += yin[0][(j * GROUPS + gq) * 4 + r];
               if constexpr (F16) vmax = fmaxf(vmax, fabsf(v4[r]));
               *(st*)((char*)out + ((uint32_t)u * obytes + voff[j])) = v4[r];
             }
