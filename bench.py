@@ -159,7 +159,7 @@ def timed(torch, fn, reps):
     return ev0.elapsed_time(ev1) * 1e-3
 
 
-WORKLOADS = ("batch512", "ho128", "free256", "hkmp", "heat64")
+WORKLOADS = ("batch512", "ho128", "free256", "hkmp", "heat64", "vortex")
 
 
 def other_workloads(ctx, mm, torch, only=WORKLOADS):
@@ -180,6 +180,9 @@ def other_workloads(ctx, mm, torch, only=WORKLOADS):
         out.update(_hkmp_workload(ctx, mm, torch, gen))
     if "heat64" in only:
         out.update(_heat_workload(ctx, mm, torch, gen))
+    if "vortex" in only:
+        log("  vortex reconnection (Section 4.5)")
+        out.update(_vortex_workload(ctx, mm, torch))
     return out
 
 
@@ -338,6 +341,37 @@ def _heat_workload(ctx, mm, torch, gen):
                                      "us_per_step_one_launch_per_product": 1e6 * t_per / (20 * K),
                                      "note": "default: all 20 steps in one single-workgroup launch"}
     Eop.destroy()
+    torch.cuda.empty_cache()
+    return out
+
+
+def _vortex_workload(ctx, mm, torch):
+    import synth
+    out = {}
+    # vortex reconnection of Section 4.5: [-20, 20]^3 on graded non-uniform
+    # nodes with homogeneous Neumann ends, symmetrised variable v = W^(1/2) u,
+    # Strang steps of tau = 0.1 up to T = 25 (250 steps), the paper's n
+    tau, T = 0.1, 25.0
+    steps = int(round(T / tau))
+    for n in (81, 141):
+        xs = [synth.graded_nodes(n, -20.0, 20.0, 2.0)] * 3
+        M, w = mm.nonuniform_neumann_d2(xs[0])
+        E = mm.expm(M, 0.5j * tau)
+        W = w[:, None, None] * w[None, :, None] * w[None, None, :]
+        v0 = np.sqrt(W) * synth.vortex_pair_initial(xs)
+        for prec in ("fp64", "fp32", "bf16x3", "fp16x2"):
+            npdt = np.complex128 if prec == "fp64" else np.complex64
+            v = torch.from_numpy(synth.to_device_layout(v0.astype(npdt))).cuda()
+            Eop = ctx.mm_op_prepare(E, prec)
+            ctx.vortex_strang_step(v, [Eop] * 3, [w] * 3, tau, 2)
+            t = timed(torch, lambda k: ctx.vortex_strang_step(v, [Eop] * 3, [w] * 3, tau, k), steps)
+            out[f"vortex{n}_{prec}"] = {"ms_per_step": 1e3 * t / steps, "s_to_T25": t,
+                                        "tflops_effective": 3 * 8.0 * n * n ** 3 / (t / steps) / 1e12}
+            Eop.destroy()
+            del v
+    out["vortex_paper_cpu_s_to_T25"] = {"n81": 14.94, "n101": 29.51, "n121": 58.74, "n141": 102.40,
+                                        "source": "the paper's figure for the mu-mode integrator (MATLAB, CPU), "
+                                                  "context only"}
     torch.cuda.empty_cache()
     return out
 
