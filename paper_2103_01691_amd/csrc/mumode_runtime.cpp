@@ -1307,11 +1307,12 @@ mm_status vortex_strang_step(mm_ctx ctx, mm_tensor* v, const mm_op* E, const dou
   const int f64 = is_f64(v->dtype) ? 1 : 0;
   // merged steps N(tau/2) [L N(tau)]^(nsteps-1) L N(tau/2): N keeps |v|, so
   // adjacent half steps compose; each N is one pass over the state (its
-  // coefficient depends on the position through W^-1), after which an FP16X2
-  // product starts a new running bound (a rotation can raise a component)
+  // coefficient depends on the position through W^-1).  FP16X2: a rotation
+  // raises a component by at most sqrt(2), which the state scale's headroom
+  // covers (as for the fused prologue phase), so the running bound of the
+  // last product carries over the pass to the next step's first product
   HIPCHK(ctx, mm::launch_vortex_phase(v->data, f64, v->d, v->dims, ctx->winv, 0.5 * tau, s));
   for (int it = 0; it < nsteps; ++it) {
-    ctx->chain_end = nullptr;
     st = sweep(ctx, v, E, 0.0, 0.0, s);
     if (st != MM_OK) return st;
     HIPCHK(ctx, mm::launch_vortex_phase(v->data, f64, v->d, v->dims, ctx->winv, it + 1 < nsteps ? tau : 0.5 * tau, s));
