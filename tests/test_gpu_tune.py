@@ -231,3 +231,42 @@ def test_three_product_fp16x2_range(ctx, tmp_path, cls, state, op, growth):
     ctx.mm_tune_clear()
     note(f"three-product class {cls} state x{state:g} operator x{op:g} growth {growth:g}: rel err {err:.3e}")
     assert err < steps * REL_TOL["fp16x2"]
+
+
+@pytest.mark.parametrize("prec", ["bf16x3", "fp16x2"])
+@pytest.mark.parametrize("cls", [8, 9])
+@pytest.mark.parametrize("mu,m", [(1, 40), (2, 72), (3, 24)])
+def test_three_product_rectangular_apply(ctx, tmp_path, prec, cls, mu, m):
+    # a rectangular complex operator (m x n_mu, m != n_mu) through
+    # mumode_apply on the three-product kernels: rows and columns of the
+    # prepared Re L, Im L, Re L + Im L blocks differ
+    dims = (48, 56, 32)
+    g = synth.rng(1105, mu * 10 + cls)
+    U = cast(synth.random_tensor(dims, True, g), prec, True)
+    n = dims[mu - 1]
+    L = synth.random_matrix(m, n, True, g)
+    ref = om.mode_product(U, L, mu)
+    P = int(np.prod(dims[:mu - 1]))
+    F = int(np.prod(dims)) // n
+    load = 0 if P == 1 else 1
+    f = tmp_path / "t.txt"
+    f.write_text(f"mumode-tune 1\n{PREC_CODE[prec]} 1 {load} {2 * m} {2 * n} {F} {cls} 0.0\n")
+    ctx.mm_tune_clear()
+    ctx.mm_tune_load(f)
+    odims = list(dims)
+    odims[mu - 1] = m
+    out = empty_gpu(odims, prec, True)
+    Lop = ctx.mm_op_prepare(L, prec)
+    ctx.mm_profile_begin()
+    ctx.mumode_apply(out, to_gpu(U, prec, True), Lop, mu)
+    rec = ctx.mm_profile_end()
+    got = from_gpu(out)
+    ctx.mm_tune_clear()
+    # the four-product kernel of the built-in choice rounds differently: the
+    # forced class really ran
+    ctx.mumode_apply(out, to_gpu(U, prec, True), Lop, mu)
+    assert not np.array_equal(got, from_gpu(out))
+    err = rel(got, ref)
+    note(f"three-product class {cls} {prec} mode {mu} {m}x{n}: rel err {err:.3e}")
+    assert len(rec) == 1
+    assert err < REL_TOL[prec]
