@@ -836,9 +836,21 @@ mm_status mm_op_prepare_ex(mm_ctx ctx, const mm_matrix* M, mm_prec prec, unsigne
   op->a_exp = prec == MM_PREC_SPLIT_FP16X2 ? mm::fp16x2_op_exp(amax) : 0;
   const int kp = kprec(prec);
   mm::op_blocks(kp, comps * M->rows, comps * M->cols, &op->KBT, &op->MFT);
+  // the three-product form of a complex split operator is prepared with it
+  // (no product call allocates): Re L, Im L and Re L + Im L
+  const bool gauss = cplx && !idsplit && (kp == mm::KP_FP16X2 || kp == mm::KP_BF16X3);
+  if (gauss) {
+    double gmax = 0.0;
+    for (size_t e = 0; e + 1 < host.size(); e += 2)
+      gmax = std::max(gmax, std::max(std::fabs(host[e]), std::max(std::fabs(host[e + 1]), std::fabs(host[e] + host[e + 1]))));
+    op->a_exp_g = kp == mm::KP_FP16X2 ? mm::fp16x2_op_exp(gmax) : 0;
+    mm::gauss_blocks(op->rows, op->cols, &op->JBT_g, &op->MFT_g);
+  }
   if (hipMalloc((void**)&op->dev_master, host.size() * sizeof(double)) != hipSuccess ||
-      hipMalloc(&op->prep, mm::prepared_bytes(kp, op->KBT, op->MFT)) != hipSuccess) {
+      hipMalloc(&op->prep, mm::prepared_bytes(kp, op->KBT, op->MFT)) != hipSuccess ||
+      (gauss && hipMalloc(&op->prep_g, mm::gauss_prepared_bytes(kp, op->JBT_g, op->MFT_g)) != hipSuccess)) {
     if (op->dev_master) hipFree(op->dev_master);
+    if (op->prep) hipFree(op->prep);
     delete op;
     return fail(ctx, MM_ERR_NOMEM, "operator buffers");
   }
@@ -846,19 +858,9 @@ mm_status mm_op_prepare_ex(mm_ctx ctx, const mm_matrix* M, mm_prec prec, unsigne
   HIPCHK(ctx, hipMemcpy(op->dev_master, host.data(), host.size() * sizeof(double), hipMemcpyHostToDevice));
   HIPCHK(ctx, mm::launch_prepare(kp, cplx, op->dev_master, op->rows, op->cols, op->rows, mm::PhaseScale(),
                                  op->prep, op->KBT, op->MFT, 0, op->a_exp));
-  if (cplx && !idsplit && (kp == mm::KP_FP16X2 || kp == mm::KP_BF16X3)) {
-    // the three-product form, prepared with the operator so that no product
-    // call allocates
-    double gmax = 0.0;
-    for (size_t e = 0; e + 1 < host.size(); e += 2)
-      gmax = std::max(gmax, std::max(std::fabs(host[e]), std::max(std::fabs(host[e + 1]), std::fabs(host[e] + host[e + 1]))));
-    op->a_exp_g = kp == mm::KP_FP16X2 ? mm::fp16x2_op_exp(gmax) : 0;
-    mm::gauss_blocks(op->rows, op->cols, &op->JBT_g, &op->MFT_g);
-    if (hipMalloc(&op->prep_g, mm::gauss_prepared_bytes(kp, op->JBT_g, op->MFT_g)) != hipSuccess)
-      return fail(ctx, MM_ERR_NOMEM, "operator buffers");
+  if (gauss)
     HIPCHK(ctx, mm::launch_prepare_gauss(kp, op->dev_master, op->rows, op->cols, op->rows, op->prep_g, op->JBT_g,
                                          op->MFT_g, op->a_exp_g, 0));
-  }
   HIPCHK(ctx, hipDeviceSynchronize());
   *out = op;
   return MM_OK;
