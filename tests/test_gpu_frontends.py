@@ -190,3 +190,31 @@ def test_vortex_background_steady_and_weights_reuploaded(ctx):
         assert err < 1e-12
         for o in ops:
             o.destroy()
+
+
+def test_vortex_step_checks(ctx):
+    # zero steps leave the state alone; a real state, a non-positive width,
+    # a wrong operator size or a missing weight array are refused before any
+    # launch
+    import paper_2103_01691_amd as mm
+    dims, tau = (24, 16, 8), 0.1
+    xs, Ml, Mo, ws, W = _vortex_problem(dims)
+    ops = [ctx.mm_op_prepare(mm.expm(m, 0.5j * tau), "fp64") for m in Ml]
+    v0 = np.sqrt(W).astype(np.complex128) * (1.0 + 0.1j)
+    v = to_gpu(v0, "fp64", True)
+    ctx.vortex_strang_step(v, ops, ws, tau, 0)
+    assert np.array_equal(from_gpu(v), v0)
+    with pytest.raises(mm.MumodeError) as e:
+        ctx.vortex_strang_step(to_gpu(np.abs(v0), "fp64", False), ops, ws, tau, 1)
+    assert e.value.status == 3       # MM_ERR_DTYPE
+    bad = [w.copy() for w in ws]
+    bad[1][3] = 0.0
+    with pytest.raises(mm.MumodeError) as e:
+        ctx.vortex_strang_step(v, ops, bad, tau, 1)
+    assert e.value.status == 1       # MM_ERR_ARG
+    with pytest.raises(mm.MumodeError) as e:
+        ctx.vortex_strang_step(v, [ops[1], ops[0], ops[2]], ws, tau, 1)
+    assert e.value.status == 2       # MM_ERR_SHAPE
+    assert np.array_equal(from_gpu(v), v0)
+    for o in ops:
+        o.destroy()
