@@ -174,8 +174,22 @@ __global__ __launch_bounds__(NORM_THREADS) void reduce_partial_kernel(const S* _
                                                                       double* __restrict__ partial) {
   __shared__ double red[NORM_THREADS];
   double acc = 0.0;
-  for (int64_t i = (int64_t)blockIdx.x * NORM_THREADS + threadIdx.x; i < count;
-       i += (int64_t)gridDim.x * NORM_THREADS) {
+  const int64_t stride = (int64_t)gridDim.x * NORM_THREADS;
+  int64_t start = (int64_t)blockIdx.x * NORM_THREADS + threadIdx.x;
+  if constexpr (KIND == RED_SQ) {
+    // 16-byte loads (the state is 16-byte aligned), then the scalar tail
+    constexpr int VN = 16 / sizeof(S);
+    typedef S vecS __attribute__((ext_vector_type(VN)));
+    const int64_t countv = count / VN;
+    const vecS* __restrict__ xv = (const vecS*)x;
+    for (int64_t i = start; i < countv; i += stride) {
+      const vecS v = xv[i];
+#pragma unroll
+      for (int e = 0; e < VN; ++e) acc += (double)v[e] * (double)v[e];
+    }
+    start += VN * countv;
+  }
+  for (int64_t i = start; i < count; i += stride) {
     if constexpr (KIND == RED_SQ) {
       const double v = (double)x[i];
       acc += v * v;
@@ -220,9 +234,28 @@ __global__ __launch_bounds__(NORM_THREADS) void maxabs_partial_kernel(const floa
                                                                       uint32_t* __restrict__ partial) {
   __shared__ uint32_t red[NORM_THREADS];
   uint32_t m = 0;
-  for (int64_t i = (int64_t)blockIdx.x * NORM_THREADS + threadIdx.x; i < count;
-       i += (int64_t)gridDim.x * NORM_THREADS)
-    m = max(m, __float_as_uint(fabsf(x[i])));
+  // 16-byte loads (the state is 16-byte aligned), four in flight per thread,
+  // then the scalar tail
+  const int64_t count4 = count / 4;
+  const f32x4* __restrict__ x4 = (const f32x4*)x;
+  const int64_t stride = (int64_t)gridDim.x * NORM_THREADS;
+  int64_t i = (int64_t)blockIdx.x * NORM_THREADS + threadIdx.x;
+  for (; i + 3 * stride < count4; i += 4 * stride) {
+    f32x4 v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) v[u] = x4[i + u * stride];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) m = max(m, __float_as_uint(fabsf(v[u][e])));
+  }
+  for (; i < count4; i += stride) {
+    const f32x4 v = x4[i];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) m = max(m, __float_as_uint(fabsf(v[e])));
+  }
+  for (int64_t t = 4 * count4 + (int64_t)blockIdx.x * NORM_THREADS + threadIdx.x; t < count; t += stride)
+    m = max(m, __float_as_uint(fabsf(x[t])));
   red[threadIdx.x] = m;
   __syncthreads();
   for (int w = NORM_THREADS / 2; w > 0; w >>= 1) {
