@@ -363,12 +363,15 @@ def _vortex_workload(ctx, mm, torch):
             npdt = np.complex128 if prec == "fp64" else np.complex64
             v = torch.from_numpy(synth.to_device_layout(v0.astype(npdt))).cuda()
             Eop = ctx.mm_op_prepare(E, prec)
+            ctx.mm_tune_clear()
+            ctx.mm_autotune(v, [Eop] * 3, 300)
             ctx.vortex_strang_step(v, [Eop] * 3, [w] * 3, tau, 2)
             t = timed(torch, lambda k: ctx.vortex_strang_step(v, [Eop] * 3, [w] * 3, tau, k), steps)
             out[f"vortex{n}_{prec}"] = {"ms_per_step": 1e3 * t / steps, "s_to_T25": t,
                                         "tflops_effective": 3 * 8.0 * n * n ** 3 / (t / steps) / 1e12}
             Eop.destroy()
             del v
+    ctx.mm_tune_clear()
     out["vortex_paper_cpu_s_to_T25"] = {"n81": 14.94, "n101": 29.51, "n121": 58.74, "n141": 102.40,
                                         "source": "the paper's figure for the mu-mode integrator (MATLAB, CPU), "
                                                   "context only"}
