@@ -51,6 +51,26 @@ def test_noalloc_matches_allocating_step_twice(ctx, prec):
         assert err < nsteps * REL_TOL[prec]
 
 
+@pytest.mark.parametrize("prec", ["fp16x2", "bf16x3"])
+def test_noalloc_on_three_product_kernels(ctx, tmp_path, prec):
+    # a tune table naming the three-product class for every product of the
+    # step (plain and prologue-phase keys): its operator form is prepared
+    # with the operator, so the allocation-free step runs it too, in place
+    code = {"bf16x3": 2, "fp16x2": 3}[prec]
+    for n, nsteps in ((96, 3), (40, 2)):
+        lines = [f"{code} 1 {ld} {2 * n} {2 * n} {n * n} 8 0.0\n" for ld in (0, 1, 8, 9)]
+        f = tmp_path / f"t{n}.txt"
+        f.write_text("mumode-tune 1\n" + "".join(lines))
+        ctx.mm_tune_clear()
+        ctx.mm_tune_load(f)
+        ga, gb, ref = _run(ctx, n, prec, nsteps)
+        ctx.mm_tune_clear()
+        assert np.array_equal(ga, gb), f"n={n}: differs from gpe_strang_step"
+        err = rel(ga, ref)
+        note(f"noalloc three-product n={n} {prec}: rel err vs oracle {err:.3e}")
+        assert err < nsteps * REL_TOL[prec]
+
+
 def test_noalloc_rejects_what_needs_memory(ctx):
     import torch
     import paper_2103_01691_amd as mm
