@@ -27,6 +27,17 @@ PRECISIONS = {"fp64": MM_PREC_FP64, "fp32": MM_PREC_FP32, "bf16x3": MM_PREC_SPLI
               "fp16x2": MM_PREC_SPLIT_FP16X2, "bf16": MM_PREC_BF16}
 
 
+def _mode_arrays(xs, t, name):
+    """Per-mode host arrays of the tensor's mode lengths (the library reads
+    n_k values of array k), as FP64 and as the pointer array the ABI takes."""
+    keep = [np.ascontiguousarray(np.asarray(x, dtype=np.float64)).reshape(-1) for x in xs]
+    if len(keep) < t.d or any(keep[k].size != t.dims[k] for k in range(t.d)):
+        raise ValueError(f"{name}: one array per mode with n_k entries each, "
+                         f"modes {[int(t.dims[k]) for k in range(t.d)]}")
+    arr = (C.POINTER(C.c_double) * len(keep))(*[k.ctypes.data_as(C.POINTER(C.c_double)) for k in keep])
+    return keep, arr
+
+
 class MumodeError(RuntimeError):
     def __init__(self, status: int, where: str, detail: str):
         self.status = status
@@ -302,8 +313,7 @@ class Context:
         """Phi_fwd / Psi_bwd: per-mode prepared real forward / backward Hermite
         transforms (Op); nodes: per-mode arrays of the quadrature nodes."""
         t = as_mm_tensor(psi)
-        keep = [np.ascontiguousarray(np.asarray(x, dtype=np.float64)) for x in nodes]
-        arr = (C.POINTER(C.c_double) * len(keep))(*[k.ctypes.data_as(C.POINTER(C.c_double)) for k in keep])
+        keep, arr = _mode_arrays(nodes, t, "nodes")
         self._chk(_lib.lib.ho_strang_step(self.handle, C.byref(t), _op_array(Phi_fwd), _op_array(Psi_bwd), arr,
                                           float(t0), float(tau), float(eps), nsteps, _stream(stream)),
                   "ho_strang_step")
@@ -312,8 +322,7 @@ class Context:
     def vortex_strang_step(self, v, E, w, tau: float, nsteps: int = 1, stream=None):
         """E: per-mode exp(i tau/2 M_k) operators; w: per-mode dual-cell widths."""
         t = as_mm_tensor(v)
-        keep = [np.ascontiguousarray(np.asarray(x, dtype=np.float64)) for x in w]
-        arr = (C.POINTER(C.c_double) * len(keep))(*[k.ctypes.data_as(C.POINTER(C.c_double)) for k in keep])
+        keep, arr = _mode_arrays(w, t, "w")
         self._chk(_lib.lib.vortex_strang_step(self.handle, C.byref(t), _op_array(E), arr, float(tau), nsteps,
                                               _stream(stream)), "vortex_strang_step")
         return v
